@@ -1,0 +1,151 @@
+/*
+ * gmps.h -- batched iterative Grover search on matrix product states (AMD gfx950).
+ *
+ * The library simulates the paper's "iterative method" (Section III-A, Fig. 1(C)):
+ * one Grover gate G = D O (Eq. (3)) is re-applied to a stored matrix product state
+ * (Section III-B) k times. Each reflection -- the oracle I - 2|x><x| for every marked x
+ * and the diffusion D = H^n (2|0><0| - I) H^n = 2|s><s| - I (Eq. (4)) -- is applied as a
+ * bond-2 matrix product operator and followed by recompression: a QR
+ * left-canonicalisation sweep and a truncated-SVD sweep (singular values below
+ * trunc_tol * sigma_0 are dropped, at most chi_cap kept). The state is renormalised
+ * after every iteration.
+ *
+ * Conventions shared by every call:
+ *  - Status: every int-returning call returns GMPS_OK (0) or a negative GMPS_E_* code.
+ *    Nothing throws across the ABI. gmps_strerror() names each code.
+ *  - Bits: site i of the chain carries bit (n-1-i) of a basis index (most significant
+ *    bit first). Marked indices, amplitude queries and sampled bitstrings all use it.
+ *  - Memory: pointers documented as "host" are caller-owned host memory, read or
+ *    written during the call only. The device workspace is caller-owned device memory
+ *    (for example a torch uint8 tensor) that must outlive the batch handle. The batch
+ *    handle itself is library-owned and freed by gmps_destroy().
+ *  - Streams: device work is enqueued on the HIP stream given to gmps_create() (a
+ *    hipStream_t passed as void*; NULL means the default stream). grover_iterate() and
+ *    mps_init_uniform() are asynchronous; calls that return host values synchronise
+ *    that stream first.
+ *  - Threads: a handle is not thread-safe; distinct handles are independent.
+ *  - Precision: GMPS_FP64 keeps site tensors and all arithmetic in complex128.
+ *    GMPS_MIXED stores site tensors in complex64 and runs the MPO application and the
+ *    site contractions in complex64, while QR, SVD, norms and renormalisation run in
+ *    FP64 on up-converted tiles.
+ */
+#ifndef GMPS_H
+#define GMPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmps_batch gmps_batch; /* opaque, library-owned */
+
+typedef enum { GMPS_FP64 = 0, GMPS_MIXED = 1 } gmps_prec;
+
+enum {
+  GMPS_OK = 0,
+  GMPS_E_ARG = -1,         /* invalid argument; nothing was enqueued               */
+  GMPS_E_WORKSPACE = -2,   /* workspace NULL, misaligned (<256 B) or too small      */
+  GMPS_E_HIP = -3,         /* a HIP runtime call failed                             */
+  GMPS_E_UNSUPPORTED = -4, /* bond cap beyond the compiled tile classes, no device  */
+  GMPS_E_NUMERIC = -5      /* some instance reports NaN/Inf or norm drift (see      *
+                            * gmps_diagnostics); results were still written         */
+};
+
+/* Per-instance status bits reported by gmps_diagnostics(). */
+enum {
+  GMPS_ST_NAN = 1,   /* a non-finite value appeared in the chain               */
+  GMPS_ST_DRIFT = 2, /* |norm - 1| before a renormalisation exceeded 1e-3     */
+  GMPS_ST_TRUNC = 4  /* a truncation dropped more than 1e-8 of the weight     */
+};
+
+/* One independent search: n qubits (1..63), M marked items (1 <= M < 2^n) whose
+ * indices are marked[marked_off .. marked_off+M-1] (distinct, < 2^n), and the bond cap
+ * chi_cap (>= 1; the exact Schmidt rank is at most M+1, so chi_cap >= M+1 is exact up
+ * to rounding). */
+typedef struct {
+  int32_t n;
+  int32_t M;
+  int32_t chi_cap;
+  int32_t reserved; /* must be 0 */
+  int64_t marked_off;
+} gmps_instance;
+
+/* Optional knobs; pass NULL for defaults. Zero-initialise unused fields. */
+typedef struct {
+  double trunc_tol;     /* relative SVD cut; <= 0: 1e-12 (FP64) or 5e-7 (mixed)       */
+  int32_t max_sweeps;   /* one-sided Jacobi sweep cap per SVD; <= 0: 16                */
+  int32_t waves_per_cu; /* persistent-grid occupancy; <= 0: library plan              */
+  int32_t use_graph;    /* 1 (default when 0): replay grover_iterate from a hipGraph;
+                           -1: plain launches                                         */
+  int32_t reserved[5];
+} gmps_options;
+
+/* Bytes of device workspace gmps_create() needs for this batch (0 on invalid input).
+ * inst: host [B]; marked offsets are not read. */
+size_t gmps_workspace_bytes(const gmps_instance* inst, int32_t B, gmps_prec prec);
+
+/* Creates a handle over B instances. inst: host [B]; marked: host, every instance's
+ * marked indices at its marked_off; both are copied. dev_workspace: device memory of at
+ * least gmps_workspace_bytes() bytes, 256-byte aligned. hip_stream: hipStream_t or NULL.
+ * The chain is left uninitialised: call mps_init_uniform() next.
+ * Errors: GMPS_E_ARG (bad instance, duplicate or out-of-range marked index),
+ * GMPS_E_WORKSPACE, GMPS_E_UNSUPPORTED (no tile class holds the bond cap), GMPS_E_HIP. */
+int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const uint64_t* marked,
+                gmps_prec prec, const gmps_options* opt, void* dev_workspace, size_t ws_bytes,
+                void* hip_stream);
+
+/* Section II, Eq. (2): every instance <- |s> = |+>^n (bond dimension 1), k_done = 0,
+ * diagnostics cleared. Asynchronous. */
+int mps_init_uniform(gmps_batch* b);
+
+/* Section III-A (Fig. 1(C)): applies G = D O (Eq. (3)) k times to every instance, in one
+ * persistent kernel launch. k: host, k_len == 1 (same k for all) or k_len == B
+ * (per-instance, each >= 0). Additive: k_done += k. Asynchronous. */
+int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len);
+
+/* Eq. (6): out_p[i] = sum_{x in W_i} |<x|psi_i>|^2 / <psi_i|psi_i>, accumulated in FP64.
+ * out_p: host [B]. Synchronises. Returns GMPS_E_NUMERIC if any status bit is set. */
+int marked_prob(gmps_batch* b, double* out_p);
+
+/* Section IV (shots): perfect sampling of each instance's final state, site by site on
+ * the right-canonical chain. shots: host, shots_len == 1 or B (each >= 0). The uniform for
+ * (instance i, shot j, site t) is word t%4 of Philox4x64-10(counter = (j, t/4, 0, 0),
+ * key = (seed, i)) as (word >> 11) * 2^-53; the site takes bit 0 iff u < p(0 | prefix).
+ * out_bits: host [sum shots], instance-major; out_hits: host [B], the number of shots
+ * that landed in W_i (either may be NULL). Synchronises. */
+int sample_shots(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_t seed,
+                 uint64_t* out_bits, int64_t* out_hits);
+
+/* <x|psi_inst> for cnt basis indices. xs: host [cnt]; out_reim: host [2*cnt] (re, im).
+ * Synchronises. */
+int gmps_amplitudes(gmps_batch* b, int32_t inst, const uint64_t* xs, int64_t cnt,
+                    double* out_reim);
+
+/* Per-instance diagnostics; any pointer may be NULL. Synchronises.
+ *  norm_drift:   host [B], largest |norm - 1| seen before a renormalisation
+ *  trunc_weight: host [B], largest fraction of weight dropped by one truncation
+ *  bond_dims:    host [B*64], bond_dims[i*64 + l] = bond l of instance i (l = 0..n)
+ *  status:       host [B], GMPS_ST_* bits
+ *  k_done:       host [B], iterations applied since mps_init_uniform
+ *  flops:        host [2*B], algorithmic FP64 and FP32 flops spent by grover_iterate
+ *                since mps_init_uniform (LAPACK-style counts at the actual tile sizes) */
+int gmps_diagnostics(gmps_batch* b, double* norm_drift, double* trunc_weight, int32_t* bond_dims,
+                     int32_t* status, int64_t* k_done, double* flops);
+
+/* Milliseconds taken by the last grover_iterate() launch on the batch's stream, measured
+ * with HIP events recorded around that launch. Synchronises. */
+int gmps_last_iterate_ms(gmps_batch* b, double* ms);
+
+/* Frees the handle and its library-owned staging memory (not the workspace). NULL is OK. */
+int gmps_destroy(gmps_batch* b);
+
+/* Static string for a GMPS_* status code. */
+const char* gmps_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMPS_H */

@@ -1,0 +1,517 @@
+// Host runtime of libgmps: argument checking, workspace carving, bundling of instances
+// into waves (longest first), hipGraph capture of the iterate launch, and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/gmps.h"
+#include "gmps_internal.h"
+
+namespace gmps {
+hipError_t launch_iterate(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st);
+hipError_t iterate_occupancy(bool mixed, size_t lds, int* blocks_per_cu);
+size_t group_lds_bytes(bool mixed, int cls);
+hipError_t launch_init(bool mixed, InstDev* inst, int B, const int64_t* site_start, int32_t* bonds, void* arena,
+                       int64_t total_sites, hipStream_t st);
+hipError_t launch_prob(bool mixed, InstDev* inst, const uint64_t* marked, const int32_t* bonds, const void* arena,
+                       int B, double* out, hipStream_t st);
+hipError_t launch_amplitudes(bool mixed, const InstDev* inst, int which, const int32_t* bonds, const void* arena,
+                             const uint64_t* xs, int64_t cnt, double* out, hipStream_t st);
+hipError_t launch_sample(bool mixed, const InstDev* inst, const uint64_t* marked, const int32_t* bonds,
+                         const void* arena, int B, const int64_t* shot_off, int64_t total, uint64_t seed,
+                         uint64_t* bits, unsigned long long* hits, hipStream_t st);
+}  // namespace gmps
+
+using namespace gmps;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Smallest tile class whose bond capacity holds min(cap, 2^floor(n/2)); -1 if none.
+int pick_class(int n, int cap) {
+  int need = cap;
+  if (n / 2 < 30) need = std::min<int64_t>(need, int64_t(1) << (n / 2));
+  for (int c = 0; c < kNumClasses; ++c)
+    if (kClasses[c].CM >= need) return c;
+  return -1;
+}
+
+bool valid_instance(const gmps_instance& in) {
+  return in.n >= 1 && in.n <= 63 && in.M >= 1 && (in.n >= 62 || in.M < (int64_t(1) << in.n)) && in.chi_cap >= 1 &&
+         in.reserved == 0 && in.marked_off >= 0;
+}
+
+struct Layout {
+  size_t inst, marked, bonds, bundles, queue, prob, hits, site_start, arena, total;
+  int64_t total_marked, total_sites;
+};
+
+bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, Layout* L, std::vector<int>* cls_out,
+                    std::vector<int64_t>* site_off_out) {
+  const size_t elem = prec == GMPS_MIXED ? 8 : 16;
+  int64_t tm = 0, ts = 0;
+  size_t arena_elems = 0;
+  if (cls_out) cls_out->resize(B);
+  if (site_off_out) site_off_out->resize(B);
+  for (int i = 0; i < B; ++i) {
+    if (!valid_instance(inst[i])) return false;
+    const int c = pick_class(inst[i].n, inst[i].chi_cap);
+    if (c < 0) return false;
+    if (cls_out) (*cls_out)[i] = c;
+    if (site_off_out) (*site_off_out)[i] = (int64_t)arena_elems;
+    arena_elems += (size_t)inst[i].n * slot_elems(kClasses[c].CM);
+    tm += inst[i].M;
+    ts += inst[i].n;
+  }
+  size_t off = 0;
+  L->inst = off;       off = align_up(off + sizeof(InstDev) * B);
+  L->marked = off;     off = align_up(off + sizeof(uint64_t) * std::max<int64_t>(tm, 1));
+  L->bonds = off;      off = align_up(off + sizeof(int32_t) * kBondStride * B);
+  L->bundles = off;    off = align_up(off + sizeof(Bundle) * B);
+  L->queue = off;      off = align_up(off + sizeof(QueueState));
+  L->prob = off;       off = align_up(off + sizeof(double) * B);
+  L->hits = off;       off = align_up(off + sizeof(uint64_t) * B);
+  L->site_start = off; off = align_up(off + sizeof(int64_t) * (B + 1));
+  L->arena = off;      off = align_up(off + elem * arena_elems);
+  L->total = off;
+  L->total_marked = tm;
+  L->total_sites = ts;
+  return true;
+}
+
+}  // namespace
+
+struct gmps_batch {
+  int B = 0;
+  bool mixed = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* ws = nullptr;
+  Layout lay{};
+  std::vector<InstDev> inst_h;
+  std::vector<int64_t> k_done_h;
+  IterParams params{};
+  double trunc_tol = 1e-12;
+  int max_sweeps = 16;
+  int waves_per_cu = 0;
+  bool use_graph = true;
+  int num_cus = 0;
+  // pinned staging for the per-call bundle table
+  Bundle* bundles_pin = nullptr;
+  QueueState* queue_pin = nullptr;
+  hipEvent_t staging_done = nullptr;
+  bool staging_pending = false;
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+  bool timed = false;
+  // graph cache keyed by (grid, lds)
+  hipGraphExec_t graph = nullptr;
+  int graph_grid = -1;
+  size_t graph_lds = 0;
+  // lazily grown device staging for read-out calls
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
+};
+
+namespace {
+
+int hip_fail(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    std::fprintf(stderr, "gmps: %s failed: %s\n", what, hipGetErrorString(e));
+    return GMPS_E_HIP;
+  }
+  return GMPS_OK;
+}
+
+#define GMPS_HIP(call)                                 \
+  do {                                                 \
+    int _rc = hip_fail((call), #call);                 \
+    if (_rc != GMPS_OK) return _rc;                    \
+  } while (0)
+
+int ensure_stage(gmps_batch* b, size_t bytes) {
+  if (bytes <= b->stage_bytes) return GMPS_OK;
+  if (b->stage) {
+    GMPS_HIP(hipStreamSynchronize(b->stream));
+    GMPS_HIP(hipFree(b->stage));
+    b->stage = nullptr;
+    b->stage_bytes = 0;
+  }
+  size_t sz = std::max<size_t>(bytes, 1 << 20);
+  GMPS_HIP(hipMalloc(&b->stage, sz));
+  b->stage_bytes = sz;
+  return GMPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gmps_strerror(int status) {
+  switch (status) {
+    case GMPS_OK: return "ok";
+    case GMPS_E_ARG: return "invalid argument";
+    case GMPS_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case GMPS_E_HIP: return "HIP runtime error";
+    case GMPS_E_UNSUPPORTED: return "unsupported configuration (bond cap beyond the compiled tile classes, or no GPU)";
+    case GMPS_E_NUMERIC: return "numerical failure in some instance (NaN/Inf or norm drift)";
+  }
+  return "unknown status";
+}
+
+size_t gmps_workspace_bytes(const gmps_instance* inst, int32_t B, gmps_prec prec) {
+  if (!inst || B <= 0 || (prec != GMPS_FP64 && prec != GMPS_MIXED)) return 0;
+  Layout L;
+  if (!compute_layout(inst, B, prec, &L, nullptr, nullptr)) return 0;
+  return L.total;
+}
+
+int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const uint64_t* marked, gmps_prec prec,
+                const gmps_options* opt, void* dev_workspace, size_t ws_bytes, void* hip_stream) {
+  if (!out) return GMPS_E_ARG;
+  *out = nullptr;
+  if (!inst || B <= 0 || !marked || (prec != GMPS_FP64 && prec != GMPS_MIXED)) return GMPS_E_ARG;
+  for (int i = 0; i < B; ++i)
+    if (!valid_instance(inst[i])) return GMPS_E_ARG;
+  Layout L;
+  std::vector<int> cls;
+  std::vector<int64_t> site_off;
+  for (int i = 0; i < B; ++i)
+    if (pick_class(inst[i].n, inst[i].chi_cap) < 0) return GMPS_E_UNSUPPORTED;
+  if (!compute_layout(inst, B, prec, &L, &cls, &site_off)) return GMPS_E_ARG;
+  // marked sets: in range and distinct within an instance
+  int64_t tm = 0;
+  for (int i = 0; i < B; ++i) tm = std::max<int64_t>(tm, inst[i].marked_off + inst[i].M);
+  std::vector<uint64_t> packed;
+  packed.reserve(L.total_marked);
+  for (int i = 0; i < B; ++i) {
+    std::unordered_set<uint64_t> seen;
+    for (int j = 0; j < inst[i].M; ++j) {
+      const uint64_t x = marked[inst[i].marked_off + j];
+      if (inst[i].n < 64 && (x >> inst[i].n) != 0) return GMPS_E_ARG;
+      if (!seen.insert(x).second) return GMPS_E_ARG;
+      packed.push_back(x);
+    }
+  }
+  if (!dev_workspace || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) != 0)
+    return GMPS_E_WORKSPACE;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return GMPS_E_UNSUPPORTED;
+
+  gmps_batch* b = new (std::nothrow) gmps_batch();
+  if (!b) return GMPS_E_ARG;
+  b->B = B;
+  b->mixed = prec == GMPS_MIXED;
+  b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  b->ws = reinterpret_cast<char*>(dev_workspace);
+  b->lay = L;
+  b->trunc_tol = b->mixed ? 5e-7 : 1e-12;
+  if (opt) {
+    if (opt->trunc_tol > 0) b->trunc_tol = opt->trunc_tol;
+    if (opt->max_sweeps > 0) b->max_sweeps = opt->max_sweeps;
+    if (opt->waves_per_cu > 0) b->waves_per_cu = opt->waves_per_cu;
+    if (opt->use_graph < 0) b->use_graph = false;
+  }
+  hipGetDevice(&b->device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
+    delete b;
+    return GMPS_E_HIP;
+  }
+  b->num_cus = prop.multiProcessorCount;
+
+  b->inst_h.resize(B);
+  int64_t moff = 0;
+  std::vector<int64_t> site_start(B + 1, 0);
+  for (int i = 0; i < B; ++i) {
+    InstDev& d = b->inst_h[i];
+    std::memset(&d, 0, sizeof(d));
+    d.n = inst[i].n;
+    d.M = inst[i].M;
+    d.cap = inst[i].chi_cap;
+    d.cls = cls[i];
+    d.marked_off = moff;
+    d.site_off = site_off[i];
+    moff += inst[i].M;
+    site_start[i + 1] = site_start[i] + inst[i].n;
+  }
+  b->k_done_h.assign(B, 0);
+  hipStream_t st = b->stream;
+  int rc = GMPS_OK;
+  auto fail = [&](int code) {
+    gmps_destroy(b);
+    return code;
+  };
+  if ((rc = hip_fail(hipMemcpyAsync(b->ws + L.inst, b->inst_h.data(), sizeof(InstDev) * B, hipMemcpyHostToDevice, st),
+                     "copy instances")) != GMPS_OK)
+    return fail(rc);
+  if ((rc = hip_fail(hipMemcpyAsync(b->ws + L.marked, packed.data(), sizeof(uint64_t) * packed.size(),
+                                    hipMemcpyHostToDevice, st),
+                     "copy marked")) != GMPS_OK)
+    return fail(rc);
+  if ((rc = hip_fail(hipMemcpyAsync(b->ws + L.site_start, site_start.data(), sizeof(int64_t) * (B + 1),
+                                    hipMemcpyHostToDevice, st),
+                     "copy site table")) != GMPS_OK)
+    return fail(rc);
+  if ((rc = hip_fail(hipStreamSynchronize(st), "sync")) != GMPS_OK) return fail(rc);
+  if ((rc = hip_fail(hipHostMalloc(reinterpret_cast<void**>(&b->bundles_pin), sizeof(Bundle) * B, hipHostMallocDefault),
+                     "pinned bundles")) != GMPS_OK)
+    return fail(rc);
+  if ((rc = hip_fail(hipHostMalloc(reinterpret_cast<void**>(&b->queue_pin), sizeof(QueueState), hipHostMallocDefault),
+                     "pinned queue")) != GMPS_OK)
+    return fail(rc);
+  if ((rc = hip_fail(hipEventCreateWithFlags(&b->staging_done, hipEventDisableTiming), "event")) != GMPS_OK)
+    return fail(rc);
+  if ((rc = hip_fail(hipEventCreate(&b->ev_start), "event")) != GMPS_OK) return fail(rc);
+  if ((rc = hip_fail(hipEventCreate(&b->ev_stop), "event")) != GMPS_OK) return fail(rc);
+
+  IterParams& P = b->params;
+  P.inst = reinterpret_cast<InstDev*>(b->ws + L.inst);
+  P.marked = reinterpret_cast<const uint64_t*>(b->ws + L.marked);
+  P.bonds = reinterpret_cast<int32_t*>(b->ws + L.bonds);
+  P.arena = b->ws + L.arena;
+  P.bundles = reinterpret_cast<const Bundle*>(b->ws + L.bundles);
+  P.queue = reinterpret_cast<QueueState*>(b->ws + L.queue);
+  P.trunc_tol = b->trunc_tol;
+  P.max_sweeps = b->max_sweeps;
+  *out = b;
+  return GMPS_OK;
+}
+
+int mps_init_uniform(gmps_batch* b) {
+  if (!b) return GMPS_E_ARG;
+  GMPS_HIP(launch_init(b->mixed, b->params.inst, b->B, reinterpret_cast<const int64_t*>(b->ws + b->lay.site_start),
+                       b->params.bonds, b->params.arena, b->lay.total_sites, b->stream));
+  std::fill(b->k_done_h.begin(), b->k_done_h.end(), 0);
+  return GMPS_OK;
+}
+
+int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
+  if (!b || !k || (k_len != 1 && k_len != b->B)) return GMPS_E_ARG;
+  for (int i = 0; i < k_len; ++i)
+    if (k[i] < 0) return GMPS_E_ARG;
+  // Bundle instances that share (class, n, M, k), then order bundles by estimated cost,
+  // longest first, so the persistent queue hands out the long serial chains early.
+  struct Key {
+    int cls, n, M;
+    int64_t k;
+    bool operator<(const Key& o) const {
+      if (cls != o.cls) return cls < o.cls;
+      if (n != o.n) return n < o.n;
+      if (M != o.M) return M < o.M;
+      return k < o.k;
+    }
+  };
+  std::map<Key, std::vector<int>> groups;
+  for (int i = 0; i < b->B; ++i) {
+    const int64_t ki = k[k_len == 1 ? 0 : i];
+    if (ki == 0) continue;
+    const InstDev& d = b->inst_h[i];
+    groups[{d.cls, d.n, d.M, ki}].push_back(i);
+  }
+  if (b->staging_pending) {
+    GMPS_HIP(hipEventSynchronize(b->staging_done));
+    b->staging_pending = false;
+  }
+  std::vector<std::pair<double, Bundle>> bundles;
+  int max_cls = 0;
+  for (auto& g : groups) {
+    const int per = 64 / kClasses[g.first.cls].G;
+    const double cm = kClasses[g.first.cls].CM;
+    const double cost = (double)g.first.k * (g.first.M + 1) * std::max(1, g.first.n - 1) * cm * cm * cm;
+    max_cls = std::max(max_cls, g.first.cls);
+    for (size_t s = 0; s < g.second.size(); s += per) {
+      Bundle bd;
+      std::memset(&bd, 0, sizeof(bd));
+      bd.cls = g.first.cls;
+      bd.k = g.first.k;
+      bd.count = (int)std::min<size_t>(per, g.second.size() - s);
+      for (int t = 0; t < bd.count; ++t) bd.inst[t] = g.second[s + t];
+      bundles.push_back({cost, bd});
+    }
+  }
+  std::stable_sort(bundles.begin(), bundles.end(),
+                   [](const std::pair<double, Bundle>& a, const std::pair<double, Bundle>& c) { return a.first > c.first; });
+  const int nb = (int)bundles.size();
+  for (int i = 0; i < b->B; ++i) b->k_done_h[i] += k[k_len == 1 ? 0 : i];
+  b->timed = false;
+  if (nb == 0) return GMPS_OK;
+  size_t lds = 0;
+  for (auto& bp : bundles) {
+    const int cls = bp.second.cls;
+    lds = std::max(lds, group_lds_bytes(b->mixed, cls) * (64 / kClasses[cls].G));
+  }
+  for (int i = 0; i < nb; ++i) b->bundles_pin[i] = bundles[i].second;
+  b->queue_pin->next = 0;
+  b->queue_pin->nbundles = nb;
+  GMPS_HIP(hipMemcpyAsync(b->ws + b->lay.bundles, b->bundles_pin, sizeof(Bundle) * nb, hipMemcpyHostToDevice,
+                          b->stream));
+  GMPS_HIP(hipMemcpyAsync(b->ws + b->lay.queue, b->queue_pin, sizeof(QueueState), hipMemcpyHostToDevice, b->stream));
+  GMPS_HIP(hipEventRecord(b->staging_done, b->stream));
+  b->staging_pending = true;
+
+  int per_cu = 0;
+  GMPS_HIP(iterate_occupancy(b->mixed, lds, &per_cu));
+  if (b->waves_per_cu > 0) per_cu = std::min(per_cu, b->waves_per_cu);
+  per_cu = std::max(per_cu, 1);
+  const int grid = std::min(nb, per_cu * b->num_cus);
+
+  GMPS_HIP(hipEventRecord(b->ev_start, b->stream));
+  if (b->use_graph) {
+    if (!b->graph || b->graph_grid != grid || b->graph_lds != lds) {
+      if (b->graph) {
+        hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+      }
+      hipStream_t cap;
+      GMPS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipGraph_t g;
+      GMPS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      hipError_t le = launch_iterate(b->mixed, b->params, grid, lds, cap);
+      hipError_t ce = hipStreamEndCapture(cap, &g);
+      hipStreamDestroy(cap);
+      GMPS_HIP(le);
+      GMPS_HIP(ce);
+      hipError_t ie = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      GMPS_HIP(ie);
+      b->graph_grid = grid;
+      b->graph_lds = lds;
+    }
+    GMPS_HIP(hipGraphLaunch(b->graph, b->stream));
+  } else {
+    GMPS_HIP(launch_iterate(b->mixed, b->params, grid, lds, b->stream));
+  }
+  GMPS_HIP(hipEventRecord(b->ev_stop, b->stream));
+  b->timed = true;
+  return GMPS_OK;
+}
+
+int gmps_last_iterate_ms(gmps_batch* b, double* ms) {
+  if (!b || !ms) return GMPS_E_ARG;
+  if (!b->timed) {
+    *ms = 0.0;
+    return GMPS_OK;
+  }
+  GMPS_HIP(hipEventSynchronize(b->ev_stop));
+  float f = 0.f;
+  GMPS_HIP(hipEventElapsedTime(&f, b->ev_start, b->ev_stop));
+  *ms = f;
+  return GMPS_OK;
+}
+
+static int any_bad_status(gmps_batch* b, bool* bad) {
+  std::vector<InstDev> h(b->B);
+  GMPS_HIP(hipMemcpyAsync(h.data(), b->params.inst, sizeof(InstDev) * b->B, hipMemcpyDeviceToHost, b->stream));
+  GMPS_HIP(hipStreamSynchronize(b->stream));
+  *bad = false;
+  for (auto& d : h)
+    if (d.status & (GMPS_ST_NAN | GMPS_ST_DRIFT)) *bad = true;
+  return GMPS_OK;
+}
+
+int marked_prob(gmps_batch* b, double* out_p) {
+  if (!b || !out_p) return GMPS_E_ARG;
+  double* dprob = reinterpret_cast<double*>(b->ws + b->lay.prob);
+  GMPS_HIP(launch_prob(b->mixed, b->params.inst, b->params.marked, b->params.bonds, b->params.arena, b->B, dprob,
+                       b->stream));
+  GMPS_HIP(hipMemcpyAsync(out_p, dprob, sizeof(double) * b->B, hipMemcpyDeviceToHost, b->stream));
+  bool bad = false;
+  int rc = any_bad_status(b, &bad);
+  if (rc != GMPS_OK) return rc;
+  return bad ? GMPS_E_NUMERIC : GMPS_OK;
+}
+
+int sample_shots(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_t seed, uint64_t* out_bits,
+                 int64_t* out_hits) {
+  if (!b || !shots || (shots_len != 1 && shots_len != b->B)) return GMPS_E_ARG;
+  std::vector<int64_t> off(b->B + 1, 0);
+  for (int i = 0; i < b->B; ++i) {
+    const int64_t s = shots[shots_len == 1 ? 0 : i];
+    if (s < 0) return GMPS_E_ARG;
+    off[i + 1] = off[i] + s;
+  }
+  const int64_t total = off[b->B];
+  const size_t need = align_up(sizeof(int64_t) * (b->B + 1)) + align_up(sizeof(uint64_t) * std::max<int64_t>(total, 1));
+  int rc = ensure_stage(b, need);
+  if (rc != GMPS_OK) return rc;
+  char* st = reinterpret_cast<char*>(b->stage);
+  int64_t* doff = reinterpret_cast<int64_t*>(st);
+  uint64_t* dbits = reinterpret_cast<uint64_t*>(st + align_up(sizeof(int64_t) * (b->B + 1)));
+  unsigned long long* dhits = reinterpret_cast<unsigned long long*>(b->ws + b->lay.hits);
+  GMPS_HIP(hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (b->B + 1), hipMemcpyHostToDevice, b->stream));
+  GMPS_HIP(hipMemsetAsync(dhits, 0, sizeof(uint64_t) * b->B, b->stream));
+  GMPS_HIP(launch_sample(b->mixed, b->params.inst, b->params.marked, b->params.bonds, b->params.arena, b->B, doff,
+                         total, seed, dbits, dhits, b->stream));
+  if (out_bits && total > 0)
+    GMPS_HIP(hipMemcpyAsync(out_bits, dbits, sizeof(uint64_t) * total, hipMemcpyDeviceToHost, b->stream));
+  if (out_hits) GMPS_HIP(hipMemcpyAsync(out_hits, dhits, sizeof(int64_t) * b->B, hipMemcpyDeviceToHost, b->stream));
+  GMPS_HIP(hipStreamSynchronize(b->stream));
+  return GMPS_OK;
+}
+
+int gmps_amplitudes(gmps_batch* b, int32_t inst, const uint64_t* xs, int64_t cnt, double* out_reim) {
+  if (!b || inst < 0 || inst >= b->B || cnt < 0 || (cnt > 0 && (!xs || !out_reim))) return GMPS_E_ARG;
+  if (cnt == 0) return GMPS_OK;
+  const int n = b->inst_h[inst].n;
+  for (int64_t t = 0; t < cnt; ++t)
+    if (n < 64 && (xs[t] >> n) != 0) return GMPS_E_ARG;
+  const size_t need = align_up(sizeof(uint64_t) * cnt) + align_up(sizeof(double) * 2 * cnt);
+  int rc = ensure_stage(b, need);
+  if (rc != GMPS_OK) return rc;
+  char* st = reinterpret_cast<char*>(b->stage);
+  uint64_t* dxs = reinterpret_cast<uint64_t*>(st);
+  double* dout = reinterpret_cast<double*>(st + align_up(sizeof(uint64_t) * cnt));
+  GMPS_HIP(hipMemcpyAsync(dxs, xs, sizeof(uint64_t) * cnt, hipMemcpyHostToDevice, b->stream));
+  GMPS_HIP(launch_amplitudes(b->mixed, b->params.inst, inst, b->params.bonds, b->params.arena, dxs, cnt, dout,
+                             b->stream));
+  GMPS_HIP(hipMemcpyAsync(out_reim, dout, sizeof(double) * 2 * cnt, hipMemcpyDeviceToHost, b->stream));
+  GMPS_HIP(hipStreamSynchronize(b->stream));
+  return GMPS_OK;
+}
+
+int gmps_diagnostics(gmps_batch* b, double* norm_drift, double* trunc_weight, int32_t* bond_dims, int32_t* status,
+                     int64_t* k_done, double* flops) {
+  if (!b) return GMPS_E_ARG;
+  std::vector<InstDev> h(b->B);
+  GMPS_HIP(hipMemcpyAsync(h.data(), b->params.inst, sizeof(InstDev) * b->B, hipMemcpyDeviceToHost, b->stream));
+  if (bond_dims)
+    GMPS_HIP(hipMemcpyAsync(bond_dims, b->params.bonds, sizeof(int32_t) * kBondStride * b->B, hipMemcpyDeviceToHost,
+                            b->stream));
+  GMPS_HIP(hipStreamSynchronize(b->stream));
+  for (int i = 0; i < b->B; ++i) {
+    if (norm_drift) norm_drift[i] = h[i].drift;
+    if (trunc_weight) trunc_weight[i] = h[i].trunc_w;
+    if (status) status[i] = h[i].status;
+    if (k_done) k_done[i] = h[i].k_done;
+    if (flops) {
+      flops[2 * i] = h[i].flops64;
+      flops[2 * i + 1] = h[i].flops32;
+    }
+  }
+  return GMPS_OK;
+}
+
+int gmps_destroy(gmps_batch* b) {
+  if (!b) return GMPS_OK;
+  if (b->stream || true) hipStreamSynchronize(b->stream);
+  if (b->graph) hipGraphExecDestroy(b->graph);
+  if (b->bundles_pin) hipHostFree(b->bundles_pin);
+  if (b->queue_pin) hipHostFree(b->queue_pin);
+  if (b->staging_done) hipEventDestroy(b->staging_done);
+  if (b->ev_start) hipEventDestroy(b->ev_start);
+  if (b->ev_stop) hipEventDestroy(b->ev_stop);
+  if (b->stage) hipFree(b->stage);
+  delete b;
+  return GMPS_OK;
+}
+
+}  // extern "C"

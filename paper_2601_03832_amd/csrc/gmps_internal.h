@@ -1,0 +1,57 @@
+// Internal structures shared by the HIP kernels and the host runtime of libgmps.
+#pragma once
+#include <stdint.h>
+
+namespace gmps {
+
+// Device-side record of one Grover instance.
+struct InstDev {
+  int32_t n, M, cap, cls;  // qubits, marked count, bond cap, tile class
+  int64_t marked_off;      // first marked index in the marked[] array
+  int64_t site_off;        // complex-element offset of site 0's slot in the arena
+  int64_t k_done;          // iterations applied since init
+  int32_t status, pad;     // GMPS_ST_* bits
+  double drift;            // largest |norm - 1| before a renormalisation
+  double trunc_w;          // largest dropped-weight fraction of one truncation
+  double flops64, flops32; // algorithmic flops spent so far
+};
+
+// A wave processes one bundle: up to kMaxBundle instances that share (class, n, M, k),
+// one per lane group of G lanes.
+constexpr int kMaxBundle = 8;
+struct Bundle {
+  int32_t inst[kMaxBundle];
+  int32_t count;
+  int32_t cls;
+  int64_t k;
+};
+
+// Tile classes: CM is the largest bond after truncation; D = 2*CM is the largest bond
+// after a bond-2 MPO; a QR tile has up to 2*D rows, so a lane group has G >= 4*CM lanes.
+struct ClassCfg {
+  int CM, G;
+};
+constexpr int kNumClasses = 4;
+constexpr ClassCfg kClasses[kNumClasses] = {{2, 8}, {3, 16}, {4, 16}, {6, 32}};
+constexpr int kBondStride = 64;  // bonds[i * 64 + l], l = 0..n
+
+// Elements of one site slot: (D, 2, D) with row stride 2*D and physical stride D.
+__host__ __device__ constexpr int slot_elems(int CM) { return (2 * CM) * 2 * (2 * CM); }
+
+struct QueueState {
+  uint32_t next;      // next bundle to hand out
+  int32_t nbundles;   // bundles in this launch
+};
+
+struct IterParams {
+  InstDev* inst;
+  const uint64_t* marked;
+  int32_t* bonds;
+  void* arena;
+  const Bundle* bundles;
+  QueueState* queue;
+  double trunc_tol;
+  int32_t max_sweeps;
+};
+
+}  // namespace gmps

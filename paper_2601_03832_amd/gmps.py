@@ -1,0 +1,239 @@
+"""ctypes binding of libgmps (include/gmps.h): argument marshalling only.
+
+Every step of the simulation runs in the HIP kernels of ``csrc/``. PyTorch supplies the
+device workspace (a uint8 tensor) and the stream. If the shared library is missing, or no
+GPU is visible, constructing a :class:`Batch` raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmps.so")
+
+GMPS_FP64 = 0
+GMPS_MIXED = 1
+GMPS_OK = 0
+GMPS_E_ARG = -1
+GMPS_E_WORKSPACE = -2
+GMPS_E_HIP = -3
+GMPS_E_UNSUPPORTED = -4
+GMPS_E_NUMERIC = -5
+ST_NAN, ST_DRIFT, ST_TRUNC = 1, 2, 4
+BOND_STRIDE = 64
+
+EXPORTED = ("gmps_workspace_bytes", "gmps_create", "mps_init_uniform", "grover_iterate", "marked_prob",
+            "sample_shots", "gmps_amplitudes", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
+            "gmps_strerror")
+
+
+class GmpsInstance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("M", ctypes.c_int32), ("chi_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("marked_off", ctypes.c_int64)]
+
+
+class GmpsOptions(ctypes.Structure):
+    _fields_ = [("trunc_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class GmpsError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__("%s failed: %s (%d)" % (what, strerror(code), code))
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Loads libgmps.so (built in-tree by ``paper_2601_03832_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError("libgmps.so not built (%s); run python -m paper_2601_03832_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, u64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    lib.gmps_workspace_bytes.restype = ctypes.c_size_t
+    lib.gmps_workspace_bytes.argtypes = [ctypes.POINTER(GmpsInstance), i32, ctypes.c_int]
+    lib.gmps_create.restype = ctypes.c_int
+    lib.gmps_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(GmpsInstance), i32, ctypes.POINTER(u64),
+                                ctypes.c_int, ctypes.POINTER(GmpsOptions), P, ctypes.c_size_t, P]
+    lib.mps_init_uniform.restype = ctypes.c_int
+    lib.mps_init_uniform.argtypes = [P]
+    lib.grover_iterate.restype = ctypes.c_int
+    lib.grover_iterate.argtypes = [P, ctypes.POINTER(i64), i32]
+    lib.marked_prob.restype = ctypes.c_int
+    lib.marked_prob.argtypes = [P, ctypes.POINTER(dbl)]
+    lib.sample_shots.restype = ctypes.c_int
+    lib.sample_shots.argtypes = [P, ctypes.POINTER(i64), i32, u64, ctypes.POINTER(u64), ctypes.POINTER(i64)]
+    lib.gmps_amplitudes.restype = ctypes.c_int
+    lib.gmps_amplitudes.argtypes = [P, i32, ctypes.POINTER(u64), i64, ctypes.POINTER(dbl)]
+    lib.gmps_diagnostics.restype = ctypes.c_int
+    lib.gmps_diagnostics.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(i32),
+                                     ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl)]
+    lib.gmps_last_iterate_ms.restype = ctypes.c_int
+    lib.gmps_last_iterate_ms.argtypes = [P, ctypes.POINTER(dbl)]
+    lib.gmps_destroy.restype = ctypes.c_int
+    lib.gmps_destroy.argtypes = [P]
+    lib.gmps_strerror.restype = ctypes.c_char_p
+    lib.gmps_strerror.argtypes = [ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().gmps_strerror(int(code)).decode()
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def pack_instances(instances):
+    """(ctypes array of GmpsInstance, packed uint64 marked array) from inputs.Instance objects."""
+    arr = (GmpsInstance * len(instances))()
+    marked = []
+    off = 0
+    for i, inst in enumerate(instances):
+        W = np.asarray(inst.marked, dtype=np.uint64)
+        arr[i].n = int(inst.n)
+        arr[i].M = int(len(W))
+        arr[i].chi_cap = int(inst.chi_cap)
+        arr[i].reserved = 0
+        arr[i].marked_off = off
+        marked.append(W)
+        off += len(W)
+    return arr, np.ascontiguousarray(np.concatenate(marked) if marked else np.zeros(1, np.uint64))
+
+
+def workspace_bytes(instances, precision: str) -> int:
+    arr, _ = pack_instances(instances)
+    return int(load().gmps_workspace_bytes(arr, len(instances), _prec(precision)))
+
+
+def _prec(precision: str) -> int:
+    if precision in ("fp64", GMPS_FP64):
+        return GMPS_FP64
+    if precision in ("mixed", GMPS_MIXED):
+        return GMPS_MIXED
+    raise ValueError("precision must be 'fp64' or 'mixed'")
+
+
+class Batch:
+    """A batch of independent Grover instances resident on the current GPU.
+
+    The device workspace is a torch uint8 tensor owned by this object; all work is
+    enqueued on ``stream`` (default: torch's current stream)."""
+
+    def __init__(self, instances: Sequence, precision: str = "fp64", trunc_tol: float = 0.0,
+                 max_sweeps: int = 0, waves_per_cu: int = 0, use_graph: bool = True, stream=None,
+                 device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libgmps needs a ROCm GPU; none is visible")
+        self.lib = load()
+        self.instances = list(instances)
+        self.B = len(self.instances)
+        self.precision = precision
+        self.n = np.array([i.n for i in self.instances], dtype=np.int64)
+        self._arr, self._marked = pack_instances(self.instances)
+        prec = _prec(precision)
+        nbytes = int(self.lib.gmps_workspace_bytes(self._arr, self.B, prec))
+        if nbytes == 0:
+            raise GmpsError(GMPS_E_ARG, "gmps_workspace_bytes")
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        opt = GmpsOptions()
+        opt.trunc_tol = float(trunc_tol)
+        opt.max_sweeps = int(max_sweeps)
+        opt.waves_per_cu = int(waves_per_cu)
+        opt.use_graph = 1 if use_graph else -1
+        self._opt = opt
+        h = ctypes.c_void_p()
+        rc = self.lib.gmps_create(ctypes.byref(h), self._arr, self.B, _ptr(self._marked, ctypes.c_uint64), prec,
+                                  ctypes.byref(opt), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                  ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != GMPS_OK:
+            raise GmpsError(rc, "gmps_create")
+        self.handle = h
+
+    # -- lifecycle ---------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gmps_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what, allow_numeric=False):
+        if rc == GMPS_OK or (allow_numeric and rc == GMPS_E_NUMERIC):
+            return rc
+        raise GmpsError(rc, what)
+
+    # -- the four hot-path calls ----------------------------------------------------------
+    def init_uniform(self):
+        self._check(self.lib.mps_init_uniform(self.handle), "mps_init_uniform")
+
+    def iterate(self, k):
+        ks = np.ascontiguousarray(np.atleast_1d(np.asarray(k, dtype=np.int64)))
+        self._check(self.lib.grover_iterate(self.handle, _ptr(ks, ctypes.c_int64), len(ks)), "grover_iterate")
+
+    def marked_prob(self, allow_numeric: bool = False) -> np.ndarray:
+        out = np.zeros(self.B, dtype=np.float64)
+        self.last_status = self._check(self.lib.marked_prob(self.handle, _ptr(out, ctypes.c_double)),
+                                       "marked_prob", allow_numeric)
+        return out
+
+    def sample(self, shots, seed: int):
+        sh = np.ascontiguousarray(np.atleast_1d(np.asarray(shots, dtype=np.int64)))
+        per = sh if len(sh) == self.B else np.full(self.B, sh[0], dtype=np.int64)
+        bits = np.zeros(max(int(per.sum()), 1), dtype=np.uint64)
+        hits = np.zeros(self.B, dtype=np.int64)
+        self._check(self.lib.sample_shots(self.handle, _ptr(sh, ctypes.c_int64), len(sh), ctypes.c_uint64(seed),
+                                          _ptr(bits, ctypes.c_uint64), _ptr(hits, ctypes.c_int64)), "sample_shots")
+        offs = np.concatenate([[0], np.cumsum(per)])
+        return [bits[offs[i]:offs[i + 1]] for i in range(self.B)], hits
+
+    # -- read-out -----------------------------------------------------------------------------
+    def amplitudes(self, inst: int, xs) -> np.ndarray:
+        xs = np.ascontiguousarray(np.asarray(xs, dtype=np.uint64))
+        out = np.zeros(2 * len(xs), dtype=np.float64)
+        self._check(self.lib.gmps_amplitudes(self.handle, int(inst), _ptr(xs, ctypes.c_uint64), len(xs),
+                                             _ptr(out, ctypes.c_double)), "gmps_amplitudes")
+        return out[0::2] + 1j * out[1::2]
+
+    def diagnostics(self) -> dict:
+        B = self.B
+        drift = np.zeros(B)
+        trunc = np.zeros(B)
+        bonds = np.zeros(B * BOND_STRIDE, dtype=np.int32)
+        status = np.zeros(B, dtype=np.int32)
+        kd = np.zeros(B, dtype=np.int64)
+        flops = np.zeros(2 * B)
+        self._check(self.lib.gmps_diagnostics(self.handle, _ptr(drift, ctypes.c_double), _ptr(trunc, ctypes.c_double),
+                                              _ptr(bonds, ctypes.c_int32), _ptr(status, ctypes.c_int32),
+                                              _ptr(kd, ctypes.c_int64), _ptr(flops, ctypes.c_double)),
+                    "gmps_diagnostics")
+        bonds = bonds.reshape(B, BOND_STRIDE)
+        return {"norm_drift": drift, "trunc_weight": trunc, "status": status, "k_done": kd,
+                "bond_dims": [bonds[i, :self.instances[i].n + 1].tolist() for i in range(B)],
+                "flops64": flops[0::2], "flops32": flops[1::2]}
+
+    def last_iterate_ms(self) -> float:
+        v = ctypes.c_double()
+        self._check(self.lib.gmps_last_iterate_ms(self.handle, ctypes.byref(v)), "gmps_last_iterate_ms")
+        return v.value

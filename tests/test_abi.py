@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every function
+include/gmps.h declares, sizes workspaces and rejects bad arguments before any device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2601_03832_amd import gmps, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gmps.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(gmps.LIB_PATH):
+        pytest.fail("libgmps.so is not built; run python -m paper_2601_03832_amd.build")
+    return gmps.load()
+
+
+def test_header_declares_the_hot_path_calls():
+    names = _declared()
+    for must in ("mps_init_uniform", "grover_iterate", "marked_prob", "sample_shots", "gmps_create",
+                 "gmps_destroy", "gmps_workspace_bytes", "gmps_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(gmps.EXPORTED) <= set(_declared())
+
+
+def test_strerror_names_every_code(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        s = gmps.strerror(code)
+        assert s and s != "unknown status"
+    assert gmps.strerror(-99) == "unknown status"
+
+
+def test_workspace_bytes(lib):
+    c1 = inputs.config_c1().instances
+    arr, _ = gmps.pack_instances(c1)
+    b64 = lib.gmps_workspace_bytes(arr, 1, gmps.GMPS_FP64)
+    b32 = lib.gmps_workspace_bytes(arr, 1, gmps.GMPS_MIXED)
+    assert b64 > b32 > 0 and b64 % 256 == 0
+    # invalid: n = 0, M >= 2^n, cap 0, B = 0, bad precision
+    for n, M, cap in ((0, 1, 2), (3, 8, 2), (5, 1, 0), (64, 1, 2)):
+        bad = (gmps.GmpsInstance * 1)()
+        bad[0].n, bad[0].M, bad[0].chi_cap = n, M, cap
+        assert lib.gmps_workspace_bytes(bad, 1, gmps.GMPS_FP64) == 0
+    assert lib.gmps_workspace_bytes(arr, 0, gmps.GMPS_FP64) == 0
+    assert lib.gmps_workspace_bytes(arr, 1, 7) == 0
+
+
+def test_bond_cap_beyond_tile_classes_is_unsupported(lib):
+    big = (gmps.GmpsInstance * 1)()
+    big[0].n, big[0].M, big[0].chi_cap = 30, 40, 41
+    assert lib.gmps_workspace_bytes(big, 1, gmps.GMPS_MIXED) == 0
+    h = ctypes.c_void_p()
+    marked = np.arange(40, dtype=np.uint64)
+    rc = lib.gmps_create(ctypes.byref(h), big, 1, marked.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                         gmps.GMPS_MIXED, None, ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == gmps.GMPS_E_UNSUPPORTED
+
+
+def _create(lib, insts, marked, ws_ptr=256, ws_bytes=1 << 30, prec=gmps.GMPS_FP64):
+    h = ctypes.c_void_p()
+    return lib.gmps_create(ctypes.byref(h), insts, len(insts),
+                           marked.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), prec, None,
+                           ctypes.c_void_p(ws_ptr), ws_bytes, None)
+
+
+def test_create_rejects_bad_marked_sets_before_touching_a_device(lib):
+    inst = (gmps.GmpsInstance * 1)()
+    inst[0].n, inst[0].M, inst[0].chi_cap, inst[0].marked_off = 4, 2, 3, 0
+    assert _create(lib, inst, np.array([3, 3], dtype=np.uint64)) == gmps.GMPS_E_ARG      # duplicate
+    assert _create(lib, inst, np.array([3, 16], dtype=np.uint64)) == gmps.GMPS_E_ARG     # out of range
+    inst[0].reserved = 1
+    assert _create(lib, inst, np.array([3, 4], dtype=np.uint64)) == gmps.GMPS_E_ARG      # reserved != 0
+
+
+def test_create_checks_the_workspace(lib):
+    inst = (gmps.GmpsInstance * 1)()
+    inst[0].n, inst[0].M, inst[0].chi_cap = 6, 1, 2
+    m = np.array([5], dtype=np.uint64)
+    need = lib.gmps_workspace_bytes(inst, 1, gmps.GMPS_FP64)
+    assert _create(lib, inst, m, ws_ptr=0) == gmps.GMPS_E_WORKSPACE
+    assert _create(lib, inst, m, ws_bytes=need - 1) == gmps.GMPS_E_WORKSPACE
+    assert _create(lib, inst, m, ws_ptr=256 + 8) == gmps.GMPS_E_WORKSPACE
+
+
+def test_calls_on_null_handle_fail_cleanly(lib):
+    assert lib.mps_init_uniform(None) == gmps.GMPS_E_ARG
+    k = np.array([1], dtype=np.int64)
+    assert lib.grover_iterate(None, k.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1) == gmps.GMPS_E_ARG
+    assert lib.marked_prob(None, None) == gmps.GMPS_E_ARG
+    assert lib.gmps_destroy(None) == gmps.GMPS_OK
+
+
+def test_binding_refuses_to_run_without_a_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(RuntimeError):
+        gmps.Batch(inputs.config_c1().instances)

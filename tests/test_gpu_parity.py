@@ -1,0 +1,171 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances: marked probability within 1e-10 of the oracle on the FP64 path and 1e-6 on the
+mixed path; amplitudes likewise. Sampled bitstrings must equal the oracle's exact
+site-by-site draw except where the uniform falls within 1e-9 (FP64) / 1e-5 (mixed) of the
+decision threshold, since there the two sides may round the marginal differently."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import closed_form as cf
+from oracle import mps as omps
+from oracle import sampling as osamp
+from oracle import statevector as sv
+from paper_2601_03832_amd import gmps, inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "mixed": 1e-6}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run(instances, precision, k=None, **kw):
+    b = gmps.Batch(instances, precision, **kw)
+    b.init_uniform()
+    b.iterate([i.k for i in instances] if k is None else k)
+    return b
+
+
+def check_sampling(bits, n, W, k, shots, seed, inst, tie_tol):
+    exp, p0s, us = osamp.sample(n, W, k, shots, seed, inst)
+    bad = np.nonzero(bits != exp)[0]
+    for sh in bad:
+        # the first differing site must be a near-tie
+        x, y = int(bits[sh]), int(exp[sh])
+        first = next(i for i in range(n) if ((x ^ y) >> (n - 1 - i)) & 1)
+        assert abs(us[sh, first] - p0s[sh, first]) < tie_tol, (sh, first, us[sh, first], p0s[sh, first])
+    return len(bad)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c1_full_statevector(gpu, precision):
+    say("case: C1 n=10 k=25 %s" % precision)
+    inst = inputs.config_c1().instances[0]
+    b = run([inst], precision)
+    p = b.marked_prob()[0]
+    assert abs(p - cf.p_marked(10, 1, 25)) < TOL[precision]
+    psi = sv.grover_sv(10, inst.marked, 25)
+    amps = b.amplitudes(0, np.arange(1024, dtype=np.uint64))
+    assert np.max(np.abs(amps - psi)) < (1e-12 if precision == "fp64" else 1e-6)
+    d = b.diagnostics()
+    ref = omps.run(10, inst.marked, 25, inst.chi_cap)
+    assert d["bond_dims"][0] == ref.bond_dims()
+    assert d["k_done"][0] == 25 and d["status"][0] == 0
+    assert d["norm_drift"][0] < (1e-12 if precision == "fp64" else 1e-5)
+    assert d["flops64"][0] > 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_ragged_batch_small_n(gpu, precision):
+    say("case: ragged batch n in [2,14], M in {1..4}, %s" % precision)
+    insts = inputs.random_batch(37, 2, 14, (1, 2, 3, 4), seed=31, cap_extra=1)
+    b = run(insts, precision)
+    p = b.marked_prob()
+    for i, inst in enumerate(insts):
+        assert abs(p[i] - cf.p_marked(inst.n, inst.M, inst.k)) < TOL[precision], (i, inst.n, inst.M, inst.k)
+    # full statevector of a few instances
+    for i in (0, 5, 17, 36):
+        inst = insts[i]
+        psi = sv.grover_sv(inst.n, inst.marked, inst.k)
+        amps = b.amplitudes(i, np.arange(1 << inst.n, dtype=np.uint64))
+        assert np.max(np.abs(amps - psi)) < TOL[precision] * 10
+    d = b.diagnostics()
+    for i, inst in enumerate(insts):
+        prof = d["bond_dims"][i]
+        for l in range(1, inst.n):
+            assert prof[l] <= min(2 ** l, 2 ** (inst.n - l), inst.M + 1)
+
+
+def test_edge_cases(gpu):
+    say("case: edge cases n=1, n=2, M=N-1, k=0, extra cap")
+    insts = [inputs.Instance(1, np.array([1], np.uint64), 1, 2),
+             inputs.Instance(2, np.array([2], np.uint64), 1, 2),
+             inputs.Instance(3, np.arange(7, dtype=np.uint64), 3, 6),
+             inputs.Instance(6, np.array([0, 63], np.uint64), 0, 3),
+             inputs.Instance(7, np.array([5], np.uint64), 4, 6)]
+    b = run(insts, "fp64")
+    p = b.marked_prob()
+    for i, inst in enumerate(insts):
+        assert abs(p[i] - cf.p_marked(inst.n, inst.M, inst.k)) < 1e-12, i
+        psi = sv.grover_sv(inst.n, inst.marked, inst.k)
+        amps = b.amplitudes(i, np.arange(1 << inst.n, dtype=np.uint64))
+        assert np.max(np.abs(amps - psi)) < 1e-12, i
+    assert p[1] == pytest.approx(1.0, abs=1e-14)  # N=4 textbook case
+
+
+def test_iterate_is_additive(gpu):
+    say("case: additivity 5+7 == 12")
+    insts = inputs.random_batch(9, 8, 13, (1, 2), seed=8)
+    a = gmps.Batch(insts, "fp64")
+    a.init_uniform()
+    a.iterate(5)
+    a.iterate(7)
+    c = run(insts, "fp64", k=12)
+    assert np.max(np.abs(a.marked_prob() - c.marked_prob())) < 1e-13
+    assert list(a.diagnostics()["k_done"]) == [12] * 9
+    for i, inst in enumerate(insts):
+        assert abs(c.marked_prob()[i] - cf.p_marked(inst.n, inst.M, 12)) < 1e-10
+
+
+def test_cap_below_rank_is_flagged(gpu):
+    say("case: cap below exact rank")
+    n, M = 10, 3
+    W = inputs.draw_marked(n, M, inputs.SplitMix64(77))
+    b = run([inputs.Instance(n, W, 3, 2)], "fp64")
+    d = b.diagnostics()
+    assert d["status"][0] & gmps.ST_TRUNC
+    assert d["trunc_weight"][0] > 1e-8
+    ref = omps.run(n, W, 3, chi_cap=2)
+    # dropping physical weight also moves the norm before each renormalisation, which the
+    # library reports as GMPS_E_NUMERIC (results are still written)
+    p = b.marked_prob(allow_numeric=True)[0]
+    assert b.last_status in (gmps.GMPS_OK, gmps.GMPS_E_NUMERIC)
+    assert abs(p - ref.marked_prob()) < 1e-10
+
+
+def test_c2_with_sampling(gpu):
+    say("case: C2 n=20 k=804 fp64 + 4096 shots")
+    w = inputs.config_c2()
+    inst = w.instances[0]
+    b = run([inst], "fp64")
+    p = b.marked_prob()[0]
+    assert abs(p - cf.p_marked(20, 1, 804)) < 1e-10
+    xs = np.array([int(inst.marked[0]), 0, 12345, (1 << 20) - 1], dtype=np.uint64)
+    amps = b.amplitudes(0, xs)
+    am, au = cf.amplitudes_wr(20, 1, 804)
+    assert abs(amps[0] - am) < 1e-10 and np.max(np.abs(amps[1:] - au)) < 1e-12
+    bits, hits = b.sample(4096, w.shot_seed)
+    nbad = check_sampling(bits[0][:512], 20, inst.marked, 804, 512, w.shot_seed, 0, 1e-9)
+    assert nbad == 0
+    assert hits[0] == int(np.sum(bits[0] == inst.marked[0]))
+    assert hits[0] >= 4090
+
+
+def test_sampling_many_instances_matches_oracle(gpu):
+    say("case: sampling replay, 12 instances x 64 shots, fp64 and mixed")
+    insts = inputs.random_batch(12, 5, 12, (1, 2, 4), seed=99)
+    for precision, tie in (("fp64", 1e-9), ("mixed", 1e-5)):
+        b = run(insts, precision)
+        bits, hits = b.sample(64, 4242)
+        for i, inst in enumerate(insts):
+            check_sampling(bits[i], inst.n, inst.marked, inst.k, 64, 4242, i, tie)
+            assert hits[i] == sum(1 for x in bits[i] if int(x) in set(int(v) for v in inst.marked))
+
+
+def test_bad_arguments_through_binding(gpu):
+    say("case: argument errors")
+    insts = inputs.random_batch(2, 4, 6, (1,), seed=3)
+    b = gmps.Batch(insts, "fp64")
+    b.init_uniform()
+    with pytest.raises(gmps.GmpsError):
+        b.iterate([-1])
+    with pytest.raises(gmps.GmpsError):
+        b.iterate([1, 2, 3])
+    with pytest.raises(gmps.GmpsError):
+        b.amplitudes(0, [1 << 40])
