@@ -1,0 +1,235 @@
+"""Benchmark: Grover iterations/s on one MI355X, batched mixed precision vs plain FP64.
+
+One step is one pass of the whole hot path over the batched workload: every instance is
+reset to |s> (mps_init_uniform), iterated to its own k (grover_iterate, one persistent
+launch), read out (marked_prob) and sampled (sample_shots). value = sum_i k_i / step time.
+The accuracy gate requires |P_i - sin^2((2k_i+1) theta_i)| <= 1e-6 for every instance.
+
+    python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--workload c4|c2|c3]
+
+Prints one JSON line. See the design doc for the roofline and baseline definitions.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2601_03832_amd import inputs  # noqa: E402
+
+FP64_VECTOR_PEAK = 78.6e12    # MI355X published FP64 vector rate, FLOP/s
+FP32_VECTOR_PEAK = 157.3e12   # MI355X published FP32 vector rate, FLOP/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grover_kernel.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2601_03832_amd", "csrc", f)
+                  for f in ("gmps_kernels.hip", "gmps_internal.h")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def exact_p(n: int, M: int, k: int) -> float:
+    """Accuracy gate: sin^2((2k+1) asin(sqrt(M/2^n))), the success probability of Eq. (6)."""
+    return math.sin((2 * k + 1) * math.asin(math.sqrt(M / float(2 ** n)))) ** 2
+
+
+def workload(name: str) -> inputs.Workload:
+    if name == "c4":
+        return inputs.config_c4()
+    if name == "c2":
+        return inputs.config_c2()
+    if name == "c3":
+        return inputs.config_c3("mixed")
+    if name == "c3fp64":
+        return inputs.config_c3("fp64")
+    raise SystemExit("unknown workload " + name)
+
+
+def run_step(batch, ks, shots, seed):
+    batch.init_uniform()
+    batch.iterate(ks)
+    p = batch.marked_prob(allow_numeric=True)
+    _, hits = batch.sample(shots, seed) if shots else (None, None)
+    return p, hits
+
+
+def plain_fp64_rate(w, max_instances: int):
+    """The same instances through one B=1 FP64 handle each (one wave per launch), on a
+    stratified subset: one instance per (n, M) stratum, smallest k first, capped."""
+    import torch
+    from paper_2601_03832_amd import gmps
+    seen = {}
+    for inst in w.instances:
+        seen.setdefault((inst.n, inst.M), inst)
+    picks = sorted(seen.values(), key=lambda i: i.k)[:max_instances]
+    tot_k = 0
+    tot_s = 0.0
+    worst = 0.0
+    for inst in picks:
+        b = gmps.Batch([inst], "fp64")
+        b.init_uniform()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.iterate(inst.k)
+        p = b.marked_prob()[0]
+        t1 = time.perf_counter()
+        worst = max(worst, abs(p - exact_p(inst.n, inst.M, inst.k)))
+        tot_k += inst.k
+        tot_s += t1 - t0
+        b.close()
+    return {"value": tot_k / tot_s, "unit": "iterations/s", "instances": len(picks),
+            "sum_k": tot_k, "seconds": tot_s, "max_abs_err": worst,
+            "sample": "one instance per (n, M) stratum of the same workload, smallest k first, "
+                      "each through its own B=1 FP64 handle"}
+
+
+def cpu_baseline(w, iters_per_stratum: int = 3):
+    """The oracle (numpy FP64 MPS, one thread) on a bounded sample: a few iterations of one
+    instance per (n, M) stratum; the per-iteration time of each stratum is extrapolated to
+    every instance's own k."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import mps as omps
+    strata = {}
+    for inst in w.instances:
+        strata.setdefault((inst.n, inst.M), inst)
+    per_iter = {}
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    t_all = time.perf_counter()
+    try:
+        if ctx:
+            ctx.__enter__()
+        for key, inst in strata.items():
+            m = omps.GroverMPS(inst.n, inst.marked, inst.chi_cap)
+            m.iterate(1)  # warm
+            t0 = time.perf_counter()
+            m.iterate(iters_per_stratum)
+            per_iter[key] = (time.perf_counter() - t0) / iters_per_stratum
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    wall = time.perf_counter() - t_all
+    est = sum(inst.k * per_iter[(inst.n, inst.M)] for inst in w.instances)
+    tot_k = sum(inst.k for inst in w.instances)
+    return {"value": tot_k / est, "unit": "iterations/s", "cores": 1, "kind": "oracle",
+            "sample": "%d iterations of one instance per (n,M) stratum (%d strata, %.1f s of CPU), "
+                      "extrapolated to every instance's k (est. %.0f s for the whole workload)"
+                      % (iters_per_stratum, len(strata), wall, est)}
+
+
+def traffic_record():
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return rec if rec.get("kernel_hash") == kernel_hash() else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--plain-max", type=int, default=51)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--shots", type=int, default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: instances are independent, so a multi-GPU run "
+              "would shard the batch (see DESIGN.md); --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2601_03832_amd import gmps
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible: the benchmark needs the HIP library on an MI355X")
+    torch.cuda.set_device(0)
+    w = workload(args.workload)
+    shots = (w.shots[-1] if w.shots else 0) if args.shots is None else args.shots
+    ks = [i.k for i in w.instances]
+    sum_k = int(sum(ks))
+    print("bench: workload %s, %d instances, sum k = %d, precision %s, shots %d"
+          % (w.name, len(ks), sum_k, w.precision, shots), file=sys.stderr, flush=True)
+    batch = gmps.Batch(w.instances, w.precision)
+
+    for s in range(args.warmup):
+        run_step(batch, ks, shots, w.shot_seed)
+        print("bench: warmup step %d done" % s, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    p = None
+    for s in range(args.steps):
+        p, hits = run_step(batch, ks, shots, w.shot_seed)
+        kernel_ms.append(batch.last_iterate_ms())
+        print("bench: timed step %d done" % s, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+
+    errs = np.array([abs(p[i] - exact_p(inst.n, inst.M, inst.k)) for i, inst in enumerate(w.instances)])
+    tol = 1e-6 if w.precision == "mixed" else 1e-10
+    diag = batch.diagnostics()
+    # mps_init_uniform clears the counters, so they hold the last step's launch
+    f64 = float(np.sum(diag["flops64"]))
+    f32 = float(np.sum(diag["flops32"]))
+    kms = float(np.mean(kernel_ms))
+    # FP64-equivalent work: FP32 flops count at the FP64/FP32 peak ratio
+    achieved = (f64 + f32 * FP64_VECTOR_PEAK / FP32_VECTOR_PEAK) / (kms / 1000.0)
+    tr = traffic_record()
+    line = {
+        "metric": "Grover iterations/s on 1 GPU, batched mixed-prec vs plain FP64, err<=1e-6",
+        "value": sum_k / (ms_per_step / 1000.0),
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64/f64" if w.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "instances": len(ks), "sum_k": sum_k, "precision": w.precision,
+                   "shots_per_instance": shots, "description": w.description},
+        "accuracy": {"max_abs_err_p": float(errs.max()), "tolerance": tol, "pass": bool(errs.max() <= tol),
+                     "status_flags": int(np.bitwise_or.reduce(diag["status"]))},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK,
+                     "traffic": tr["bytes_per_launch"] if tr else None,
+                     "kernel": "grover_kernel", "kernel_ms": kms,
+                     "flops64_per_launch": f64, "flops32_per_launch": f32},
+    }
+    print("bench: main measurement done (%.1f ms/step)" % ms_per_step, file=sys.stderr, flush=True)
+    batch.close()
+    if not args.no_plain:
+        line["plain_fp64"] = plain_fp64_rate(w, args.plain_max)
+        line["plain_fp64"]["speedup_of_batched_mixed"] = line["value"] / line["plain_fp64"]["value"]
+        print("bench: plain fp64 leg done", file=sys.stderr, flush=True)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w)
+        print("bench: cpu baseline leg done", file=sys.stderr, flush=True)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,8 +62,10 @@ enum {
 
 /* One independent search: n qubits (1..63), M marked items (1 <= M < 2^n) whose
  * indices are marked[marked_off .. marked_off+M-1] (distinct, < 2^n), and the bond cap
- * chi_cap (>= 1; the exact Schmidt rank is at most M+1, so chi_cap >= M+1 is exact up
- * to rounding). */
+ * chi_cap >= 1. Every state the iteration passes through is a combination of |s> and the
+ * M marked basis states, so its Schmidt rank at any cut is at most M+1: the library caps
+ * each bond at min(chi_cap, M+1, 2^floor(n/2)), which drops only rounding noise when
+ * chi_cap >= M+1 and truncates physical weight (reported by gmps_diagnostics) otherwise. */
 typedef struct {
   int32_t n;
   int32_t M;

@@ -36,10 +36,18 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Smallest tile class whose bond capacity holds min(cap, 2^floor(n/2)); -1 if none.
-int pick_class(int n, int cap) {
-  int need = cap;
+// Effective bond cap: the exact Schmidt rank of every intermediate state is at most M+1
+// (the state stays a combination of the uniform superposition and M marked basis states),
+// and a bond of a chain of n sites never exceeds 2^floor(n/2).
+int effective_cap(int n, int M, int cap) {
+  int64_t need = std::min<int64_t>(cap, (int64_t)M + 1);
   if (n / 2 < 30) need = std::min<int64_t>(need, int64_t(1) << (n / 2));
+  return (int)need;
+}
+
+// Smallest tile class whose bond capacity holds the effective cap; -1 if none.
+int pick_class(int n, int M, int cap) {
+  const int need = effective_cap(n, M, cap);
   for (int c = 0; c < kNumClasses; ++c)
     if (kClasses[c].CM >= need) return c;
   return -1;
@@ -64,7 +72,7 @@ bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, Layout* L,
   if (site_off_out) site_off_out->resize(B);
   for (int i = 0; i < B; ++i) {
     if (!valid_instance(inst[i])) return false;
-    const int c = pick_class(inst[i].n, inst[i].chi_cap);
+    const int c = pick_class(inst[i].n, inst[i].M, inst[i].chi_cap);
     if (c < 0) return false;
     if (cls_out) (*cls_out)[i] = c;
     if (site_off_out) (*site_off_out)[i] = (int64_t)arena_elems;
@@ -185,7 +193,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   std::vector<int> cls;
   std::vector<int64_t> site_off;
   for (int i = 0; i < B; ++i)
-    if (pick_class(inst[i].n, inst[i].chi_cap) < 0) return GMPS_E_UNSUPPORTED;
+    if (pick_class(inst[i].n, inst[i].M, inst[i].chi_cap) < 0) return GMPS_E_UNSUPPORTED;
   if (!compute_layout(inst, B, prec, &L, &cls, &site_off)) return GMPS_E_ARG;
   // marked sets: in range and distinct within an instance
   int64_t tm = 0;
@@ -236,7 +244,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     std::memset(&d, 0, sizeof(d));
     d.n = inst[i].n;
     d.M = inst[i].M;
-    d.cap = inst[i].chi_cap;
+    d.cap = effective_cap(inst[i].n, inst[i].M, inst[i].chi_cap);
     d.cls = cls[i];
     d.marked_off = moff;
     d.site_off = site_off[i];
@@ -281,6 +289,9 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   P.bundles = reinterpret_cast<const Bundle*>(b->ws + L.bundles);
   P.queue = reinterpret_cast<QueueState*>(b->ws + L.queue);
   P.trunc_tol = b->trunc_tol;
+  // rounding-noise floor of an SVD tile: FP64 contractions, or complex64 ones
+  P.skip_tol = std::min(b->trunc_tol, b->mixed ? 1e-7 : 1e-15);
+  P.rank_tol = b->trunc_tol;
   P.max_sweeps = b->max_sweeps;
   *out = b;
   return GMPS_OK;

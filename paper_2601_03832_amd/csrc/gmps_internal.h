@@ -26,13 +26,15 @@ struct Bundle {
   int64_t k;
 };
 
-// Tile classes: CM is the largest bond after truncation; D = 2*CM is the largest bond
-// after a bond-2 MPO; a QR tile has up to 2*D rows, so a lane group has G >= 4*CM lanes.
+// Tile classes: CM is the largest bond after truncation and D = 2*CM the largest bond after
+// a bond-2 MPO. The QR sweep keeps at most CM+1 columns (the rank bound of a tile after
+// the MPO), so a QR tile has up to 2*(CM+1) rows: a lane group has G >= 2*CM+2 lanes. The
+// SVD runs on M^H (up to 2*CM rows) over its own WS <= G lanes.
 struct ClassCfg {
-  int CM, G;
+  int CM, G, WS;
 };
-constexpr int kNumClasses = 4;
-constexpr ClassCfg kClasses[kNumClasses] = {{2, 8}, {3, 16}, {4, 16}, {6, 32}};
+constexpr int kNumClasses = 5;
+constexpr ClassCfg kClasses[kNumClasses] = {{2, 8, 4}, {3, 8, 8}, {4, 16, 8}, {5, 16, 16}, {6, 16, 16}};
 constexpr int kBondStride = 64;  // bonds[i * 64 + l], l = 0..n
 
 // Elements of one site slot: (D, 2, D) with row stride 2*D and physical stride D.
@@ -50,7 +52,9 @@ struct IterParams {
   void* arena;
   const Bundle* bundles;
   QueueState* queue;
-  double trunc_tol;
+  double trunc_tol;  // relative singular-value cut of the truncation
+  double skip_tol;   // relative column norm below which Jacobi leaves a column unrotated
+  double rank_tol;   // relative trailing norm at which the QR sweep stops (numerical rank)
   int32_t max_sweeps;
 };
 

@@ -68,16 +68,67 @@ template <class S>
 __device__ __forceinline__ cx<S> czero() { return {(S)0, (S)0}; }
 
 // ------------------------------------------------------------------------ group collectives
+// Butterfly sums inside a lane group of G = 2, 4, 8, 16 or 32 lanes. Steps 1 and 2 swap
+// neighbours inside a quad (DPP quad_perm); once values are quad-uniform the half-row
+// mirror pairs the two quads of an 8-lane half, once they are half-row uniform the row
+// mirror pairs the two halves of a 16-lane row, and a swizzle swaps 16-lane halves of a
+// 32-lane group. Each step adds a value to its partner's, so every lane of the group ends
+// with the same bits (addition is commutative), and branches on the sums are uniform.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double swap16_f64(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_ds_swizzle(lo, 0x401F);  // bit-mask mode: xor lane id with 16
+  hi = __builtin_amdgcn_ds_swizzle(hi, 0x401F);
+  return __hiloint2double(hi, lo);
+}
 template <int G>
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m, G);
+  static_assert(G == 2 || G == 4 || G == 8 || G == 16 || G == 32, "group size");
+  v += dpp_f64<0xB1>(v);                   // quad_perm [1,0,3,2]
+  if (G > 2) v += dpp_f64<0x4E>(v);        // quad_perm [2,3,0,1]
+  if (G > 4) v += dpp_f64<0x141>(v);       // row_half_mirror
+  if (G > 8) v += dpp_f64<0x140>(v);       // row_mirror
+  if (G > 16) v += swap16_f64(v);
   return v;
 }
 template <int G>
 __device__ __forceinline__ cd gsum(cd v) { return {gsum<G>(v.re), gsum<G>(v.im)}; }
+// value held by group lane src, delivered to every lane of the group
 template <int G>
-__device__ __forceinline__ cd gbcast(cd v, int src) { return {__shfl(v.re, src, G), __shfl(v.im, src, G)}; }
+__device__ __forceinline__ cd gbcast(cd v, int gl, int src) {
+  return gsum<G>(gl == src ? v : cd{0.0, 0.0});
+}
+
+// Raw v_rsq_f64 / v_rcp_f64 are accurate to about 2^-23; two Newton steps bring them to
+// working precision, which keeps Householder reflectors and Jacobi rotations unitary.
+__device__ __forceinline__ double rsqrt_acc(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double r = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, r, y);
+  r = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, r, y);
+}
+__device__ __forceinline__ double rcp_acc(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double r = fma(-x, y, 1.0);
+  y = fma(y, r, y);
+  r = fma(-x, y, 1.0);
+  return fma(y, r, y);
+}
+
+// Orders LDS traffic between the lanes of the (single-wave) workgroup without waiting
+// for outstanding global memory operations.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // Round-robin (circle method) pairing of NC columns: round r pairs NC-1 with r and
 // (r+p) with (r-p) mod (NC-1); after NC-1 rounds every pair has met once.
@@ -89,28 +140,54 @@ __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a < b ? b : a; }
 
 // ------------------------------------------------------------------------------- QR
-// Householder QR of an m x c tile (row gl of the tile in x[], m <= G, c <= NC; rows >= m
-// and columns >= c are zero). On exit lanes gl < min(m, c) hold row gl of R in x[] and
-// q[] holds row gl of the thin Q (m x min(m, c)).
-template <int G, int NC>
-__device__ __forceinline__ void householder_qr(cd (&x)[NC], cd (&q)[NC], int gl, int m, int c) {
-  const int kr = m < c ? m : c;
-  cd hv[NC];
-  double tau[NC];
+// Householder QR of an m x c tile X held row per lane (row gl in x[], m <= G, c <= NC;
+// rows >= m and columns >= c are zero), stopped at the numerical rank: before step j > 0
+// the squared norm T_j of the trailing block X[j:, j:] is compared with rank2 * ||X||^2,
+// and the factorisation ends when it falls below, or after KMAX steps. Returns the rank k
+// kept; lanes gl < k then hold row gl of R (k x c, upper trapezoidal) in x[] and q[] holds
+// row gl of the thin Q (m x k), so X = Q R + E with ||E||^2 = T_k (*dropped = T_k/||X||^2).
+// A tile after a bond-2 MPO has its columns in the order [A block | P A block]; the first
+// block has full rank chi and the projector block adds one direction, so the rank is at
+// most chi + 1 and the trailing rows left after KMAX = chi_max + 1 steps are rounding noise.
+template <int G, int NC, int KMAX>
+__device__ __forceinline__ int householder_qr_rank(cd (&x)[NC], cd (&q)[KMAX], int gl, int m, int c,
+                                                   double rank2, double* dropped) {
+  const int kmax = min(min(m, c), KMAX);
+  cd hv[KMAX];
+  double tau[KMAX];
+  double t0 = 0.0;
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
+  for (int k = 0; k < NC; ++k) t0 += norm2(x[k]);
+  t0 = gsum<G>(gl < m ? t0 : 0.0);
+  int kr = kmax;
+  bool done = false;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
     hv[j] = {0.0, 0.0};
     tau[j] = 0.0;
-    if (j < kr) {
+    if (j > 0 && !done && j < kmax) {
+      double tj = 0.0;
+#pragma unroll
+      for (int k = j; k < NC; ++k) tj += norm2(x[k]);
+      tj = gsum<G>((gl >= j && gl < m) ? tj : 0.0);
+      if (tj <= rank2 * t0) {
+        done = true;
+        kr = j;
+      }
+    }
+    if (!done && j < kmax) {
       const cd xj = x[j];
       const double sub = gsum<G>((gl > j && gl < m) ? norm2(xj) : 0.0);
-      const cd alpha = gbcast<G>(xj, j);
-      const double aa = sqrt(norm2(alpha));
-      const double nrm = sqrt(aa * aa + sub);
+      const cd alpha = gbcast<G>(xj, gl, j);
+      const double a2 = norm2(alpha);
       const bool refl = sub > 0.0;
-      const cd ph = aa > 0.0 ? cd{alpha.re / aa, alpha.im / aa} : cd{1.0, 0.0};
+      const double ra = a2 > 0.0 ? rsqrt_acc(a2) : 0.0;
+      const double aa = a2 * ra;                          // |alpha|
+      const double n2 = a2 + sub;
+      const double nrm = refl ? n2 * rsqrt_acc(n2) : aa;  // norm of column j from the diagonal down
+      const cd ph = a2 > 0.0 ? cd{alpha.re * ra, alpha.im * ra} : cd{1.0, 0.0};
       const cd beta = {-ph.re * nrm, -ph.im * nrm};
-      const double t = refl ? 1.0 / (nrm * (nrm + aa)) : 0.0;
+      const double t = refl ? rcp_acc(nrm * (nrm + aa)) : 0.0;
       cd v = (gl == j) ? alpha - beta : ((gl > j && gl < m) ? xj : cd{0.0, 0.0});
       if (!refl) v = {0.0, 0.0};
       cd w[NC];
@@ -128,83 +205,127 @@ __device__ __forceinline__ void householder_qr(cd (&x)[NC], cd (&q)[NC], int gl,
       tau[j] = t;
     }
   }
-  // thin Q = H_0 H_1 ... H_{kr-1} [I; 0], applied right to left
+  double tk = 0.0;
 #pragma unroll
-  for (int k = 0; k < NC; ++k) q[k] = {(gl == k && k < kr) ? 1.0 : 0.0, 0.0};
+  for (int k = 0; k < NC; ++k) tk += (k >= kr) ? norm2(x[k]) : 0.0;
+  tk = gsum<G>((gl >= kr && gl < m) ? tk : 0.0);
+  *dropped = t0 > 0.0 ? tk / t0 : 0.0;
+  // thin Q = H_0 ... H_{kr-1} [I; 0], applied right to left
 #pragma unroll
-  for (int j = NC - 1; j >= 0; --j) {
+  for (int k = 0; k < KMAX; ++k) q[k] = {(gl == k && k < kr) ? 1.0 : 0.0, 0.0};
+#pragma unroll
+  for (int j = KMAX - 1; j >= 0; --j) {
     if (j < kr && tau[j] != 0.0) {
-      cd w[NC];
+      cd w[KMAX];
 #pragma unroll
-      for (int k = j; k < NC; ++k)
+      for (int k = j; k < KMAX; ++k)
         if (k < kr) w[k] = gsum<G>(cmulc(hv[j], q[k]));
 #pragma unroll
-      for (int k = j; k < NC; ++k)
+      for (int k = j; k < KMAX; ++k)
         if (k < kr) {
           const cd tw = tau[j] * w[k];
           q[k] = q[k] - hv[j] * tw;
         }
     }
   }
+  return kr;
+}
+
+// (x, y) <- (c x - conj(se) y, se x + c y) for real c and complex se = s e^{i phi}.
+__device__ __forceinline__ void rot2(cd& x, cd& y, double c, cd se) {
+  const cd x0 = x, y0 = y;
+  x.re = fma(c, x0.re, fma(-se.re, y0.re, -se.im * y0.im));
+  x.im = fma(c, x0.im, fma(-se.re, y0.im, se.im * y0.re));
+  y.re = fma(c, y0.re, fma(se.re, x0.re, -se.im * x0.im));
+  y.im = fma(c, y0.im, fma(se.re, x0.im, se.im * x0.re));
 }
 
 // ---------------------------------------------------------------------------- Jacobi SVD
-// One-sided (Hestenes) Jacobi on the columns of a rows x c tile held row per lane in a[]
-// (columns >= c are zero). Accumulates V (c x c, row gl in v[]). On exit the columns of
-// a[] are U*Sigma (mutually orthogonal) and tile = (U Sigma) V^dagger. Returns sweeps run.
-template <int G, int NC>
-__device__ __forceinline__ int jacobi_svd(cd (&a)[NC], cd (&v)[NC], int gl, int c, double tol,
-                                          int max_sweeps) {
-#pragma unroll
-  for (int k = 0; k < NC; ++k) v[k] = {(gl == k && k < c) ? 1.0 : 0.0, 0.0};
+// One-sided (Hestenes) Jacobi on the first NC columns of a tile held row per lane in a[]
+// over a lane group of W lanes (rows beyond the tile are zero), accumulating V (NC x NC,
+// row gl in v[]). For a pair (i, j) with gamma = a_i^H a_j and phi = arg(gamma), the rotation
+//   a_i' = c a_i - s e^{-i phi} a_j,   a_j' = s e^{i phi} a_i + c a_j,
+// with t = s/c the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (|a_j|^2 - |a_i|^2)/(2|gamma|),
+// makes the pair orthogonal and moves t|gamma| of squared norm from a_i to a_j; the norms are
+// tracked that way within a sweep and recomputed at the start of the next.
+// A pair is skipped when it is already orthogonal to tol2 (relative, squared) or when one
+// of its columns lies at the rounding-noise floor of the tile (skip2 * largest squared
+// norm): such a column is dropped by the truncation, and leaving it unrotated changes the
+// kept part by no more than its own norm. Convergence is quadratic, so a sweep whose
+// largest relative off-diagonal was below 1e-10 leaves ~1e-20 behind and ends the iteration.
+template <int W, int NC, int NCM>
+__device__ __forceinline__ int jacobi_fixed(cd (&a)[NCM], cd (&v)[NCM], double tol2, double skip2,
+                                            int max_sweeps) {
   int sweeps = 0;
-  while (sweeps < max_sweeps) {
+  bool more = true;
+  while (more && sweeps < max_sweeps) {
     ++sweeps;
-    double off = 0.0;
+    double nrm[NC];
+    double amax = 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      nrm[k] = gsum<W>(norm2(a[k]));
+      amax = fmax(amax, nrm[k]);
+    }
+    const double floor2 = skip2 * amax;
+    more = false;
 #pragma unroll
     for (int r = 0; r < NC - 1; ++r) {
-      double al[NC / 2], be[NC / 2];
       cd ga[NC / 2];
 #pragma unroll
       for (int p = 0; p < NC / 2; ++p) {
         const int i = cmin(circ_a(NC, r, p), circ_b(NC, r, p));
         const int j = cmax(circ_a(NC, r, p), circ_b(NC, r, p));
-        if (j < c) {
-          al[p] = gsum<G>(norm2(a[i]));
-          be[p] = gsum<G>(norm2(a[j]));
-          ga[p] = gsum<G>(cmulc(a[i], a[j]));
-        }
+        ga[p] = gsum<W>(cmulc(a[i], a[j]));
       }
 #pragma unroll
       for (int p = 0; p < NC / 2; ++p) {
         const int i = cmin(circ_a(NC, r, p), circ_b(NC, r, p));
         const int j = cmax(circ_a(NC, r, p), circ_b(NC, r, p));
-        if (j < c) {
-          const double g = sqrt(norm2(ga[p]));
-          const double ab = sqrt(al[p] * be[p]);
-          if (g > tol * ab && g > 1e-300) {
-            const double zeta = (be[p] - al[p]) / (2.0 * g);
-            const double az = fabs(zeta);
-            const double t = az > 1e150 ? 0.5 / zeta : copysign(1.0, zeta) / (az + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + t * t);
-            const double sn = cs * t;
-            const cd e = {ga[p].re / g, ga[p].im / g};
-            const cd se = sn * e;          // s e^{i phi}
-            const cd sec = conj(se);       // s e^{-i phi}
-            const cd ai = a[i], aj = a[j];
-            a[i] = cs * ai - sec * aj;
-            a[j] = se * ai + cs * aj;
-            const cd vi = v[i], vj = v[j];
-            v[i] = cs * vi - sec * vj;
-            v[j] = se * vi + cs * vj;
-            off = fmax(off, g / ab);
-          }
+        const double g2 = norm2(ga[p]);
+        const double ab = nrm[i] * nrm[j];
+        if (g2 > tol2 * ab && fmin(nrm[i], nrm[j]) > floor2 && g2 > 1e-300) {
+          more |= g2 > 1e-20 * ab;
+          const double rg = rsqrt_acc(g2);                       // 1/|gamma|
+          const double zeta = (nrm[j] - nrm[i]) * (0.5 * rg);
+          const double az = fabs(zeta);
+          const double u = fmin(fma(zeta, zeta, 1.0), 1e300);
+          const double den = az + u * __builtin_amdgcn_rsq(u);  // |zeta| + sqrt(1 + zeta^2)
+          double t = __builtin_amdgcn_rcp(den);
+          t = fma(t, fma(-den, t, 1.0), t);
+          t = copysign(t, zeta);
+          const double cs = rsqrt_acc(fma(t, t, 1.0));
+          const double sn = cs * t;
+          const cd se = {sn * ga[p].re * rg, sn * ga[p].im * rg};  // s e^{i phi}
+          rot2(a[i], a[j], cs, se);
+          rot2(v[i], v[j], cs, se);
+          const double tg = t * (g2 * rg);
+          nrm[i] -= tg;
+          nrm[j] += tg;
         }
       }
     }
-    if (!(off > tol)) break;
   }
   return sweeps;
+}
+
+// Dispatches on the runtime (even) column count c <= NCM so that every round of the
+// round-robin schedule is full.
+template <int W, int NCM>
+__device__ __forceinline__ int jacobi_svd(cd (&a)[NCM], cd (&v)[NCM], int gl, int c, double tol2,
+                                          double skip2, int max_sweeps) {
+#pragma unroll
+  for (int k = 0; k < NCM; ++k) v[k] = {(gl == k && k < c) ? 1.0 : 0.0, 0.0};
+  switch (c) {
+    case 2: return jacobi_fixed<W, 2, NCM>(a, v, tol2, skip2, max_sweeps);
+    case 4: if constexpr (NCM >= 4) return jacobi_fixed<W, 4, NCM>(a, v, tol2, skip2, max_sweeps); break;
+    case 6: if constexpr (NCM >= 6) return jacobi_fixed<W, 6, NCM>(a, v, tol2, skip2, max_sweeps); break;
+    case 8: if constexpr (NCM >= 8) return jacobi_fixed<W, 8, NCM>(a, v, tol2, skip2, max_sweeps); break;
+    case 10: if constexpr (NCM >= 10) return jacobi_fixed<W, 10, NCM>(a, v, tol2, skip2, max_sweeps); break;
+    case 12: if constexpr (NCM >= 12) return jacobi_fixed<W, 12, NCM>(a, v, tol2, skip2, max_sweeps); break;
+    default: break;
+  }
+  return 0;
 }
 
 // ---------------------------------------------------------------------------- per-group LDS
@@ -234,15 +355,18 @@ __device__ __forceinline__ cx<S> proj_apply(cx<S> a0, cx<S> a1, int s, bool diff
   return s == xb ? sel(a0, a1, xb) : czero<S>();
 }
 
-constexpr double kJacobiTol = 1e-15;
+constexpr double kJacobiTol2 = 1e-30;  // (relative off-diagonal 1e-15)^2
 
 // ------------------------------------------------------------------------------ one bundle
-template <class S, int CM, int G>
+template <class S, int CM, int G, int WS>
 __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base) {
   constexpr int D = 2 * CM;
   constexpr int SLOT = slot_elems(CM);
   constexpr bool kMixed = sizeof(S) == sizeof(float);
-  static_assert(G >= 2 * D, "a lane group must hold a QR tile's rows");
+  constexpr int KQ = CM + 1;                 // rank of a tile after the bond-2 MPO, at most
+  constexpr int KJ = (KQ + 1) & ~1;          // Jacobi columns (even)
+  static_assert(G >= 2 * KQ, "a lane group must hold a QR tile's rows");
+  static_assert(WS >= D && WS >= KJ && WS <= G, "the SVD lanes must hold M^H's rows and J's rows");
   const int lane = threadIdx.x;
   const int grp = lane / G;
   const int gl = lane % G;
@@ -257,9 +381,10 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
   cx<S>* arena = reinterpret_cast<cx<S>*>(P.arena) + I->site_off;
   const uint64_t* W = P.marked + I->marked_off;
   const double tol2 = P.trunc_tol * P.trunc_tol;
+  const double rank2 = P.rank_tol * P.rank_tol;
 
   for (int l = gl; l < kBondStride; l += G) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
-  __syncthreads();
+  lds_sync();
 
   double f64 = 0.0, f32 = 0.0, drift = 0.0, truncw = 0.0;
   int status = 0;
@@ -285,9 +410,9 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
           if (!(nn > 0.0) || !isfinite(nn)) status |= GMPS_ST_NAN;
           o = down<S>((1.0 / nr) * up(o));
         }
-        __syncthreads();
+        lds_sync();
         if (real && gl < 2) arena[gl * D] = o;
-        __syncthreads();
+        lds_sync();
       }
     }
   } else {
@@ -303,7 +428,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
           L.R[0][0] = {1.0, 0.0};
           L.rdim[0] = 1;
         }
-        __syncthreads();
+        lds_sync();
         for (int i = 0; i < n; ++i) {
           const int chl = L.bond[i], chr = L.bond[i + 1];
           const bool first = (i == 0), last = (i == n - 1);
@@ -317,7 +442,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
             if (a < chl && b < chr) val = slot[a * 2 * D + s * D + b];
             (&L.A[0][0][0])[e] = val;
           }
-          __syncthreads();
+          lds_sync();
           if (gl < 2 * D) {
             const int a = gl >> 1, s = gl & 1;
             const bool rowok = a < r;
@@ -367,7 +492,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
           }
           const double macs = (double)r * Dl * 2.0 * Dr;
           if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
-          __syncthreads();
+          lds_sync();
           if (last) {
             if (real && gl < 2 * r) {
               const int a = gl >> 1, s = gl & 1;
@@ -377,24 +502,25 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
               L.rdim[n - 1] = r;
               L.rdim[n] = 1;
             }
-            __syncthreads();
+            lds_sync();
             break;
           }
-          cd xr[D], q[D];
+          cd xr[D], q[KQ];
 #pragma unroll
           for (int col = 0; col < D; ++col) xr[col] = (gl < 2 * D) ? L.X[gl][col] : cd{0.0, 0.0};
           const int m = 2 * r;
-          householder_qr<G, D>(xr, q, gl, m, Dr);
-          const int kr = m < Dr ? m : Dr;
+          double qdrop = 0.0;
+          const int kr = householder_qr_rank<G, D, KQ>(xr, q, gl, m, Dr, rank2, &qdrop);
+          truncw = fmax(truncw, qdrop);
           {
-            const double mm = m, cc = Dr;
-            f64 += mm >= cc ? 8.0 * (2.0 * mm * cc * cc - 2.0 * cc * cc * cc / 3.0)
-                            : 8.0 * (2.0 * cc * mm * mm - 2.0 * mm * mm * mm / 3.0);
+            const double mm = m, cc = Dr, kk = kr;
+            f64 += 8.0 * (2.0 * mm * cc * kk - (mm + cc) * kk * kk + 2.0 * kk * kk * kk / 3.0) +
+                   8.0 * (2.0 * mm * kk * kk - 2.0 * kk * kk * kk / 3.0);
           }
           if (real && gl < m) {
             const int a = gl >> 1, s = gl & 1;
 #pragma unroll
-            for (int col = 0; col < D; ++col)
+            for (int col = 0; col < KQ; ++col)
               if (col < kr) slot[a * 2 * D + s * D + col] = down<S>(q[col]);
           }
           if (gl < kr) {
@@ -403,87 +529,96 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
           }
           if (gl == 0) L.rdim[i + 1] = kr;
           r = kr;
-          __syncthreads();
+          lds_sync();
         }
 
         // ---------------------------------------------- truncated-SVD sweep
+        // At site i the tile is M = Q_i (U Sigma)_{i+1} reshaped (r_i, 2 chi'). Jacobi runs on
+        // the r_i columns of M^H (rows (s, j) on lanes): M^H J = V Sigma with J = U, so
+        // V^H = Sigma^{-1} (M^H J)^H stays in site i and U Sigma = J Sigma moves left.
         if (gl == 0) L.Y[0][0] = {1.0, 0.0};
-        __syncthreads();
+        lds_sync();
         for (int i = n - 1; i >= 1; --i) {
           const int ri = L.rdim[i], rn = L.rdim[i + 1];
           const int chn = L.bond[i + 1];
           const int c = 2 * chn;
           cx<S>* slot = arena + (int64_t)i * SLOT;
-          if (gl < D) {
-            const bool rowok = gl < ri;
+          if (gl < ri) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-              cx<S> qrow[D];
+              cx<S> qrow[KQ];
 #pragma unroll
-              for (int b = 0; b < D; ++b)
-                qrow[b] = (rowok && b < rn) ? slot[gl * 2 * D + s * D + b] : czero<S>();
+              for (int b = 0; b < KQ; ++b) qrow[b] = (b < rn) ? slot[gl * 2 * D + s * D + b] : czero<S>();
 #pragma unroll
               for (int jj = 0; jj < CM; ++jj)
                 if (jj < chn) {
                   cx<S> acc = czero<S>();
 #pragma unroll
-                  for (int b = 0; b < D; ++b)
+                  for (int b = 0; b < KQ; ++b)
                     if (b < rn) acc = cfma(acc, qrow[b], down<S>(L.Y[b][jj]));
                   L.X[gl][s * chn + jj] = up(acc);
                 }
             }
-            for (int col = c; col < D; ++col) L.X[gl][col] = {0.0, 0.0};
           }
           {
             const double macs = (double)ri * 2.0 * rn * chn;
             if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
           }
-          __syncthreads();
-          cd mrow[D], vrow[D];
+          lds_sync();
+          cd mh[KJ], u[KJ];
 #pragma unroll
-          for (int col = 0; col < D; ++col) mrow[col] = (gl < D) ? L.X[gl][col] : cd{0.0, 0.0};
-          const int sweeps = jacobi_svd<G, D>(mrow, vrow, gl, c, kJacobiTol, P.max_sweeps);
-          f64 += (double)sweeps * c * (c - 1) / 2.0 * 56.0 * ri;
-          double sg[D];
+          for (int a = 0; a < KJ; ++a) mh[a] = (gl < c && a < ri) ? conj(L.X[a][gl]) : cd{0.0, 0.0};
+          const int ncj = (ri + 1) & ~1;
+          int sweeps = 0;
+          if (gl < WS) sweeps = jacobi_svd<WS, KJ>(mh, u, gl, ncj, kJacobiTol2, P.skip_tol * P.skip_tol, P.max_sweeps);
+          else {
+#pragma unroll
+            for (int a = 0; a < KJ; ++a) u[a] = {0.0, 0.0};
+          }
+          sweeps = (int)gsum<G>(gl == 0 ? (double)sweeps : 0.0);
+          f64 += (double)sweeps * ri * (ri - 1) / 2.0 * 56.0 * c;
+          double sg[KJ];
           double smax = 0.0, stot = 0.0;
 #pragma unroll
-          for (int col = 0; col < D; ++col) {
-            sg[col] = col < c ? gsum<G>(gl < ri ? norm2(mrow[col]) : 0.0) : 0.0;
+          for (int col = 0; col < KJ; ++col) {
+            sg[col] = col < ri ? gsum<G>(gl < c ? norm2(mh[col]) : 0.0) : 0.0;
             smax = fmax(smax, sg[col]);
             stot += sg[col];
           }
           int above = 0;
 #pragma unroll
-          for (int col = 0; col < D; ++col) above += (col < c && sg[col] > 0.0 && sg[col] >= tol2 * smax) ? 1 : 0;
+          for (int col = 0; col < KJ; ++col) above += (col < ri && sg[col] > 0.0 && sg[col] >= tol2 * smax) ? 1 : 0;
           int chi_new = above < cap ? above : cap;
           if (chi_new < 1) chi_new = 1;
           double dropped = 0.0;
-          int rank[D];
+          int rank[KJ];
 #pragma unroll
-          for (int col = 0; col < D; ++col) {
+          for (int col = 0; col < KJ; ++col) {
             int rk = 0;
 #pragma unroll
-            for (int o = 0; o < D; ++o) rk += (sg[o] > sg[col] || (sg[o] == sg[col] && o < col)) ? 1 : 0;
+            for (int o = 0; o < KJ; ++o) rk += (sg[o] > sg[col] || (sg[o] == sg[col] && o < col)) ? 1 : 0;
             rank[col] = rk;
             if (rk >= chi_new) dropped += sg[col];
           }
           if (stot > 0.0) truncw = fmax(truncw, dropped / stot);
           if (!isfinite(stot)) status |= GMPS_ST_NAN;
-          __syncthreads();
+          lds_sync();
 #pragma unroll
-          for (int col = 0; col < D; ++col) {
+          for (int col = 0; col < KJ; ++col) {
             if (rank[col] < chi_new) {
               const int rk = rank[col];
+              const double sig2 = sg[col];
+              const double rs = rsqrt_acc(sig2);  // 1/sigma
               if (real && gl < c) {
                 const int s = gl >= chn ? 1 : 0;
                 const int jp = gl - s * chn;
-                slot[rk * 2 * D + s * D + jp] = down<S>(conj(vrow[col]));
+                slot[rk * 2 * D + s * D + jp] = down<S>(rs * conj(mh[col]));
               }
-              if (gl < ri) L.Y[gl][rk] = mrow[col];
+              if (gl < ri) L.Y[gl][rk] = (sig2 * rs) * u[col];
             }
           }
           if (gl == 0) L.bond[i] = chi_new;
-          __syncthreads();
+          lds_sync();
         }
         // ---------------------------------------------- site 0 (holds the norm)
         {
@@ -495,7 +630,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
           const int jj = gl - s * chn;
           if (act) {
 #pragma unroll
-            for (int b = 0; b < D; ++b)
+            for (int b = 0; b < KQ; ++b)
               if (b < rn) acc = cfma(acc, slot[s * D + b], down<S>(L.Y[b][jj]));
           }
           const double macs = 2.0 * rn * chn;
@@ -507,10 +642,10 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
             drift = fmax(drift, fabs(nr - 1.0));
             acc = down<S>((1.0 / nr) * up(acc));
           }
-          __syncthreads();
+          lds_sync();
           if (real && act) slot[s * D + jj] = acc;
           if (gl == 0) L.bond[0] = 1;
-          __syncthreads();
+          lds_sync();
         }
       }
     }
@@ -530,7 +665,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
       I->status |= status;
     }
   }
-  __syncthreads();
+  lds_sync();
 }
 
 template <class S>
@@ -543,10 +678,11 @@ __global__ __launch_bounds__(64) void grover_kernel(IterParams P) {
     if ((int)bi >= P.queue->nbundles) break;
     const Bundle bd = P.bundles[bi];
     switch (bd.cls) {
-      case 0: run_bundle<S, 2, 8>(P, bd, lds); break;
-      case 1: run_bundle<S, 3, 16>(P, bd, lds); break;
-      case 2: run_bundle<S, 4, 16>(P, bd, lds); break;
-      case 3: run_bundle<S, 6, 32>(P, bd, lds); break;
+      case 0: run_bundle<S, 2, 8, 4>(P, bd, lds); break;
+      case 1: run_bundle<S, 3, 8, 8>(P, bd, lds); break;
+      case 2: run_bundle<S, 4, 16, 8>(P, bd, lds); break;
+      case 3: run_bundle<S, 5, 16, 16>(P, bd, lds); break;
+      case 4: run_bundle<S, 6, 16, 16>(P, bd, lds); break;
       default: break;
     }
   }
@@ -775,7 +911,8 @@ size_t group_lds_bytes(bool mixed, int cls) {
     case 0: return mixed ? sizeof(GroupLds<float, 2>) : sizeof(GroupLds<double, 2>);
     case 1: return mixed ? sizeof(GroupLds<float, 3>) : sizeof(GroupLds<double, 3>);
     case 2: return mixed ? sizeof(GroupLds<float, 4>) : sizeof(GroupLds<double, 4>);
-    case 3: return mixed ? sizeof(GroupLds<float, 6>) : sizeof(GroupLds<double, 6>);
+    case 3: return mixed ? sizeof(GroupLds<float, 5>) : sizeof(GroupLds<double, 5>);
+    case 4: return mixed ? sizeof(GroupLds<float, 6>) : sizeof(GroupLds<double, 6>);
   }
   return 0;
 }

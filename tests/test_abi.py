@@ -63,7 +63,7 @@ def test_workspace_bytes(lib):
 
 def test_bond_cap_beyond_tile_classes_is_unsupported(lib):
     big = (gmps.GmpsInstance * 1)()
-    big[0].n, big[0].M, big[0].chi_cap = 30, 40, 41
+    big[0].n, big[0].M, big[0].chi_cap = 30, 40, 41   # effective cap min(41, M+1) = 41
     assert lib.gmps_workspace_bytes(big, 1, gmps.GMPS_MIXED) == 0
     h = ctypes.c_void_p()
     marked = np.arange(40, dtype=np.uint64)
