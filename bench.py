@@ -66,19 +66,23 @@ def run_step(batch, ks, shots, seed):
     return p, hits
 
 
-def plain_fp64_rate(w, max_instances: int):
+def plain_fp64_rate(w, budget_s: float):
     """The same instances through one B=1 FP64 handle each (one wave per launch), on a
-    stratified subset: one instance per (n, M) stratum, smallest k first, capped."""
+    stratified subset: one instance per (n, M) stratum, in increasing k, until the time
+    budget is spent."""
     import torch
     from paper_2601_03832_amd import gmps
     seen = {}
     for inst in w.instances:
         seen.setdefault((inst.n, inst.M), inst)
-    picks = sorted(seen.values(), key=lambda i: i.k)[:max_instances]
+    picks = sorted(seen.values(), key=lambda i: (i.k * (i.M + 1) * (i.n - 1), i.n, i.M))
     tot_k = 0
     tot_s = 0.0
     worst = 0.0
+    used = []
     for inst in picks:
+        if tot_s > budget_s:
+            break
         b = gmps.Batch([inst], "fp64")
         b.init_uniform()
         torch.cuda.synchronize()
@@ -89,14 +93,16 @@ def plain_fp64_rate(w, max_instances: int):
         worst = max(worst, abs(p - exact_p(inst.n, inst.M, inst.k)))
         tot_k += inst.k
         tot_s += t1 - t0
+        used.append((inst.n, inst.M))
         b.close()
-    return {"value": tot_k / tot_s, "unit": "iterations/s", "instances": len(picks),
+    return {"value": tot_k / tot_s, "unit": "iterations/s", "instances": len(used),
             "sum_k": tot_k, "seconds": tot_s, "max_abs_err": worst,
-            "sample": "one instance per (n, M) stratum of the same workload, smallest k first, "
-                      "each through its own B=1 FP64 handle"}
+            "sample": "one instance per (n, M) stratum of the same workload, cheapest strata first "
+                      "(%d of %d strata within a %.0f s budget), each alone through its own B=1 FP64 "
+                      "handle" % (len(used), len(picks), budget_s)}
 
 
-def cpu_baseline(w, iters_per_stratum: int = 3):
+def cpu_baseline(w, iters_per_stratum: int = 100):
     """The oracle (numpy FP64 MPS, one thread) on a bounded sample: a few iterations of one
     instance per (n, M) stratum; the per-iteration time of each stratum is extrapolated to
     every instance's own k."""
@@ -147,9 +153,12 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4")
-    ap.add_argument("--plain-max", type=int, default=51)
+    ap.add_argument("--plain-budget", type=float, default=20.0)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run one device copy of this many bytes (counter calibration)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64-batch", action="store_true")
     ap.add_argument("--shots", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -169,6 +178,14 @@ def main():
     sum_k = int(sum(ks))
     print("bench: workload %s, %d instances, sum k = %d, precision %s, shots %d"
           % (w.name, len(ks), sum_k, w.precision, shots), file=sys.stderr, flush=True)
+    if args.copy_bytes:
+        src = torch.empty(args.copy_bytes, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print("bench: calibration copy of %d bytes done" % args.copy_bytes, file=sys.stderr, flush=True)
     batch = gmps.Batch(w.instances, w.precision)
 
     for s in range(args.warmup):
@@ -221,8 +238,21 @@ def main():
     }
     print("bench: main measurement done (%.1f ms/step)" % ms_per_step, file=sys.stderr, flush=True)
     batch.close()
+    if w.precision == "mixed" and not args.no_fp64_batch:
+        b64 = gmps.Batch(w.instances, "fp64")
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        p64, _ = run_step(b64, ks, shots, w.shot_seed)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        e64 = max(abs(p64[i] - exact_p(inst.n, inst.M, inst.k)) for i, inst in enumerate(w.instances))
+        line["batched_fp64"] = {"value": sum_k / (t3 - t2), "unit": "iterations/s", "ms_per_step": (t3 - t2) * 1000.0,
+                                "kernel_ms": b64.last_iterate_ms(), "max_abs_err_p": e64,
+                                "note": "same workload and step through the FP64 path (one untimed-warmup-free step)"}
+        b64.close()
+        print("bench: batched fp64 leg done", file=sys.stderr, flush=True)
     if not args.no_plain:
-        line["plain_fp64"] = plain_fp64_rate(w, args.plain_max)
+        line["plain_fp64"] = plain_fp64_rate(w, args.plain_budget)
         line["plain_fp64"]["speedup_of_batched_mixed"] = line["value"] / line["plain_fp64"]["value"]
         print("bench: plain fp64 leg done", file=sys.stderr, flush=True)
     if not args.no_cpu:

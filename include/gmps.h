@@ -81,7 +81,11 @@ typedef struct {
   int32_t waves_per_cu; /* persistent-grid occupancy; <= 0: library plan              */
   int32_t use_graph;    /* 1 (default when 0): replay grover_iterate from a hipGraph;
                            -1: plain launches                                         */
-  int32_t reserved[5];
+  int32_t round_mode;   /* GMPS_MIXED only. 0 or 1 (default): every FP64 result stored as
+                           complex64 is rounded stochastically (unbiased), so rounding
+                           errors of successive iterations do not add up coherently;
+                           -1: round to nearest                                         */
+  int32_t reserved[4];
 } gmps_options;
 
 /* Bytes of device workspace gmps_create() needs for this batch (0 on invalid input).

@@ -112,6 +112,7 @@ struct gmps_batch {
   int max_sweeps = 16;
   int waves_per_cu = 0;
   bool use_graph = true;
+  bool stoch_round = true;
   int num_cus = 0;
   // pinned staging for the per-call bundle table
   Bundle* bundles_pin = nullptr;
@@ -227,6 +228,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     if (opt->max_sweeps > 0) b->max_sweeps = opt->max_sweeps;
     if (opt->waves_per_cu > 0) b->waves_per_cu = opt->waves_per_cu;
     if (opt->use_graph < 0) b->use_graph = false;
+    if (opt->round_mode < 0) b->stoch_round = false;
   }
   hipGetDevice(&b->device);
   hipDeviceProp_t prop;
@@ -293,6 +295,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   P.skip_tol = std::min(b->trunc_tol, b->mixed ? 1e-7 : 1e-15);
   P.rank_tol = b->trunc_tol;
   P.max_sweeps = b->max_sweeps;
+  P.stoch_round = (b->mixed && b->stoch_round) ? 1 : 0;
   *out = b;
   return GMPS_OK;
 }

@@ -56,6 +56,7 @@ struct IterParams {
   double skip_tol;   // relative column norm below which Jacobi leaves a column unrotated
   double rank_tol;   // relative trailing norm at which the QR sweep stops (numerical rank)
   int32_t max_sweeps;
+  int32_t stoch_round;  // mixed path: stochastic rounding of FP64 results stored as complex64
 };
 
 }  // namespace gmps

@@ -67,6 +67,41 @@ __device__ __forceinline__ cd up(cx<S> a) { return {(double)a.re, (double)a.im};
 template <class S>
 __device__ __forceinline__ cx<S> czero() { return {(S)0, (S)0}; }
 
+// ---------------------------------------------------------------------- stochastic rounding
+// Unbiased (stochastic) rounding of a double to float: 29 random bits are added to the low
+// 29 bits of the magnitude, which a float does not keep, and those bits are then cut, so x
+// rounds up with probability equal to its distance from the lower neighbour over the gap
+// (E[round(x)] = x). The float conversion of the truncated value is exact. Random bits come
+// from the high bits of a 64-bit linear congruential stream (Knuth's MMIX constants).
+__device__ __forceinline__ uint32_t rng29(uint64_t& st) {
+  st = st * 6364136223846793005ull + 1442695040888963407ull;
+  return (uint32_t)(st >> 35);
+}
+__device__ __forceinline__ float sround_f32(double x, uint32_t r29) {
+  uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint64_t sign = b & 0x8000000000000000ull;
+  uint64_t mag = (b & 0x7FFFFFFFFFFFFFFFull) + (uint64_t)r29;
+  mag &= ~((1ull << 29) - 1ull);
+  return (float)__longlong_as_double((long long)(sign | mag));
+}
+// Conversion of an FP64 result to the storage type S.
+template <class S>
+__device__ __forceinline__ cx<S> store_cast(cd a, uint64_t& st, bool sr) {
+  if constexpr (sizeof(S) == sizeof(double)) {
+    return {(S)a.re, (S)a.im};
+  } else {
+    if (!sr) return {(S)a.re, (S)a.im};
+    const float re = sround_f32(a.re, rng29(st));
+    const float im = sround_f32(a.im, rng29(st));
+    return {re, im};
+  }
+}
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // ------------------------------------------------------------------------ group collectives
 // Butterfly sums inside a lane group of G = 2, 4, 8, 16 or 32 lanes. Steps 1 and 2 swap
 // neighbours inside a quad (DPP quad_perm); once values are quad-uniform the half-row
@@ -382,6 +417,8 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
   const uint64_t* W = P.marked + I->marked_off;
   const double tol2 = P.trunc_tol * P.trunc_tol;
   const double rank2 = P.rank_tol * P.rank_tol;
+  const bool sr = P.stoch_round != 0;
+  uint64_t rs_state = mix64(((uint64_t)me << 32) ^ ((uint64_t)I->k_done * 0x9E3779B97F4A7C15ull) ^ (uint64_t)gl);
 
   for (int l = gl; l < kBondStride; l += G) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
   lds_sync();
@@ -496,7 +533,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
           if (last) {
             if (real && gl < 2 * r) {
               const int a = gl >> 1, s = gl & 1;
-              slot[a * 2 * D + s * D] = down<S>(L.X[gl][0]);
+              slot[a * 2 * D + s * D] = store_cast<S>(L.X[gl][0], rs_state, sr);
             }
             if (gl == 0) {
               L.rdim[n - 1] = r;
@@ -521,7 +558,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
             const int a = gl >> 1, s = gl & 1;
 #pragma unroll
             for (int col = 0; col < KQ; ++col)
-              if (col < kr) slot[a * 2 * D + s * D + col] = down<S>(q[col]);
+              if (col < kr) slot[a * 2 * D + s * D + col] = store_cast<S>(q[col], rs_state, sr);
           }
           if (gl < kr) {
 #pragma unroll
@@ -612,7 +649,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
               if (real && gl < c) {
                 const int s = gl >= chn ? 1 : 0;
                 const int jp = gl - s * chn;
-                slot[rk * 2 * D + s * D + jp] = down<S>(rs * conj(mh[col]));
+                slot[rk * 2 * D + s * D + jp] = store_cast<S>(rs * conj(mh[col]), rs_state, sr);
               }
               if (gl < ri) L.Y[gl][rk] = (sig2 * rs) * u[col];
             }
@@ -637,13 +674,11 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
           if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
           const double nn = gsum<G>(act ? norm2(up(acc)) : 0.0);
           if (!isfinite(nn) || !(nn > 0.0)) status |= GMPS_ST_NAN;
-          if (diff) {
-            const double nr = sqrt(nn);
-            drift = fmax(drift, fabs(nr - 1.0));
-            acc = down<S>((1.0 / nr) * up(acc));
-          }
+          const double nr = sqrt(nn);
+          if (diff) drift = fmax(drift, fabs(nr - 1.0));
+          const cx<S> out = store_cast<S>((diff ? 1.0 / nr : 1.0) * up(acc), rs_state, sr);
           lds_sync();
-          if (real && act) slot[s * D + jj] = acc;
+          if (real && act) slot[s * D + jj] = out;
           if (gl == 0) L.bond[0] = 1;
           lds_sync();
         }
