@@ -85,7 +85,12 @@ typedef struct {
                            complex64 is rounded stochastically (unbiased), so rounding
                            errors of successive iterations do not add up coherently;
                            -1: round to nearest                                         */
-  int32_t reserved[4];
+  int32_t jacobi_warm;  /* 1: each Jacobi SVD starts from the unitary it produced at the
+                           same (reflection, site) one iteration earlier, which keeps the
+                           bond bases continuous across iterations (it lowers the mixed
+                           path's error several-fold); -1: start from the identity;
+                           0: default, on for GMPS_MIXED and off for GMPS_FP64          */
+  int32_t reserved[3];
 } gmps_options;
 
 /* Bytes of device workspace gmps_create() needs for this batch (0 on invalid input).

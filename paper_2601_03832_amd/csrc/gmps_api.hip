@@ -19,7 +19,7 @@ hipError_t launch_iterate(bool mixed, const IterParams& P, int grid, size_t lds,
 hipError_t iterate_occupancy(bool mixed, size_t lds, int* blocks_per_cu);
 size_t group_lds_bytes(bool mixed, int cls);
 hipError_t launch_init(bool mixed, InstDev* inst, int B, const int64_t* site_start, int32_t* bonds, void* arena,
-                       int64_t total_sites, hipStream_t st);
+                       int64_t total_sites, WarmRec* warm, hipStream_t st);
 hipError_t launch_prob(bool mixed, InstDev* inst, const uint64_t* marked, const int32_t* bonds, const void* arena,
                        int B, double* out, hipStream_t st);
 hipError_t launch_amplitudes(bool mixed, const InstDev* inst, int which, const int32_t* bonds, const void* arena,
@@ -59,17 +59,19 @@ bool valid_instance(const gmps_instance& in) {
 }
 
 struct Layout {
-  size_t inst, marked, bonds, bundles, queue, prob, hits, site_start, arena, total;
+  size_t inst, marked, bonds, bundles, queue, prob, hits, site_start, warm, arena, total;
   int64_t total_marked, total_sites;
 };
 
 bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, Layout* L, std::vector<int>* cls_out,
-                    std::vector<int64_t>* site_off_out) {
+                    std::vector<int64_t>* site_off_out, std::vector<int64_t>* warm_off_out = nullptr) {
   const size_t elem = prec == GMPS_MIXED ? 8 : 16;
   int64_t tm = 0, ts = 0;
   size_t arena_elems = 0;
   if (cls_out) cls_out->resize(B);
   if (site_off_out) site_off_out->resize(B);
+  if (warm_off_out) warm_off_out->resize(B);
+  int64_t warm_recs = 0;
   for (int i = 0; i < B; ++i) {
     if (!valid_instance(inst[i])) return false;
     const int c = pick_class(inst[i].n, inst[i].M, inst[i].chi_cap);
@@ -77,6 +79,8 @@ bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, Layout* L,
     if (cls_out) (*cls_out)[i] = c;
     if (site_off_out) (*site_off_out)[i] = (int64_t)arena_elems;
     arena_elems += (size_t)inst[i].n * slot_elems(kClasses[c].CM);
+    if (warm_off_out) (*warm_off_out)[i] = warm_recs;
+    warm_recs += (int64_t)(inst[i].M + 1) * inst[i].n;
     tm += inst[i].M;
     ts += inst[i].n;
   }
@@ -89,6 +93,7 @@ bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, Layout* L,
   L->prob = off;       off = align_up(off + sizeof(double) * B);
   L->hits = off;       off = align_up(off + sizeof(uint64_t) * B);
   L->site_start = off; off = align_up(off + sizeof(int64_t) * (B + 1));
+  L->warm = off;       off = align_up(off + sizeof(WarmRec) * warm_recs);
   L->arena = off;      off = align_up(off + elem * arena_elems);
   L->total = off;
   L->total_marked = tm;
@@ -113,6 +118,7 @@ struct gmps_batch {
   int waves_per_cu = 0;
   bool use_graph = true;
   bool stoch_round = true;
+  int jacobi_warm = 0;  // 0: library default (mixed path only), 1 on, -1 off
   int num_cus = 0;
   // pinned staging for the per-call bundle table
   Bundle* bundles_pin = nullptr;
@@ -192,10 +198,10 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     if (!valid_instance(inst[i])) return GMPS_E_ARG;
   Layout L;
   std::vector<int> cls;
-  std::vector<int64_t> site_off;
+  std::vector<int64_t> site_off, warm_off;
   for (int i = 0; i < B; ++i)
     if (pick_class(inst[i].n, inst[i].M, inst[i].chi_cap) < 0) return GMPS_E_UNSUPPORTED;
-  if (!compute_layout(inst, B, prec, &L, &cls, &site_off)) return GMPS_E_ARG;
+  if (!compute_layout(inst, B, prec, &L, &cls, &site_off, &warm_off)) return GMPS_E_ARG;
   // marked sets: in range and distinct within an instance
   int64_t tm = 0;
   for (int i = 0; i < B; ++i) tm = std::max<int64_t>(tm, inst[i].marked_off + inst[i].M);
@@ -229,6 +235,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     if (opt->waves_per_cu > 0) b->waves_per_cu = opt->waves_per_cu;
     if (opt->use_graph < 0) b->use_graph = false;
     if (opt->round_mode < 0) b->stoch_round = false;
+    b->jacobi_warm = opt->jacobi_warm;
   }
   hipGetDevice(&b->device);
   hipDeviceProp_t prop;
@@ -250,6 +257,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     d.cls = cls[i];
     d.marked_off = moff;
     d.site_off = site_off[i];
+    d.warm_off = warm_off[i];
     moff += inst[i].M;
     site_start[i + 1] = site_start[i] + inst[i].n;
   }
@@ -296,6 +304,8 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   P.rank_tol = b->trunc_tol;
   P.max_sweeps = b->max_sweeps;
   P.stoch_round = (b->mixed && b->stoch_round) ? 1 : 0;
+  const bool warm_on = b->jacobi_warm > 0 || (b->jacobi_warm == 0 && b->mixed);
+  P.warm = warm_on ? reinterpret_cast<WarmRec*>(b->ws + L.warm) : nullptr;
   *out = b;
   return GMPS_OK;
 }
@@ -303,7 +313,8 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
 int mps_init_uniform(gmps_batch* b) {
   if (!b) return GMPS_E_ARG;
   GMPS_HIP(launch_init(b->mixed, b->params.inst, b->B, reinterpret_cast<const int64_t*>(b->ws + b->lay.site_start),
-                       b->params.bonds, b->params.arena, b->lay.total_sites, b->stream));
+                       b->params.bonds, b->params.arena, b->lay.total_sites, reinterpret_cast<WarmRec*>(b->ws + b->lay.warm),
+                       b->stream));
   std::fill(b->k_done_h.begin(), b->k_done_h.end(), 0);
   return GMPS_OK;
 }

@@ -14,6 +14,18 @@ struct InstDev {
   double drift;            // largest |norm - 1| before a renormalisation
   double trunc_w;          // largest dropped-weight fraction of one truncation
   double flops64, flops32; // algorithmic flops spent so far
+  int64_t warm_off;        // first warm-start record of this instance (see WarmRec)
+};
+
+// The Jacobi SVD at (reflection j, site i) starts from the unitary it produced at the same
+// place in the previous iteration: the tile changes by O(theta) per iteration, so the
+// warm start leaves an O(theta) off-diagonal and quadratic convergence needs ~2 sweeps.
+// One record per (instance, reflection, site): the r x r unitary (FP64, stride KJMAX) and r.
+constexpr int kWarmStride = 8;  // KJ <= 8 for every class
+struct WarmRec {
+  double u[kWarmStride * kWarmStride * 2];  // complex, row-major
+  int32_t r;                                // dimension stored, 0 = none
+  int32_t pad[3];
 };
 
 // A wave processes one bundle: up to kMaxBundle instances that share (class, n, M, k),
@@ -57,6 +69,7 @@ struct IterParams {
   double rank_tol;   // relative trailing norm at which the QR sweep stops (numerical rank)
   int32_t max_sweeps;
   int32_t stoch_round;  // mixed path: stochastic rounding of FP64 results stored as complex64
+  WarmRec* warm;        // warm-start records (null: every Jacobi starts from the identity)
 };
 
 }  // namespace gmps

@@ -179,17 +179,21 @@ __host__ __device__ constexpr int cmax(int a, int b) { return a < b ? b : a; }
 // rows >= m and columns >= c are zero), stopped at the numerical rank: before step j > 0
 // the squared norm T_j of the trailing block X[j:, j:] is compared with rank2 * ||X||^2,
 // and the factorisation ends when it falls below, or after KMAX steps. Returns the rank k
-// kept; lanes gl < k then hold row gl of R (k x c, upper trapezoidal) in x[] and q[] holds
-// row gl of the thin Q (m x k), so X = Q R + E with ||E||^2 = T_k (*dropped = T_k/||X||^2).
-// A tile after a bond-2 MPO has its columns in the order [A block | P A block]; the first
-// block has full rank chi and the projector block adds one direction, so the rank is at
-// most chi + 1 and the trailing rows left after KMAX = chi_max + 1 steps are rounding noise.
+// kept; lanes gl < k then hold row gl of R (k x c, in pivoted column order) in x[] and
+// q[] holds row gl of the thin Q (m x k), so X P = Q R + E with ||E||^2 = T_k
+// (*dropped = T_k/||X||^2), where column perm[t] of X sits in position t.
+// A tile after a bond-2 MPO has its columns in the order [A block (npiv) | P A block]. The
+// A block has full rank and is eliminated in its own order; the projector block adds one
+// direction (rank chi + 1 in all), which need not lie in the block's first column, so from
+// step npiv on the remaining column with the largest residual norm is pivoted in first.
 template <int G, int NC, int KMAX>
-__device__ __forceinline__ int householder_qr_rank(cd (&x)[NC], cd (&q)[KMAX], int gl, int m, int c,
-                                                   double rank2, double* dropped) {
+__device__ __forceinline__ int householder_qr_rank(cd (&x)[NC], cd (&q)[KMAX], int (&perm)[NC], int gl, int m,
+                                                   int c, int npiv, double rank2, double* dropped) {
   const int kmax = min(min(m, c), KMAX);
   cd hv[KMAX];
   double tau[KMAX];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) perm[k] = k;
   double t0 = 0.0;
 #pragma unroll
   for (int k = 0; k < NC; ++k) t0 += norm2(x[k]);
@@ -208,6 +212,32 @@ __device__ __forceinline__ int householder_qr_rank(cd (&x)[NC], cd (&q)[KMAX], i
       if (tj <= rank2 * t0) {
         done = true;
         kr = j;
+      }
+    }
+    if (!done && j < kmax && j >= npiv) {
+      // pivot: the remaining column with the largest norm below row j
+      double best = -1.0;
+      int p = j;
+#pragma unroll
+      for (int k = j; k < NC; ++k) {
+        if (k < c) {
+          const double nk = gsum<G>((gl >= j && gl < m) ? norm2(x[k]) : 0.0);
+          if (nk > best) {
+            best = nk;
+            p = k;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = j + 1; k < NC; ++k) {
+        if (k == p) {
+          const cd t = x[j];
+          x[j] = x[k];
+          x[k] = t;
+          const int pt = perm[j];
+          perm[j] = perm[k];
+          perm[k] = pt;
+        }
       }
     }
     if (!done && j < kmax) {
@@ -346,11 +376,11 @@ __device__ __forceinline__ int jacobi_fixed(cd (&a)[NCM], cd (&v)[NCM], double t
 
 // Dispatches on the runtime (even) column count c <= NCM so that every round of the
 // round-robin schedule is full.
+// v[] must hold row gl of the starting unitary (the identity, or a warm start whose
+// product with the tile is already in a[]).
 template <int W, int NCM>
 __device__ __forceinline__ int jacobi_svd(cd (&a)[NCM], cd (&v)[NCM], int gl, int c, double tol2,
                                           double skip2, int max_sweeps) {
-#pragma unroll
-  for (int k = 0; k < NCM; ++k) v[k] = {(gl == k && k < c) ? 1.0 : 0.0, 0.0};
   switch (c) {
     case 2: return jacobi_fixed<W, 2, NCM>(a, v, tol2, skip2, max_sweeps);
     case 4: if constexpr (NCM >= 4) return jacobi_fixed<W, 4, NCM>(a, v, tol2, skip2, max_sweeps); break;
@@ -371,6 +401,8 @@ struct GroupLds {
   cd R[D][D];               // R of the previous QR step
   cd Y[D][CM];              // U Sigma of the previous SVD step
   cx<S> A[CM][2][CM];       // compressed site tensor, zero padded
+  cd U[CM + 2][CM + 2];     // warm-start unitary
+  cd UG[CM + 2][CM + 2];    // U^H U of the warm start
   int32_t bond[kBondStride];
   int32_t rdim[kBondStride];
 };
@@ -391,6 +423,63 @@ __device__ __forceinline__ cx<S> proj_apply(cx<S> a0, cx<S> a1, int s, bool diff
 }
 
 constexpr double kJacobiTol2 = 1e-30;  // (relative off-diagonal 1e-15)^2
+
+// ----------------------------------------------------------------------- prefetched loads
+// Site tensors are read one site ahead of their use: the loads for site i+1 (QR sweep) or
+// i-1 (SVD sweep) are issued into registers while site i is being factorised, so the
+// global-memory latency overlaps the arithmetic. The slot being prefetched is never written
+// by the current step.
+template <class S, int CM, int G>
+struct APrefetch {
+  static constexpr int NE = (CM * 2 * CM + G - 1) / G;
+  cx<S> v[NE];
+  __device__ __forceinline__ void load(const cx<S>* slot, int gl, int chl, int chr) {
+    constexpr int D = 2 * CM;
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = gl + t * G;
+      const int a = e / (2 * CM), s = (e / CM) & 1, b = e % CM;
+      v[t] = (e < CM * 2 * CM && a < chl && b < chr) ? slot[a * 2 * D + s * D + b] : czero<S>();
+    }
+  }
+  __device__ __forceinline__ void stage(cx<S>* lds_a, int gl) const {
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = gl + t * G;
+      if (e < CM * 2 * CM) lds_a[e] = v[t];
+    }
+  }
+};
+
+template <class S, int CM, int KQ>
+struct QPrefetch {
+  cx<S> v[2][KQ];
+  __device__ __forceinline__ void load(const cx<S>* slot, int gl, int ri, int rn) {
+    constexpr int D = 2 * CM;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int b = 0; b < KQ; ++b) v[s][b] = (gl < ri && b < rn) ? slot[gl * 2 * D + s * D + b] : czero<S>();
+  }
+};
+
+template <int KJ, int G>
+struct WPrefetch {
+  static constexpr int NE = (KJ * KJ + G - 1) / G;
+  cd v[NE];
+  int r;
+  __device__ __forceinline__ void load(const WarmRec* w, int gl, int ncj) {
+    r = w ? w->r : 0;
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = gl + t * G;
+      const int ra = e / KJ, ca = e % KJ;
+      v[t] = (w && e < KJ * KJ && ra < ncj && ca < ncj)
+                 ? cd{w->u[2 * (ra * kWarmStride + ca)], w->u[2 * (ra * kWarmStride + ca) + 1]}
+                 : cd{0.0, 0.0};
+    }
+  }
+};
 
 // ------------------------------------------------------------------------------ one bundle
 template <class S, int CM, int G, int WS>
@@ -418,6 +507,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
   const double tol2 = P.trunc_tol * P.trunc_tol;
   const double rank2 = P.rank_tol * P.rank_tol;
   const bool sr = P.stoch_round != 0;
+  WarmRec* warm = P.warm ? P.warm + I->warm_off : nullptr;
   uint64_t rs_state = mix64(((uint64_t)me << 32) ^ ((uint64_t)I->k_done * 0x9E3779B97F4A7C15ull) ^ (uint64_t)gl);
 
   for (int l = gl; l < kBondStride; l += G) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
@@ -465,6 +555,8 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
           L.R[0][0] = {1.0, 0.0};
           L.rdim[0] = 1;
         }
+        APrefetch<S, CM, G> apre;
+        apre.load(arena, gl, L.bond[0], L.bond[1]);
         lds_sync();
         for (int i = 0; i < n; ++i) {
           const int chl = L.bond[i], chr = L.bond[i + 1];
@@ -473,12 +565,8 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
           const int Dl = first ? 1 : 2 * chl;
           const int Dr = last ? 1 : 2 * chr;
           cx<S>* slot = arena + (int64_t)i * SLOT;
-          for (int e = gl; e < CM * 2 * CM; e += G) {
-            const int a = e / (2 * CM), s = (e / CM) & 1, b = e % CM;
-            cx<S> val = czero<S>();
-            if (a < chl && b < chr) val = slot[a * 2 * D + s * D + b];
-            (&L.A[0][0][0])[e] = val;
-          }
+          apre.stage(&L.A[0][0][0], gl);
+          if (i + 1 < n) apre.load(arena + (int64_t)(i + 1) * SLOT, gl, L.bond[i + 1], L.bond[i + 2]);
           lds_sync();
           if (gl < 2 * D) {
             const int a = gl >> 1, s = gl & 1;
@@ -547,7 +635,8 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
           for (int col = 0; col < D; ++col) xr[col] = (gl < 2 * D) ? L.X[gl][col] : cd{0.0, 0.0};
           const int m = 2 * r;
           double qdrop = 0.0;
-          const int kr = householder_qr_rank<G, D, KQ>(xr, q, gl, m, Dr, rank2, &qdrop);
+          int perm[D];
+          const int kr = householder_qr_rank<G, D, KQ>(xr, q, perm, gl, m, Dr, last ? Dr : chr, rank2, &qdrop);
           truncw = fmax(truncw, qdrop);
           {
             const double mm = m, cc = Dr, kk = kr;
@@ -561,8 +650,9 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
               if (col < kr) slot[a * 2 * D + s * D + col] = store_cast<S>(q[col], rs_state, sr);
           }
           if (gl < kr) {
+            // R P^T: column t of the pivoted R belongs to column perm[t] of the tile
 #pragma unroll
-            for (int col = 0; col < D; ++col) L.R[gl][col] = col < gl ? cd{0.0, 0.0} : xr[col];
+            for (int col = 0; col < D; ++col) L.R[gl][perm[col]] = col < gl ? cd{0.0, 0.0} : xr[col];
           }
           if (gl == 0) L.rdim[i + 1] = kr;
           r = kr;
@@ -574,18 +664,28 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
         // the r_i columns of M^H (rows (s, j) on lanes): M^H J = V Sigma with J = U, so
         // V^H = Sigma^{-1} (M^H J)^H stays in site i and U Sigma = J Sigma moves left.
         if (gl == 0) L.Y[0][0] = {1.0, 0.0};
+        QPrefetch<S, CM, KQ> qpre;
+        WPrefetch<KJ, G> wpre;
+        qpre.load(arena + (int64_t)(n - 1) * SLOT, gl, L.rdim[n - 1], L.rdim[n]);
+        wpre.load(warm ? warm + ((int64_t)j * n + (n - 1)) : nullptr, gl, (L.rdim[n - 1] + 1) & ~1);
         lds_sync();
         for (int i = n - 1; i >= 1; --i) {
           const int ri = L.rdim[i], rn = L.rdim[i + 1];
           const int chn = L.bond[i + 1];
           const int c = 2 * chn;
           cx<S>* slot = arena + (int64_t)i * SLOT;
+          const QPrefetch<S, CM, KQ> qcur = qpre;
+          const WPrefetch<KJ, G> wcur = wpre;
+          if (i - 1 >= 1) {
+            qpre.load(arena + (int64_t)(i - 1) * SLOT, gl, L.rdim[i - 1], L.rdim[i]);
+            wpre.load(warm ? warm + ((int64_t)j * n + (i - 1)) : nullptr, gl, (L.rdim[i - 1] + 1) & ~1);
+          }
           if (gl < ri) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
               cx<S> qrow[KQ];
 #pragma unroll
-              for (int b = 0; b < KQ; ++b) qrow[b] = (b < rn) ? slot[gl * 2 * D + s * D + b] : czero<S>();
+              for (int b = 0; b < KQ; ++b) qrow[b] = qcur.v[s][b];
 #pragma unroll
               for (int jj = 0; jj < CM; ++jj)
                 if (jj < chn) {
@@ -606,6 +706,78 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
 #pragma unroll
           for (int a = 0; a < KJ; ++a) mh[a] = (gl < c && a < ri) ? conj(L.X[a][gl]) : cd{0.0, 0.0};
           const int ncj = (ri + 1) & ~1;
+          // warm start: the unitary from this (reflection, site) in the previous iteration
+          WarmRec* wrec = warm ? warm + ((int64_t)j * n + i) : nullptr;
+          const bool use_warm = wrec && wcur.r == ncj;
+          // the stored unitary is a product of exact rotations, so its unitarity drifts by
+          // ~1e-16 per use; one Newton-Schulz step every 64 iterations keeps it below ~1e-13
+          const bool renorm_warm = use_warm && (((uint64_t)I->k_done + (uint64_t)it) & 63ull) == 0ull;
+          if (use_warm) {
+#pragma unroll
+            for (int t = 0; t < WPrefetch<KJ, G>::NE; ++t) {
+              const int e = gl + t * G;
+              const int ra = e / KJ, ca = e % KJ;
+              if (e < KJ * KJ && ra < ncj && ca < ncj) L.U[ra][ca] = wcur.v[t];
+            }
+          }
+          lds_sync();
+          if (renorm_warm) {
+            // one Newton-Schulz polar step U <- U (3I - U^H U) / 2 removes the unitarity
+            // error the stored product picked up (error e -> O(e^2))
+            if (gl < ncj) {
+#pragma unroll
+              for (int cc = 0; cc < KJ; ++cc)
+                if (cc < ncj) {
+                  cd g = {0.0, 0.0};
+#pragma unroll
+                  for (int a = 0; a < KJ; ++a)
+                    if (a < ncj) g = g + cmulc(L.U[a][gl], L.U[a][cc]);
+                  L.UG[gl][cc] = g;
+                }
+            }
+          }
+          lds_sync();
+          if (renorm_warm) {
+            cd un[KJ];
+            if (gl < ncj) {
+#pragma unroll
+              for (int cc = 0; cc < KJ; ++cc) {
+                cd acc = {0.0, 0.0};
+#pragma unroll
+                for (int b = 0; b < KJ; ++b)
+                  if (b < ncj && cc < ncj) acc = cfma(acc, L.U[gl][b], L.UG[b][cc]);
+                un[cc] = cc < ncj ? 1.5 * L.U[gl][cc] - 0.5 * acc : cd{0.0, 0.0};
+              }
+            }
+            lds_sync();
+            if (gl < ncj) {
+#pragma unroll
+              for (int cc = 0; cc < KJ; ++cc)
+                if (cc < ncj) L.U[gl][cc] = un[cc];
+            }
+          } else {
+            lds_sync();
+          }
+          lds_sync();
+          if (use_warm) {
+            cd t[KJ];
+#pragma unroll
+            for (int b = 0; b < KJ; ++b) {
+              cd acc = {0.0, 0.0};
+#pragma unroll
+              for (int a = 0; a < KJ; ++a)
+                if (a < ncj && b < ncj) acc = cfma(acc, mh[a], L.U[a][b]);
+              t[b] = acc;
+            }
+#pragma unroll
+            for (int b = 0; b < KJ; ++b) {
+              mh[b] = t[b];
+              u[b] = (gl < ncj && b < ncj) ? L.U[gl][b] : cd{(gl == b && b < ncj) ? 1.0 : 0.0, 0.0};
+            }
+          } else {
+#pragma unroll
+            for (int b = 0; b < KJ; ++b) u[b] = {(gl == b && b < ncj) ? 1.0 : 0.0, 0.0};
+          }
           int sweeps = 0;
           if (gl < WS) sweeps = jacobi_svd<WS, KJ>(mh, u, gl, ncj, kJacobiTol2, P.skip_tol * P.skip_tol, P.max_sweeps);
           else {
@@ -616,29 +788,56 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
           f64 += (double)sweeps * ri * (ri - 1) / 2.0 * 56.0 * c;
           double sg[KJ];
           double smax = 0.0, stot = 0.0;
+          // every column below ncj can carry weight (a warm start mixes the pad column in)
 #pragma unroll
           for (int col = 0; col < KJ; ++col) {
-            sg[col] = col < ri ? gsum<G>(gl < c ? norm2(mh[col]) : 0.0) : 0.0;
+            sg[col] = col < ncj ? gsum<G>(gl < c ? norm2(mh[col]) : 0.0) : 0.0;
             smax = fmax(smax, sg[col]);
             stot += sg[col];
           }
           int above = 0;
 #pragma unroll
-          for (int col = 0; col < KJ; ++col) above += (col < ri && sg[col] > 0.0 && sg[col] >= tol2 * smax) ? 1 : 0;
+          for (int col = 0; col < KJ; ++col) above += (col < ncj && sg[col] > 0.0 && sg[col] >= tol2 * smax) ? 1 : 0;
           int chi_new = above < cap ? above : cap;
           if (chi_new < 1) chi_new = 1;
+          // keep the chi_new largest columns; kept columns stay in their index order (so the
+          // bond basis, and the next warm start, does not jump when Schmidt values are
+          // degenerate), dropped ones follow
           double dropped = 0.0;
           int rank[KJ];
+          bool keep[KJ];
 #pragma unroll
           for (int col = 0; col < KJ; ++col) {
             int rk = 0;
 #pragma unroll
             for (int o = 0; o < KJ; ++o) rk += (sg[o] > sg[col] || (sg[o] == sg[col] && o < col)) ? 1 : 0;
-            rank[col] = rk;
-            if (rk >= chi_new) dropped += sg[col];
+            keep[col] = rk < chi_new;
+            if (!keep[col]) dropped += sg[col];
+          }
+          {
+            int nk = 0, nd = 0;
+#pragma unroll
+            for (int col = 0; col < KJ; ++col) {
+              rank[col] = keep[col] ? nk : chi_new + nd;
+              nk += keep[col] ? 1 : 0;
+              nd += keep[col] ? 0 : 1;
+            }
           }
           if (stot > 0.0) truncw = fmax(truncw, dropped / stot);
           if (!isfinite(stot)) status |= GMPS_ST_NAN;
+          if (wrec && real) {
+            // keep J with its columns in singular-value order for the next iteration
+            if (gl < ncj) {
+#pragma unroll
+              for (int col = 0; col < KJ; ++col)
+                if (col < ncj) {
+                  const int rk = rank[col];
+                  wrec->u[2 * (gl * kWarmStride + rk)] = u[col].re;
+                  wrec->u[2 * (gl * kWarmStride + rk) + 1] = u[col].im;
+                }
+            }
+            if (gl == 0) wrec->r = ncj;
+          }
           lds_sync();
 #pragma unroll
           for (int col = 0; col < KJ; ++col) {
@@ -730,7 +929,7 @@ __global__ void queue_reset_kernel(QueueState* q) {
 // a2: every instance <- |+>^n with all bonds 1.
 template <class S>
 __global__ void init_uniform_kernel(InstDev* inst, int B, const int64_t* site_start, int32_t* bonds,
-                                    void* arena_v, int64_t total_sites) {
+                                    void* arena_v, int64_t total_sites, WarmRec* warm) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total_sites) return;
   // locate the instance owning global site t (site_start is the prefix sum of n)
@@ -749,6 +948,8 @@ __global__ void init_uniform_kernel(InstDev* inst, int B, const int64_t* site_st
   slot[D] = {h, (S)0};
   bonds[(int64_t)lo * kBondStride + i] = 1;
   if (i == I.n - 1) bonds[(int64_t)lo * kBondStride + I.n] = 1;
+  if (warm)
+    for (int j = 0; j <= I.M; ++j) warm[I.warm_off + (int64_t)j * I.n + i].r = 0;
   if (i == 0) {
     I.k_done = 0;
     I.status = 0;
@@ -953,14 +1154,14 @@ size_t group_lds_bytes(bool mixed, int cls) {
 }
 
 hipError_t launch_init(bool mixed, InstDev* inst, int B, const int64_t* site_start, int32_t* bonds, void* arena,
-                       int64_t total_sites, hipStream_t st) {
+                       int64_t total_sites, WarmRec* warm, hipStream_t st) {
   const int blk = 256;
   const int grid = (int)((total_sites + blk - 1) / blk);
   if (grid == 0) return hipSuccess;
   if (mixed)
-    init_uniform_kernel<float><<<grid, blk, 0, st>>>(inst, B, site_start, bonds, arena, total_sites);
+    init_uniform_kernel<float><<<grid, blk, 0, st>>>(inst, B, site_start, bonds, arena, total_sites, warm);
   else
-    init_uniform_kernel<double><<<grid, blk, 0, st>>>(inst, B, site_start, bonds, arena, total_sites);
+    init_uniform_kernel<double><<<grid, blk, 0, st>>>(inst, B, site_start, bonds, arena, total_sites, warm);
   return hipGetLastError();
 }
 
