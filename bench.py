@@ -29,15 +29,18 @@ from paper_2601_03832_amd import inputs  # noqa: E402
 FP64_VECTOR_PEAK = 78.6e12    # MI355X published FP64 vector rate, FLOP/s
 FP32_VECTOR_PEAK = 157.3e12   # MI355X published FP32 vector rate, FLOP/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grover_kernel.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2601_03832_amd", "csrc", f)
-                  for f in ("gmps_kernels.hip", "gmps_internal.h")]
+# the iterate kernel each --kernel choice runs (the library's choice is the team kernel)
+KERNEL_NAME = {"auto": "grover_team_kernel", "team": "grover_team_kernel", "group": "grover_group_kernel"}
+CSRC = os.path.join(ROOT, "paper_2601_03832_amd", "csrc")
 
 
 def kernel_hash() -> str:
+    """Hash of the device sources: a stored counter record is used only while it matches."""
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")) and name != "gmps_api.hip":
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
 
 
@@ -160,6 +163,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64-batch", action="store_true")
     ap.add_argument("--shots", type=int, default=None)
+    ap.add_argument("--kernel", default="auto", choices=sorted(["auto", "group", "team"]),
+                    help="iterate kernel: lane-group, team, or the library's choice")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: instances are independent, so a multi-GPU run "
@@ -186,7 +191,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         print("bench: calibration copy of %d bytes done" % args.copy_bytes, file=sys.stderr, flush=True)
-    batch = gmps.Batch(w.instances, w.precision)
+    batch = gmps.Batch(w.instances, w.precision, kernel=args.kernel)
 
     for s in range(args.warmup):
         run_step(batch, ks, shots, w.shot_seed)
@@ -227,19 +232,19 @@ def main():
         "dtype": "c64/f64" if w.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "instances": len(ks), "sum_k": sum_k, "precision": w.precision,
-                   "shots_per_instance": shots, "description": w.description},
+                   "shots_per_instance": shots, "kernel": args.kernel, "description": w.description},
         "accuracy": {"max_abs_err_p": float(errs.max()), "tolerance": tol, "pass": bool(errs.max() <= tol),
                      "status_flags": int(np.bitwise_or.reduce(diag["status"]))},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK,
                      "traffic": tr["bytes_per_launch"] if tr else None,
-                     "kernel": "grover_kernel", "kernel_ms": kms,
+                     "kernel": KERNEL_NAME[args.kernel], "kernel_ms": kms,
                      "flops64_per_launch": f64, "flops32_per_launch": f32},
     }
     print("bench: main measurement done (%.1f ms/step)" % ms_per_step, file=sys.stderr, flush=True)
     batch.close()
     if w.precision == "mixed" and not args.no_fp64_batch:
-        b64 = gmps.Batch(w.instances, "fp64")
+        b64 = gmps.Batch(w.instances, "fp64", kernel=args.kernel)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         p64, _ = run_step(b64, ks, shots, w.shot_seed)

@@ -48,7 +48,7 @@ enum {
   GMPS_E_ARG = -1,         /* invalid argument; nothing was enqueued               */
   GMPS_E_WORKSPACE = -2,   /* workspace NULL, misaligned (<256 B) or too small      */
   GMPS_E_HIP = -3,         /* a HIP runtime call failed                             */
-  GMPS_E_UNSUPPORTED = -4, /* bond cap beyond the compiled tile classes, no device  */
+  GMPS_E_UNSUPPORTED = -4, /* effective bond cap above 32, or no device            */
   GMPS_E_NUMERIC = -5      /* some instance reports NaN/Inf or norm drift (see      *
                             * gmps_diagnostics); results were still written         */
 };
@@ -90,19 +90,25 @@ typedef struct {
                            bond bases continuous across iterations (it lowers the mixed
                            path's error several-fold); -1: start from the identity;
                            0: default, on for GMPS_MIXED and off for GMPS_FP64          */
-  int32_t reserved[3];
+  int32_t kernel;       /* iterate kernel: 1 = lane-group kernel (a tile row per lane, up to 8
+                           instances per wave; bond caps up to 6, larger caps go to the team
+                           kernel), 2 = team kernel (a tile column per lane slot, one instance per
+                           team of 16-256 threads; bond caps up to 32), 0 = library choice
+                           (the team kernel) */
+  int32_t reserved[2];
 } gmps_options;
 
-/* Bytes of device workspace gmps_create() needs for this batch (0 on invalid input).
- * inst: host [B]; marked offsets are not read. */
+/* Bytes of device workspace gmps_create() needs for this batch with either iterate kernel
+ * (0 on invalid input). inst: host [B]; marked offsets are not read. */
 size_t gmps_workspace_bytes(const gmps_instance* inst, int32_t B, gmps_prec prec);
 
 /* Creates a handle over B instances. inst: host [B]; marked: host, every instance's
  * marked indices at its marked_off; both are copied. dev_workspace: device memory of at
  * least gmps_workspace_bytes() bytes, 256-byte aligned. hip_stream: hipStream_t or NULL.
  * The chain is left uninitialised: call mps_init_uniform() next.
- * Errors: GMPS_E_ARG (bad instance, duplicate or out-of-range marked index),
- * GMPS_E_WORKSPACE, GMPS_E_UNSUPPORTED (no tile class holds the bond cap), GMPS_E_HIP. */
+ * Errors: GMPS_E_ARG (bad instance, duplicate or out-of-range marked index, unknown
+ * kernel), GMPS_E_WORKSPACE, GMPS_E_UNSUPPORTED (no tile class holds the bond cap),
+ * GMPS_E_HIP. */
 int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const uint64_t* marked,
                 gmps_prec prec, const gmps_options* opt, void* dev_workspace, size_t ws_bytes,
                 void* hip_stream);

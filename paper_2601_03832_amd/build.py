@@ -13,7 +13,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmps.so")
-SOURCES = ["gmps_kernels.hip", "gmps_api.hip"]
+SOURCES = ["gmps_group.hip", "gmps_team.hip", "gmps_team_cm2.hip", "gmps_team_cm3.hip", "gmps_team_cm5.hip",
+           "gmps_team_cm8.hip", "gmps_team_cm17.hip", "gmps_team_cm32.hip",
+           "gmps_readout.hip", "gmps_api.hip"]
 ARCH = os.environ.get("GMPS_OFFLOAD_ARCH", "gfx950")
 
 
@@ -31,21 +33,38 @@ def flags(extra=()):
             "-I" + os.path.join(ROOT, "include"), *extra]
 
 
-def build(verbose: bool = False, save_temps: str | None = None) -> str:
-    objs = []
+def _stale(src: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")] + \
+           [os.path.join(ROOT, "include", h) for h in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(d) for d in deps) > os.path.getmtime(obj)
+
+
+def build(verbose: bool = False, save_temps: str | None = None, incremental: bool = False) -> str:
     cc = hipcc()
     tmp = os.path.join(HERE, "_build")
     os.makedirs(tmp, exist_ok=True)
+    cmds = []
+    objs = []
     for src in SOURCES:
         obj = os.path.join(tmp, src.replace(".hip", ".o"))
         extra = []
         if save_temps:
             extra = ["-save-temps=obj", "-Rpass-analysis=kernel-resource-usage"]
-        cmd = [cc, *flags(extra), "-c", os.path.join(CSRC, src), "-o", obj]
+        objs.append(obj)
+        if incremental and not _stale(os.path.join(CSRC, src), obj):
+            continue
+        cmds.append([cc, *flags(extra), "-c", os.path.join(CSRC, src), "-o", obj])
+    # the translation units are independent: compile them side by side
+    procs = []
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        procs.append(subprocess.Popen(cmd))
+    bad = [c for c, p in zip(cmds, procs) if p.wait() != 0]
+    if bad:
+        raise subprocess.CalledProcessError(1, bad[0])
     out_tmp = LIB + ".tmp"
     cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", out_tmp, *objs]
     if verbose:
@@ -56,4 +75,4 @@ def build(verbose: bool = False, save_temps: str | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -1,5 +1,5 @@
 // Host runtime of libgmps: argument checking, workspace carving, bundling of instances
-// into waves (longest first), hipGraph capture of the iterate launch, and the C ABI.
+// into workgroups (longest first), hipGraph capture of the iterate launches, and the C ABI.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,16 +15,21 @@
 #include "gmps_internal.h"
 
 namespace gmps {
-hipError_t launch_iterate(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st);
-hipError_t iterate_occupancy(bool mixed, size_t lds, int* blocks_per_cu);
+hipError_t launch_group(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st);
+hipError_t group_occupancy(bool mixed, size_t lds, int* blocks_per_cu);
 size_t group_lds_bytes(bool mixed, int cls);
+int team_per_bundle(int cls);
+size_t team_lds_bytes(bool mixed, int cls);
+hipError_t launch_team(bool mixed, int cls, const IterParams& P, int grid, size_t lds, hipStream_t st);
+hipError_t team_occupancy(bool mixed, int cls, size_t lds, int* blocks_per_cu);
+hipError_t launch_queue_reset(QueueState* q, hipStream_t st);
 hipError_t launch_init(bool mixed, InstDev* inst, int B, const int64_t* site_start, int32_t* bonds, void* arena,
-                       int64_t total_sites, WarmRec* warm, hipStream_t st);
+                       int64_t total_sites, char* warm, hipStream_t st);
 hipError_t launch_prob(bool mixed, InstDev* inst, const uint64_t* marked, const int32_t* bonds, const void* arena,
                        int B, double* out, hipStream_t st);
-hipError_t launch_amplitudes(bool mixed, const InstDev* inst, int which, const int32_t* bonds, const void* arena,
-                             const uint64_t* xs, int64_t cnt, double* out, hipStream_t st);
-hipError_t launch_sample(bool mixed, const InstDev* inst, const uint64_t* marked, const int32_t* bonds,
+hipError_t launch_amplitudes(bool mixed, int maxc, const InstDev* inst, int which, const int32_t* bonds,
+                             const void* arena, const uint64_t* xs, int64_t cnt, double* out, hipStream_t st);
+hipError_t launch_sample(bool mixed, int maxc, const InstDev* inst, const uint64_t* marked, const int32_t* bonds,
                          const void* arena, int B, const int64_t* shot_off, int64_t total, uint64_t seed,
                          uint64_t* bits, unsigned long long* hits, hipStream_t st);
 }  // namespace gmps
@@ -45,12 +50,29 @@ int effective_cap(int n, int M, int cap) {
   return (int)need;
 }
 
-// Smallest tile class whose bond capacity holds the effective cap; -1 if none.
-int pick_class(int n, int M, int cap) {
+// Iterate kernels: the lane-group kernel (bond caps up to 6) and the team kernels.
+enum { kPathAuto = 0, kPathGroup = 1, kPathTeam = 2 };
+constexpr int kLaunchKinds = 1 + kNumWide;  // the lane-group kernel, then one per team class
+
+// Smallest tile class of the requested kernel whose bond capacity holds the effective cap
+// (the lane-group kernel hands caps beyond its classes to the team kernels); -1 if none.
+int pick_class(int n, int M, int cap, int path) {
   const int need = effective_cap(n, M, cap);
-  for (int c = 0; c < kNumClasses; ++c)
-    if (kClasses[c].CM >= need) return c;
+  if (path != kPathTeam)
+    for (int c = 0; c < kNumClasses; ++c)
+      if (kClasses[c].CM >= need) return c;
+  for (int w = 0; w < kNumWide; ++w)
+    if (kWide[w].CM >= need) return kWideBase + w;
   return -1;
+}
+
+// The library's choice is the team kernel: a step of a long serial chain takes less time
+// there for every class, and it holds every bond cap.
+int resolve_path(int requested) { return requested == kPathGroup ? kPathGroup : kPathTeam; }
+
+// Warm-start record bytes of one (reflection, site) for a class.
+size_t warm_rec_bytes(int cls) {
+  return is_wide(cls) ? sizeof(double) * (size_t)wide_warm_doubles(class_cm(cls)) : sizeof(WarmRec);
 }
 
 bool valid_instance(const gmps_instance& in) {
@@ -63,7 +85,7 @@ struct Layout {
   int64_t total_marked, total_sites;
 };
 
-bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, Layout* L, std::vector<int>* cls_out,
+bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, int path, Layout* L, std::vector<int>* cls_out,
                     std::vector<int64_t>* site_off_out, std::vector<int64_t>* warm_off_out = nullptr) {
   const size_t elem = prec == GMPS_MIXED ? 8 : 16;
   int64_t tm = 0, ts = 0;
@@ -71,16 +93,16 @@ bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, Layout* L,
   if (cls_out) cls_out->resize(B);
   if (site_off_out) site_off_out->resize(B);
   if (warm_off_out) warm_off_out->resize(B);
-  int64_t warm_recs = 0;
+  size_t warm_bytes = 0;
   for (int i = 0; i < B; ++i) {
     if (!valid_instance(inst[i])) return false;
-    const int c = pick_class(inst[i].n, inst[i].M, inst[i].chi_cap);
+    const int c = pick_class(inst[i].n, inst[i].M, inst[i].chi_cap, path);
     if (c < 0) return false;
     if (cls_out) (*cls_out)[i] = c;
     if (site_off_out) (*site_off_out)[i] = (int64_t)arena_elems;
-    arena_elems += (size_t)inst[i].n * slot_elems(kClasses[c].CM);
-    if (warm_off_out) (*warm_off_out)[i] = warm_recs;
-    warm_recs += (int64_t)(inst[i].M + 1) * inst[i].n;
+    arena_elems += (size_t)inst[i].n * slot_elems(class_cm(c));
+    if (warm_off_out) (*warm_off_out)[i] = (int64_t)warm_bytes;
+    warm_bytes += (size_t)(inst[i].M + 1) * inst[i].n * warm_rec_bytes(c);
     tm += inst[i].M;
     ts += inst[i].n;
   }
@@ -89,11 +111,11 @@ bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, Layout* L,
   L->marked = off;     off = align_up(off + sizeof(uint64_t) * std::max<int64_t>(tm, 1));
   L->bonds = off;      off = align_up(off + sizeof(int32_t) * kBondStride * B);
   L->bundles = off;    off = align_up(off + sizeof(Bundle) * B);
-  L->queue = off;      off = align_up(off + sizeof(QueueState));
+  L->queue = off;      off = align_up(off + sizeof(QueueState) * kLaunchKinds);
   L->prob = off;       off = align_up(off + sizeof(double) * B);
   L->hits = off;       off = align_up(off + sizeof(uint64_t) * B);
   L->site_start = off; off = align_up(off + sizeof(int64_t) * (B + 1));
-  L->warm = off;       off = align_up(off + sizeof(WarmRec) * warm_recs);
+  L->warm = off;       off = align_up(off + warm_bytes);
   L->arena = off;      off = align_up(off + elem * arena_elems);
   L->total = off;
   L->total_marked = tm;
@@ -119,6 +141,8 @@ struct gmps_batch {
   bool use_graph = true;
   bool stoch_round = true;
   int jacobi_warm = 0;  // 0: library default (mixed path only), 1 on, -1 off
+  int path = kPathGroup;
+  int max_cm = 0;       // largest class bond of the batch (read-out register sizing)
   int num_cus = 0;
   // pinned staging for the per-call bundle table
   Bundle* bundles_pin = nullptr;
@@ -127,10 +151,13 @@ struct gmps_batch {
   bool staging_pending = false;
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
   bool timed = false;
-  // graph cache keyed by (grid, lds)
+  // graph cache keyed by every launch's (grid, lds, first bundle)
   hipGraphExec_t graph = nullptr;
-  int graph_grid = -1;
-  size_t graph_lds = 0;
+  std::vector<int64_t> graph_key;
+  // side streams and events that run the kernels of several classes side by side
+  hipStream_t side[kLaunchKinds] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kLaunchKinds] = {};
   // lazily grown device staging for read-out calls
   void* stage = nullptr;
   size_t stage_bytes = 0;
@@ -184,9 +211,11 @@ const char* gmps_strerror(int status) {
 
 size_t gmps_workspace_bytes(const gmps_instance* inst, int32_t B, gmps_prec prec) {
   if (!inst || B <= 0 || (prec != GMPS_FP64 && prec != GMPS_MIXED)) return 0;
-  Layout L;
-  if (!compute_layout(inst, B, prec, &L, nullptr, nullptr)) return 0;
-  return L.total;
+  // enough for either iterate kernel, so the choice can be made at gmps_create()
+  Layout Lg, Lt;
+  if (!compute_layout(inst, B, prec, kPathGroup, &Lg, nullptr, nullptr)) return 0;
+  if (!compute_layout(inst, B, prec, kPathTeam, &Lt, nullptr, nullptr)) return 0;
+  return std::max(Lg.total, Lt.total);
 }
 
 int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const uint64_t* marked, gmps_prec prec,
@@ -196,12 +225,14 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   if (!inst || B <= 0 || !marked || (prec != GMPS_FP64 && prec != GMPS_MIXED)) return GMPS_E_ARG;
   for (int i = 0; i < B; ++i)
     if (!valid_instance(inst[i])) return GMPS_E_ARG;
+  if (opt && (opt->kernel < 0 || opt->kernel > kPathTeam)) return GMPS_E_ARG;
+  const int path = resolve_path(opt ? opt->kernel : kPathAuto);
   Layout L;
   std::vector<int> cls;
   std::vector<int64_t> site_off, warm_off;
   for (int i = 0; i < B; ++i)
-    if (pick_class(inst[i].n, inst[i].M, inst[i].chi_cap) < 0) return GMPS_E_UNSUPPORTED;
-  if (!compute_layout(inst, B, prec, &L, &cls, &site_off, &warm_off)) return GMPS_E_ARG;
+    if (pick_class(inst[i].n, inst[i].M, inst[i].chi_cap, path) < 0) return GMPS_E_UNSUPPORTED;
+  if (!compute_layout(inst, B, prec, path, &L, &cls, &site_off, &warm_off)) return GMPS_E_ARG;
   // marked sets: in range and distinct within an instance
   int64_t tm = 0;
   for (int i = 0; i < B; ++i) tm = std::max<int64_t>(tm, inst[i].marked_off + inst[i].M);
@@ -216,7 +247,9 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
       packed.push_back(x);
     }
   }
-  if (!dev_workspace || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) != 0)
+  // the documented requirement: what gmps_workspace_bytes() returns for this batch
+  if (!dev_workspace || ws_bytes < gmps_workspace_bytes(inst, B, prec) ||
+      (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) != 0)
     return GMPS_E_WORKSPACE;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return GMPS_E_UNSUPPORTED;
@@ -228,6 +261,8 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   b->stream = reinterpret_cast<hipStream_t>(hip_stream);
   b->ws = reinterpret_cast<char*>(dev_workspace);
   b->lay = L;
+  b->path = path;
+  for (int i = 0; i < B; ++i) b->max_cm = std::max(b->max_cm, class_cm(cls[i]));
   b->trunc_tol = b->mixed ? 5e-7 : 1e-12;
   if (opt) {
     if (opt->trunc_tol > 0) b->trunc_tol = opt->trunc_tol;
@@ -283,7 +318,8 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   if ((rc = hip_fail(hipHostMalloc(reinterpret_cast<void**>(&b->bundles_pin), sizeof(Bundle) * B, hipHostMallocDefault),
                      "pinned bundles")) != GMPS_OK)
     return fail(rc);
-  if ((rc = hip_fail(hipHostMalloc(reinterpret_cast<void**>(&b->queue_pin), sizeof(QueueState), hipHostMallocDefault),
+  if ((rc = hip_fail(hipHostMalloc(reinterpret_cast<void**>(&b->queue_pin), sizeof(QueueState) * kLaunchKinds,
+                                   hipHostMallocDefault),
                      "pinned queue")) != GMPS_OK)
     return fail(rc);
   if ((rc = hip_fail(hipEventCreateWithFlags(&b->staging_done, hipEventDisableTiming), "event")) != GMPS_OK)
@@ -305,7 +341,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   P.max_sweeps = b->max_sweeps;
   P.stoch_round = (b->mixed && b->stoch_round) ? 1 : 0;
   const bool warm_on = b->jacobi_warm > 0 || (b->jacobi_warm == 0 && b->mixed);
-  P.warm = warm_on ? reinterpret_cast<WarmRec*>(b->ws + L.warm) : nullptr;
+  P.warm = warm_on ? reinterpret_cast<void*>(b->ws + L.warm) : nullptr;
   *out = b;
   return GMPS_OK;
 }
@@ -313,8 +349,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
 int mps_init_uniform(gmps_batch* b) {
   if (!b) return GMPS_E_ARG;
   GMPS_HIP(launch_init(b->mixed, b->params.inst, b->B, reinterpret_cast<const int64_t*>(b->ws + b->lay.site_start),
-                       b->params.bonds, b->params.arena, b->lay.total_sites, reinterpret_cast<WarmRec*>(b->ws + b->lay.warm),
-                       b->stream));
+                       b->params.bonds, b->params.arena, b->lay.total_sites, b->ws + b->lay.warm, b->stream));
   std::fill(b->k_done_h.begin(), b->k_done_h.end(), 0);
   return GMPS_OK;
 }
@@ -323,8 +358,9 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
   if (!b || !k || (k_len != 1 && k_len != b->B)) return GMPS_E_ARG;
   for (int i = 0; i < k_len; ++i)
     if (k[i] < 0) return GMPS_E_ARG;
-  // Bundle instances that share (class, n, M, k), then order bundles by estimated cost,
-  // longest first, so the persistent queue hands out the long serial chains early.
+  // Bundle instances that share (class, n, M, k), then order each kernel's bundles by
+  // estimated cost, longest first, so the persistent queue hands out the long serial
+  // chains early.
   struct Key {
     int cls, n, M;
     int64_t k;
@@ -346,52 +382,116 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
     GMPS_HIP(hipEventSynchronize(b->staging_done));
     b->staging_pending = false;
   }
-  std::vector<std::pair<double, Bundle>> bundles;
-  int max_cls = 0;
+  std::vector<std::pair<double, Bundle>> bundles[kLaunchKinds];
+  size_t lds[kLaunchKinds] = {};
+  double work[kLaunchKinds] = {};
   for (auto& g : groups) {
-    const int per = 64 / kClasses[g.first.cls].G;
-    const double cm = kClasses[g.first.cls].CM;
-    const double cost = (double)g.first.k * (g.first.M + 1) * std::max(1, g.first.n - 1) * cm * cm * cm;
-    max_cls = std::max(max_cls, g.first.cls);
+    const int cls = g.first.cls;
+    const bool team = is_wide(cls);
+    const int kind = team ? 1 + (cls - kWideBase) : 0;
+    const int per = team ? team_per_bundle(cls) : 64 / kClasses[cls].G;
+    // a site step of either kernel takes roughly (CM + 1) times a fixed latency
+    const double cost = (double)g.first.k * (g.first.M + 1) * std::max(1, g.first.n - 1) * (class_cm(cls) + 1.0);
+    lds[kind] = std::max(lds[kind], team ? team_lds_bytes(b->mixed, cls) : group_lds_bytes(b->mixed, cls) * per);
     for (size_t s = 0; s < g.second.size(); s += per) {
       Bundle bd;
       std::memset(&bd, 0, sizeof(bd));
-      bd.cls = g.first.cls;
+      bd.cls = cls;
       bd.k = g.first.k;
       bd.count = (int)std::min<size_t>(per, g.second.size() - s);
       for (int t = 0; t < bd.count; ++t) bd.inst[t] = g.second[s + t];
-      bundles.push_back({cost, bd});
+      bundles[kind].push_back({cost, bd});
+      work[kind] += cost;
     }
   }
-  std::stable_sort(bundles.begin(), bundles.end(),
-                   [](const std::pair<double, Bundle>& a, const std::pair<double, Bundle>& c) { return a.first > c.first; });
-  const int nb = (int)bundles.size();
   for (int i = 0; i < b->B; ++i) b->k_done_h[i] += k[k_len == 1 ? 0 : i];
   b->timed = false;
-  if (nb == 0) return GMPS_OK;
-  size_t lds = 0;
-  for (auto& bp : bundles) {
-    const int cls = bp.second.cls;
-    lds = std::max(lds, group_lds_bytes(b->mixed, cls) * (64 / kClasses[cls].G));
+  int first[kLaunchKinds], count[kLaunchKinds], grid[kLaunchKinds];
+  int nb = 0;
+  for (int kd = 0; kd < kLaunchKinds; ++kd) {
+    std::stable_sort(bundles[kd].begin(), bundles[kd].end(),
+                     [](const std::pair<double, Bundle>& a, const std::pair<double, Bundle>& c) { return a.first > c.first; });
+    first[kd] = nb;
+    count[kd] = (int)bundles[kd].size();
+    for (auto& bp : bundles[kd]) b->bundles_pin[nb++] = bp.second;
+    b->queue_pin[kd].next = 0;
+    b->queue_pin[kd].nbundles = count[kd];
   }
-  for (int i = 0; i < nb; ++i) b->bundles_pin[i] = bundles[i].second;
-  b->queue_pin->next = 0;
-  b->queue_pin->nbundles = nb;
+  if (nb == 0) return GMPS_OK;
   GMPS_HIP(hipMemcpyAsync(b->ws + b->lay.bundles, b->bundles_pin, sizeof(Bundle) * nb, hipMemcpyHostToDevice,
                           b->stream));
-  GMPS_HIP(hipMemcpyAsync(b->ws + b->lay.queue, b->queue_pin, sizeof(QueueState), hipMemcpyHostToDevice, b->stream));
+  GMPS_HIP(hipMemcpyAsync(b->ws + b->lay.queue, b->queue_pin, sizeof(QueueState) * kLaunchKinds, hipMemcpyHostToDevice,
+                          b->stream));
   GMPS_HIP(hipEventRecord(b->staging_done, b->stream));
   b->staging_pending = true;
 
-  int per_cu = 0;
-  GMPS_HIP(iterate_occupancy(b->mixed, lds, &per_cu));
-  if (b->waves_per_cu > 0) per_cu = std::min(per_cu, b->waves_per_cu);
-  per_cu = std::max(per_cu, 1);
-  const int grid = std::min(nb, per_cu * b->num_cus);
+  // Persistent grids: each class kernel gets a workgroup per bundle up to what its occupancy
+  // allows; when the kernels together would need more of the device than there is, each
+  // keeps the share of it that its estimated work has, so that no class waits for another.
+  std::vector<int64_t> key;
+  int cap_wg[kLaunchKinds] = {};
+  double fill = 0.0, work_total = 0.0;
+  for (int kd = 0; kd < kLaunchKinds; ++kd) {
+    grid[kd] = 0;
+    if (count[kd] == 0) continue;
+    int per_cu = 0;
+    if (kd == 0) GMPS_HIP(group_occupancy(b->mixed, lds[kd], &per_cu));
+    else GMPS_HIP(team_occupancy(b->mixed, kWideBase + kd - 1, lds[kd], &per_cu));
+    if (b->waves_per_cu > 0) per_cu = std::min(per_cu, b->waves_per_cu);
+    per_cu = std::max(per_cu, 1);
+    cap_wg[kd] = per_cu * b->num_cus;
+    grid[kd] = std::min(count[kd], cap_wg[kd]);
+    fill += (double)grid[kd] / cap_wg[kd];
+    work_total += work[kd];
+  }
+  for (int kd = 0; kd < kLaunchKinds; ++kd) {
+    if (count[kd] == 0) continue;
+    if (fill > 1.0 && work_total > 0.0)
+      grid[kd] = std::max(1, std::min(grid[kd], (int)(cap_wg[kd] * work[kd] / work_total)));
+    key.insert(key.end(), {kd, grid[kd], (int64_t)lds[kd], first[kd]});
+  }
+  Bundle* dev_bundles = reinterpret_cast<Bundle*>(b->ws + b->lay.bundles);
+  QueueState* dev_queue = reinterpret_cast<QueueState*>(b->ws + b->lay.queue);
+  // the kernels of different classes run side by side: the first on st, the others on side
+  // streams forked from st after the queue reset and joined back into st
+  int nkinds = 0;
+  for (int kd = 0; kd < kLaunchKinds; ++kd) nkinds += grid[kd] > 0 ? 1 : 0;
+  if (nkinds > 1 && !b->fork_ev) {
+    GMPS_HIP(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+    for (int kd = 0; kd < kLaunchKinds; ++kd) {
+      GMPS_HIP(hipStreamCreateWithFlags(&b->side[kd], hipStreamNonBlocking));
+      GMPS_HIP(hipEventCreateWithFlags(&b->join_ev[kd], hipEventDisableTiming));
+    }
+  }
+  auto launch_all = [&](hipStream_t st) -> hipError_t {
+    hipError_t e = launch_queue_reset(dev_queue, st);
+    if (e == hipSuccess && nkinds > 1) e = hipEventRecord(b->fork_ev, st);
+    bool on_main = true;
+    for (int kd = 0; kd < kLaunchKinds && e == hipSuccess; ++kd) {
+      if (grid[kd] == 0) continue;
+      hipStream_t ks = st;
+      if (!on_main) {
+        ks = b->side[kd];
+        e = hipStreamWaitEvent(ks, b->fork_ev, 0);
+        if (e != hipSuccess) break;
+      }
+      IterParams P = b->params;
+      P.bundles = dev_bundles + first[kd];
+      P.queue = dev_queue + kd;
+      e = kd == 0 ? launch_group(b->mixed, P, grid[kd], lds[kd], ks)
+                  : launch_team(b->mixed, kWideBase + kd - 1, P, grid[kd], lds[kd], ks);
+      if (e == hipSuccess && !on_main) {
+        e = hipEventRecord(b->join_ev[kd], ks);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join_ev[kd], 0);
+      }
+      on_main = false;
+    }
+    return e;
+  };
 
   GMPS_HIP(hipEventRecord(b->ev_start, b->stream));
   if (b->use_graph) {
-    if (!b->graph || b->graph_grid != grid || b->graph_lds != lds) {
+    if (!b->graph || b->graph_key != key) {
       if (b->graph) {
         hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
@@ -400,7 +500,7 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
       GMPS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
       hipGraph_t g;
       GMPS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-      hipError_t le = launch_iterate(b->mixed, b->params, grid, lds, cap);
+      hipError_t le = launch_all(cap);
       hipError_t ce = hipStreamEndCapture(cap, &g);
       hipStreamDestroy(cap);
       GMPS_HIP(le);
@@ -408,12 +508,11 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
       hipError_t ie = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
       hipGraphDestroy(g);
       GMPS_HIP(ie);
-      b->graph_grid = grid;
-      b->graph_lds = lds;
+      b->graph_key = key;
     }
     GMPS_HIP(hipGraphLaunch(b->graph, b->stream));
   } else {
-    GMPS_HIP(launch_iterate(b->mixed, b->params, grid, lds, b->stream));
+    GMPS_HIP(launch_all(b->stream));
   }
   GMPS_HIP(hipEventRecord(b->ev_stop, b->stream));
   b->timed = true;
@@ -474,8 +573,8 @@ int sample_shots(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_
   unsigned long long* dhits = reinterpret_cast<unsigned long long*>(b->ws + b->lay.hits);
   GMPS_HIP(hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (b->B + 1), hipMemcpyHostToDevice, b->stream));
   GMPS_HIP(hipMemsetAsync(dhits, 0, sizeof(uint64_t) * b->B, b->stream));
-  GMPS_HIP(launch_sample(b->mixed, b->params.inst, b->params.marked, b->params.bonds, b->params.arena, b->B, doff,
-                         total, seed, dbits, dhits, b->stream));
+  GMPS_HIP(launch_sample(b->mixed, b->max_cm, b->params.inst, b->params.marked, b->params.bonds, b->params.arena,
+                         b->B, doff, total, seed, dbits, dhits, b->stream));
   if (out_bits && total > 0)
     GMPS_HIP(hipMemcpyAsync(out_bits, dbits, sizeof(uint64_t) * total, hipMemcpyDeviceToHost, b->stream));
   if (out_hits) GMPS_HIP(hipMemcpyAsync(out_hits, dhits, sizeof(int64_t) * b->B, hipMemcpyDeviceToHost, b->stream));
@@ -496,8 +595,8 @@ int gmps_amplitudes(gmps_batch* b, int32_t inst, const uint64_t* xs, int64_t cnt
   uint64_t* dxs = reinterpret_cast<uint64_t*>(st);
   double* dout = reinterpret_cast<double*>(st + align_up(sizeof(uint64_t) * cnt));
   GMPS_HIP(hipMemcpyAsync(dxs, xs, sizeof(uint64_t) * cnt, hipMemcpyHostToDevice, b->stream));
-  GMPS_HIP(launch_amplitudes(b->mixed, b->params.inst, inst, b->params.bonds, b->params.arena, dxs, cnt, dout,
-                             b->stream));
+  GMPS_HIP(launch_amplitudes(b->mixed, b->max_cm, b->params.inst, inst, b->params.bonds, b->params.arena, dxs, cnt,
+                             dout, b->stream));
   GMPS_HIP(hipMemcpyAsync(out_reim, dout, sizeof(double) * 2 * cnt, hipMemcpyDeviceToHost, b->stream));
   GMPS_HIP(hipStreamSynchronize(b->stream));
   return GMPS_OK;
@@ -535,6 +634,11 @@ int gmps_destroy(gmps_batch* b) {
   if (b->ev_start) hipEventDestroy(b->ev_start);
   if (b->ev_stop) hipEventDestroy(b->ev_stop);
   if (b->stage) hipFree(b->stage);
+  for (int kd = 0; kd < kLaunchKinds; ++kd) {
+    if (b->side[kd]) hipStreamDestroy(b->side[kd]);
+    if (b->join_ev[kd]) hipEventDestroy(b->join_ev[kd]);
+  }
+  if (b->fork_ev) hipEventDestroy(b->fork_ev);
   delete b;
   return GMPS_OK;
 }

@@ -1,4 +1,5 @@
-// HIP kernels of libgmps: iterative Grover search on matrix product states (gfx950).
+// Lane-group iterate kernel of libgmps: iterative Grover search on matrix product states
+// (gfx950), for bond caps up to 6.
 //
 // Layout. One wave (64 lanes) takes one bundle of instances from a persistent queue;
 // each instance owns a group of G consecutive lanes. Inside a group a tile is held row
@@ -20,159 +21,9 @@
 // float (mixed path: complex64 site tensors and contractions).
 #include <hip/hip_runtime.h>
 
-#include "../../include/gmps.h"
-#include "gmps_internal.h"
+#include "gmps_device.h"
 
 namespace gmps {
-
-// ----------------------------------------------------------------------------- complex
-template <class T>
-struct cx {
-  T re, im;
-};
-using cd = cx<double>;
-
-template <class T>
-__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
-template <class T>
-__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
-template <class T>
-__device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-template <class T>
-__device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
-template <class T>
-__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
-template <class T>
-__device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
-// acc + a * b
-template <class T>
-__device__ __forceinline__ cx<T> cfma(cx<T> acc, cx<T> a, cx<T> b) {
-  acc.re = fma(a.re, b.re, acc.re);
-  acc.re = fma(-a.im, b.im, acc.re);
-  acc.im = fma(a.re, b.im, acc.im);
-  acc.im = fma(a.im, b.re, acc.im);
-  return acc;
-}
-// conj(a) * b
-template <class T>
-__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
-  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
-}
-template <class S>
-__device__ __forceinline__ cx<S> down(cd a) { return {(S)a.re, (S)a.im}; }
-template <class S>
-__device__ __forceinline__ cd up(cx<S> a) { return {(double)a.re, (double)a.im}; }
-template <class S>
-__device__ __forceinline__ cx<S> czero() { return {(S)0, (S)0}; }
-
-// ---------------------------------------------------------------------- stochastic rounding
-// Unbiased (stochastic) rounding of a double to float: 29 random bits are added to the low
-// 29 bits of the magnitude, which a float does not keep, and those bits are then cut, so x
-// rounds up with probability equal to its distance from the lower neighbour over the gap
-// (E[round(x)] = x). The float conversion of the truncated value is exact. Random bits come
-// from the high bits of a 64-bit linear congruential stream (Knuth's MMIX constants).
-__device__ __forceinline__ uint32_t rng29(uint64_t& st) {
-  st = st * 6364136223846793005ull + 1442695040888963407ull;
-  return (uint32_t)(st >> 35);
-}
-__device__ __forceinline__ float sround_f32(double x, uint32_t r29) {
-  uint64_t b = (uint64_t)__double_as_longlong(x);
-  const uint64_t sign = b & 0x8000000000000000ull;
-  uint64_t mag = (b & 0x7FFFFFFFFFFFFFFFull) + (uint64_t)r29;
-  mag &= ~((1ull << 29) - 1ull);
-  return (float)__longlong_as_double((long long)(sign | mag));
-}
-// Conversion of an FP64 result to the storage type S.
-template <class S>
-__device__ __forceinline__ cx<S> store_cast(cd a, uint64_t& st, bool sr) {
-  if constexpr (sizeof(S) == sizeof(double)) {
-    return {(S)a.re, (S)a.im};
-  } else {
-    if (!sr) return {(S)a.re, (S)a.im};
-    const float re = sround_f32(a.re, rng29(st));
-    const float im = sround_f32(a.im, rng29(st));
-    return {re, im};
-  }
-}
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-// ------------------------------------------------------------------------ group collectives
-// Butterfly sums inside a lane group of G = 2, 4, 8, 16 or 32 lanes. Steps 1 and 2 swap
-// neighbours inside a quad (DPP quad_perm); once values are quad-uniform the half-row
-// mirror pairs the two quads of an 8-lane half, once they are half-row uniform the row
-// mirror pairs the two halves of a 16-lane row, and a swizzle swaps 16-lane halves of a
-// 32-lane group. Each step adds a value to its partner's, so every lane of the group ends
-// with the same bits (addition is commutative), and branches on the sums are uniform.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double swap16_f64(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_ds_swizzle(lo, 0x401F);  // bit-mask mode: xor lane id with 16
-  hi = __builtin_amdgcn_ds_swizzle(hi, 0x401F);
-  return __hiloint2double(hi, lo);
-}
-template <int G>
-__device__ __forceinline__ double gsum(double v) {
-  static_assert(G == 2 || G == 4 || G == 8 || G == 16 || G == 32, "group size");
-  v += dpp_f64<0xB1>(v);                   // quad_perm [1,0,3,2]
-  if (G > 2) v += dpp_f64<0x4E>(v);        // quad_perm [2,3,0,1]
-  if (G > 4) v += dpp_f64<0x141>(v);       // row_half_mirror
-  if (G > 8) v += dpp_f64<0x140>(v);       // row_mirror
-  if (G > 16) v += swap16_f64(v);
-  return v;
-}
-template <int G>
-__device__ __forceinline__ cd gsum(cd v) { return {gsum<G>(v.re), gsum<G>(v.im)}; }
-// value held by group lane src, delivered to every lane of the group
-template <int G>
-__device__ __forceinline__ cd gbcast(cd v, int gl, int src) {
-  return gsum<G>(gl == src ? v : cd{0.0, 0.0});
-}
-
-// Raw v_rsq_f64 / v_rcp_f64 are accurate to about 2^-23; two Newton steps bring them to
-// working precision, which keeps Householder reflectors and Jacobi rotations unitary.
-__device__ __forceinline__ double rsqrt_acc(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double r = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, r, y);
-  r = fma(-x * y, y, 1.0);
-  return fma(0.5 * y, r, y);
-}
-__device__ __forceinline__ double rcp_acc(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double r = fma(-x, y, 1.0);
-  y = fma(y, r, y);
-  r = fma(-x, y, 1.0);
-  return fma(y, r, y);
-}
-
-// Orders LDS traffic between the lanes of the (single-wave) workgroup without waiting
-// for outstanding global memory operations.
-__device__ __forceinline__ void lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// Round-robin (circle method) pairing of NC columns: round r pairs NC-1 with r and
-// (r+p) with (r-p) mod (NC-1); after NC-1 rounds every pair has met once.
-__host__ __device__ constexpr int circ_a(int NC, int r, int p) { return p == 0 ? NC - 1 : (r + p) % (NC - 1); }
-__host__ __device__ constexpr int circ_b(int NC, int r, int p) {
-  return p == 0 ? r : (r - p + (NC - 1)) % (NC - 1);
-}
-__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
-__host__ __device__ constexpr int cmax(int a, int b) { return a < b ? b : a; }
 
 // ------------------------------------------------------------------------------- QR
 // Householder QR of an m x c tile X held row per lane (row gl in x[], m <= G, c <= NC;
@@ -296,15 +147,6 @@ __device__ __forceinline__ int householder_qr_rank(cd (&x)[NC], cd (&q)[KMAX], i
   return kr;
 }
 
-// (x, y) <- (c x - conj(se) y, se x + c y) for real c and complex se = s e^{i phi}.
-__device__ __forceinline__ void rot2(cd& x, cd& y, double c, cd se) {
-  const cd x0 = x, y0 = y;
-  x.re = fma(c, x0.re, fma(-se.re, y0.re, -se.im * y0.im));
-  x.im = fma(c, x0.im, fma(-se.re, y0.im, se.im * y0.re));
-  y.re = fma(c, y0.re, fma(se.re, x0.re, -se.im * x0.im));
-  y.im = fma(c, y0.im, fma(se.re, x0.im, se.im * x0.re));
-}
-
 // ---------------------------------------------------------------------------- Jacobi SVD
 // One-sided (Hestenes) Jacobi on the first NC columns of a tile held row per lane in a[]
 // over a lane group of W lanes (rows beyond the tile are zero), accumulating V (NC x NC,
@@ -407,49 +249,11 @@ struct GroupLds {
   int32_t rdim[kBondStride];
 };
 
-template <class S>
-__device__ __forceinline__ cx<S> sel(cx<S> a0, cx<S> a1, int s) {
-  return {s ? a1.re : a0.re, s ? a1.im : a0.im};
-}
-
-// (P A)[s] for P = |xb><xb| (oracle) or |+><+| (diffusion), given A[0] = a0, A[1] = a1.
-template <class S>
-__device__ __forceinline__ cx<S> proj_apply(cx<S> a0, cx<S> a1, int s, bool diff, int xb) {
-  if (diff) {
-    const S h = (S)0.5;
-    return {h * (a0.re + a1.re), h * (a0.im + a1.im)};
-  }
-  return s == xb ? sel(a0, a1, xb) : czero<S>();
-}
-
-constexpr double kJacobiTol2 = 1e-30;  // (relative off-diagonal 1e-15)^2
-
 // ----------------------------------------------------------------------- prefetched loads
 // Site tensors are read one site ahead of their use: the loads for site i+1 (QR sweep) or
 // i-1 (SVD sweep) are issued into registers while site i is being factorised, so the
 // global-memory latency overlaps the arithmetic. The slot being prefetched is never written
 // by the current step.
-template <class S, int CM, int G>
-struct APrefetch {
-  static constexpr int NE = (CM * 2 * CM + G - 1) / G;
-  cx<S> v[NE];
-  __device__ __forceinline__ void load(const cx<S>* slot, int gl, int chl, int chr) {
-    constexpr int D = 2 * CM;
-#pragma unroll
-    for (int t = 0; t < NE; ++t) {
-      const int e = gl + t * G;
-      const int a = e / (2 * CM), s = (e / CM) & 1, b = e % CM;
-      v[t] = (e < CM * 2 * CM && a < chl && b < chr) ? slot[a * 2 * D + s * D + b] : czero<S>();
-    }
-  }
-  __device__ __forceinline__ void stage(cx<S>* lds_a, int gl) const {
-#pragma unroll
-    for (int t = 0; t < NE; ++t) {
-      const int e = gl + t * G;
-      if (e < CM * 2 * CM) lds_a[e] = v[t];
-    }
-  }
-};
 
 template <class S, int CM, int KQ>
 struct QPrefetch {
@@ -483,7 +287,7 @@ struct WPrefetch {
 
 // ------------------------------------------------------------------------------ one bundle
 template <class S, int CM, int G, int WS>
-__device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base) {
+__device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_base) {
   constexpr int D = 2 * CM;
   constexpr int SLOT = slot_elems(CM);
   constexpr bool kMixed = sizeof(S) == sizeof(float);
@@ -494,20 +298,21 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
   const int lane = threadIdx.x;
   const int grp = lane / G;
   const int gl = lane % G;
-  const bool real = grp < bd.count;
-  const int me = bd.inst[real ? grp : 0];
+  const bool real = grp < bdp->count;
+  // inst[] is indexed per lane: read it from memory, not from a register copy
+  const int me = bdp->inst[real ? grp : 0];
   GroupLds<S, CM>& L = reinterpret_cast<GroupLds<S, CM>*>(lds_base)[grp];
   InstDev* I = P.inst + me;
   const int n = I->n;
   const int M = I->M;
   const int cap = I->cap < CM ? I->cap : CM;
-  const int64_t k = bd.k;
+  const int64_t k = bdp->k;
   cx<S>* arena = reinterpret_cast<cx<S>*>(P.arena) + I->site_off;
   const uint64_t* W = P.marked + I->marked_off;
   const double tol2 = P.trunc_tol * P.trunc_tol;
   const double rank2 = P.rank_tol * P.rank_tol;
   const bool sr = P.stoch_round != 0;
-  WarmRec* warm = P.warm ? P.warm + I->warm_off : nullptr;
+  WarmRec* warm = P.warm ? reinterpret_cast<WarmRec*>(reinterpret_cast<char*>(P.warm) + I->warm_off) : nullptr;
   uint64_t rs_state = mix64(((uint64_t)me << 32) ^ ((uint64_t)I->k_done * 0x9E3779B97F4A7C15ull) ^ (uint64_t)gl);
 
   for (int l = gl; l < kBondStride; l += G) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
@@ -903,15 +708,15 @@ __device__ void run_bundle(const IterParams& P, const Bundle& bd, char* lds_base
 }
 
 template <class S>
-__global__ __launch_bounds__(64) void grover_kernel(IterParams P) {
+__global__ __launch_bounds__(64) void grover_group_kernel(IterParams P) {
   extern __shared__ __align__(16) char lds[];
   for (;;) {
     unsigned int bi = 0;
     if (threadIdx.x == 0) bi = atomicAdd(&P.queue->next, 1u);
     bi = __shfl(bi, 0);
     if ((int)bi >= P.queue->nbundles) break;
-    const Bundle bd = P.bundles[bi];
-    switch (bd.cls) {
+    const Bundle* bd = P.bundles + bi;
+    switch (bd->cls) {
       case 0: run_bundle<S, 2, 8, 4>(P, bd, lds); break;
       case 1: run_bundle<S, 3, 8, 8>(P, bd, lds); break;
       case 2: run_bundle<S, 4, 16, 8>(P, bd, lds); break;
@@ -922,224 +727,18 @@ __global__ __launch_bounds__(64) void grover_kernel(IterParams P) {
   }
 }
 
-__global__ void queue_reset_kernel(QueueState* q) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) q->next = 0u;
-}
-
-// a2: every instance <- |+>^n with all bonds 1.
-template <class S>
-__global__ void init_uniform_kernel(InstDev* inst, int B, const int64_t* site_start, int32_t* bonds,
-                                    void* arena_v, int64_t total_sites, WarmRec* warm) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total_sites) return;
-  // locate the instance owning global site t (site_start is the prefix sum of n)
-  int lo = 0, hi = B;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (site_start[mid] <= t) lo = mid; else hi = mid;
-  }
-  InstDev& I = inst[lo];
-  const int i = (int)(t - site_start[lo]);
-  const int CM = kClasses[I.cls].CM;
-  const int D = 2 * CM;
-  cx<S>* slot = reinterpret_cast<cx<S>*>(arena_v) + I.site_off + (int64_t)i * slot_elems(CM);
-  const S h = (S)0.70710678118654752440;
-  slot[0] = {h, (S)0};
-  slot[D] = {h, (S)0};
-  bonds[(int64_t)lo * kBondStride + i] = 1;
-  if (i == I.n - 1) bonds[(int64_t)lo * kBondStride + I.n] = 1;
-  if (warm)
-    for (int j = 0; j <= I.M; ++j) warm[I.warm_off + (int64_t)j * I.n + i].r = 0;
-  if (i == 0) {
-    I.k_done = 0;
-    I.status = 0;
-    I.drift = 0.0;
-    I.trunc_w = 0.0;
-    I.flops64 = 0.0;
-    I.flops32 = 0.0;
-  }
-}
-
-// -------------------------------------------------------------------------- read-out kernels
-constexpr int kMaxChi = 8;
-
-template <class S>
-__device__ cd amplitude_of(const InstDev& I, const int32_t* bond, const cx<S>* base, uint64_t x) {
-  const int CM = kClasses[I.cls].CM;
-  const int D = 2 * CM;
-  const int n = I.n;
-  cd v[kMaxChi];
-  v[0] = {1.0, 0.0};
-  int chl = 1;
-  for (int i = 0; i < n; ++i) {
-    const int chr = bond[i + 1];
-    const int s = (int)((x >> (n - 1 - i)) & 1ull);
-    const cx<S>* slot = base + (int64_t)i * slot_elems(CM);
-    cd w[kMaxChi];
-    for (int b = 0; b < chr; ++b) {
-      cd acc = {0.0, 0.0};
-      for (int a = 0; a < chl; ++a) acc = cfma(acc, v[a], up(slot[a * 2 * D + s * D + b]));
-      w[b] = acc;
-    }
-    for (int b = 0; b < chr; ++b) v[b] = w[b];
-    chl = chr;
-  }
-  return v[0];
-}
-
-template <class S>
-__device__ double norm2_of(const InstDev& I, const int32_t* bond, const cx<S>* base) {
-  // <psi|psi> by left transfer matrices E <- sum_s A_s^dagger E A_s
-  const int CM = kClasses[I.cls].CM;
-  const int D = 2 * CM;
-  cd E[kMaxChi][kMaxChi], T[kMaxChi][kMaxChi];
-  E[0][0] = {1.0, 0.0};
-  int chl = 1;
-  for (int i = 0; i < I.n; ++i) {
-    const int chr = bond[i + 1];
-    const cx<S>* slot = base + (int64_t)i * slot_elems(CM);
-    for (int b = 0; b < chr; ++b)
-      for (int bb = 0; bb < chr; ++bb) {
-        cd acc = {0.0, 0.0};
-        for (int s = 0; s < 2; ++s)
-          for (int a = 0; a < chl; ++a) {
-            cd ea = {0.0, 0.0};
-            for (int aa = 0; aa < chl; ++aa) ea = cfma(ea, E[a][aa], up(slot[aa * 2 * D + s * D + bb]));
-            acc = acc + cmulc(up(slot[a * 2 * D + s * D + b]), ea);
-          }
-        T[b][bb] = acc;
-      }
-    for (int b = 0; b < chr; ++b)
-      for (int bb = 0; bb < chr; ++bb) E[b][bb] = T[b][bb];
-    chl = chr;
-  }
-  return E[0][0].re;
-}
-
-template <class S>
-__global__ void marked_prob_kernel(InstDev* inst, const uint64_t* marked, const int32_t* bonds,
-                                   const void* arena_v, int B, double* out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  InstDev& I = inst[b];
-  const cx<S>* base = reinterpret_cast<const cx<S>*>(arena_v) + I.site_off;
-  const int32_t* bond = bonds + (int64_t)b * kBondStride;
-  const double nn = norm2_of<S>(I, bond, base);
-  double acc = 0.0;
-  for (int j = 0; j < I.M; ++j) acc += norm2(amplitude_of<S>(I, bond, base, marked[I.marked_off + j]));
-  const double p = acc / nn;
-  if (!isfinite(p)) I.status |= GMPS_ST_NAN;
-  out[b] = p;
-}
-
-template <class S>
-__global__ void amplitude_kernel(const InstDev* inst, int which, const int32_t* bonds, const void* arena_v,
-                                 const uint64_t* xs, int64_t cnt, double* out) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cnt) return;
-  const InstDev& I = inst[which];
-  const cx<S>* base = reinterpret_cast<const cx<S>*>(arena_v) + I.site_off;
-  const cd a = amplitude_of<S>(I, bonds + (int64_t)which * kBondStride, base, xs[t]);
-  out[2 * t] = a.re;
-  out[2 * t + 1] = a.im;
-}
-
-// Philox4x64-10 (Salmon et al., SC'11).
-__device__ __forceinline__ void philox4x64_10(uint64_t (&c)[4], uint64_t k0, uint64_t k1) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += W0;
-    k1 += W1;
-  }
-}
-
-template <class S>
-__global__ void sample_kernel(const InstDev* inst, const uint64_t* marked, const int32_t* bonds,
-                              const void* arena_v, int B, const int64_t* shot_off, uint64_t seed,
-                              uint64_t* bits, unsigned long long* hits) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= shot_off[B]) return;
-  int lo = 0, hi = B;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (shot_off[mid] <= t) lo = mid; else hi = mid;
-  }
-  while (lo + 1 < B && shot_off[lo + 1] <= t) ++lo;  // skip instances with zero shots
-  const InstDev& I = inst[lo];
-  const int64_t shot = t - shot_off[lo];
-  const int CM = kClasses[I.cls].CM;
-  const int D = 2 * CM;
-  const int n = I.n;
-  const cx<S>* base = reinterpret_cast<const cx<S>*>(arena_v) + I.site_off;
-  const int32_t* bond = bonds + (int64_t)lo * kBondStride;
-  cd v[kMaxChi];
-  v[0] = {1.0, 0.0};
-  int chl = 1;
-  uint64_t x = 0;
-  uint64_t words[4] = {0, 0, 0, 0};
-  for (int i = 0; i < n; ++i) {
-    if ((i & 3) == 0) {
-      words[0] = (uint64_t)shot;
-      words[1] = (uint64_t)(i >> 2);
-      words[2] = 0;
-      words[3] = 0;
-      philox4x64_10(words, seed, (uint64_t)lo);
-    }
-    const double u = (double)(words[i & 3] >> 11) * (1.0 / 9007199254740992.0);
-    const int chr = bond[i + 1];
-    const cx<S>* slot = base + (int64_t)i * slot_elems(CM);
-    cd w0[kMaxChi], w1[kMaxChi];
-    double q0 = 0.0, q1 = 0.0;
-    for (int b = 0; b < chr; ++b) {
-      cd a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
-      for (int a = 0; a < chl; ++a) {
-        a0 = cfma(a0, v[a], up(slot[a * 2 * D + b]));
-        a1 = cfma(a1, v[a], up(slot[a * 2 * D + D + b]));
-      }
-      w0[b] = a0;
-      w1[b] = a1;
-      q0 += norm2(a0);
-      q1 += norm2(a1);
-    }
-    const double p0 = q0 / (q0 + q1);
-    const bool zero = u < p0;
-    const double sc = 1.0 / sqrt(zero ? q0 : q1);
-    for (int b = 0; b < chr; ++b) v[b] = sc * (zero ? w0[b] : w1[b]);
-    if (!zero) x |= 1ull << (n - 1 - i);
-    chl = chr;
-  }
-  bits[t] = x;
-  for (int j = 0; j < I.M; ++j)
-    if (marked[I.marked_off + j] == x) {
-      atomicAdd(hits + lo, 1ull);
-      break;
-    }
-}
-
 // ------------------------------------------------------------------------- launch wrappers
-template <class S>
-static hipError_t launch_iterate_t(const IterParams& P, int grid, size_t lds, hipStream_t st) {
-  queue_reset_kernel<<<1, 64, 0, st>>>(P.queue);
-  grover_kernel<S><<<grid, 64, lds, st>>>(P);
+hipError_t launch_group(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st) {
+  if (mixed)
+    grover_group_kernel<float><<<grid, 64, lds, st>>>(P);
+  else
+    grover_group_kernel<double><<<grid, 64, lds, st>>>(P);
   return hipGetLastError();
 }
 
-hipError_t launch_iterate(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st) {
-  return mixed ? launch_iterate_t<float>(P, grid, lds, st) : launch_iterate_t<double>(P, grid, lds, st);
-}
-
-hipError_t iterate_occupancy(bool mixed, size_t lds, int* blocks_per_cu) {
-  return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_kernel<float>, 64, lds)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_kernel<double>, 64, lds);
+hipError_t group_occupancy(bool mixed, size_t lds, int* blocks_per_cu) {
+  return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_group_kernel<float>, 64, lds)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_group_kernel<double>, 64, lds);
 }
 
 size_t group_lds_bytes(bool mixed, int cls) {
@@ -1151,54 +750,6 @@ size_t group_lds_bytes(bool mixed, int cls) {
     case 4: return mixed ? sizeof(GroupLds<float, 6>) : sizeof(GroupLds<double, 6>);
   }
   return 0;
-}
-
-hipError_t launch_init(bool mixed, InstDev* inst, int B, const int64_t* site_start, int32_t* bonds, void* arena,
-                       int64_t total_sites, WarmRec* warm, hipStream_t st) {
-  const int blk = 256;
-  const int grid = (int)((total_sites + blk - 1) / blk);
-  if (grid == 0) return hipSuccess;
-  if (mixed)
-    init_uniform_kernel<float><<<grid, blk, 0, st>>>(inst, B, site_start, bonds, arena, total_sites, warm);
-  else
-    init_uniform_kernel<double><<<grid, blk, 0, st>>>(inst, B, site_start, bonds, arena, total_sites, warm);
-  return hipGetLastError();
-}
-
-hipError_t launch_prob(bool mixed, InstDev* inst, const uint64_t* marked, const int32_t* bonds, const void* arena,
-                       int B, double* out, hipStream_t st) {
-  const int blk = 64;
-  const int grid = (B + blk - 1) / blk;
-  if (mixed)
-    marked_prob_kernel<float><<<grid, blk, 0, st>>>(inst, marked, bonds, arena, B, out);
-  else
-    marked_prob_kernel<double><<<grid, blk, 0, st>>>(inst, marked, bonds, arena, B, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_amplitudes(bool mixed, const InstDev* inst, int which, const int32_t* bonds, const void* arena,
-                             const uint64_t* xs, int64_t cnt, double* out, hipStream_t st) {
-  const int blk = 64;
-  const int grid = (int)((cnt + blk - 1) / blk);
-  if (grid == 0) return hipSuccess;
-  if (mixed)
-    amplitude_kernel<float><<<grid, blk, 0, st>>>(inst, which, bonds, arena, xs, cnt, out);
-  else
-    amplitude_kernel<double><<<grid, blk, 0, st>>>(inst, which, bonds, arena, xs, cnt, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_sample(bool mixed, const InstDev* inst, const uint64_t* marked, const int32_t* bonds,
-                         const void* arena, int B, const int64_t* shot_off, int64_t total, uint64_t seed,
-                         uint64_t* bits, unsigned long long* hits, hipStream_t st) {
-  const int blk = 64;
-  const int grid = (int)((total + blk - 1) / blk);
-  if (grid == 0) return hipSuccess;
-  if (mixed)
-    sample_kernel<float><<<grid, blk, 0, st>>>(inst, marked, bonds, arena, B, shot_off, seed, bits, hits);
-  else
-    sample_kernel<double><<<grid, blk, 0, st>>>(inst, marked, bonds, arena, B, shot_off, seed, bits, hits);
-  return hipGetLastError();
 }
 
 }  // namespace gmps

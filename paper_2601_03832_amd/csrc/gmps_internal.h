@@ -14,7 +14,7 @@ struct InstDev {
   double drift;            // largest |norm - 1| before a renormalisation
   double trunc_w;          // largest dropped-weight fraction of one truncation
   double flops64, flops32; // algorithmic flops spent so far
-  int64_t warm_off;        // first warm-start record of this instance (see WarmRec)
+  int64_t warm_off;        // byte offset of this instance's first warm-start record
 };
 
 // The Jacobi SVD at (reflection j, site i) starts from the unitary it produced at the same
@@ -49,6 +49,26 @@ constexpr int kNumClasses = 5;
 constexpr ClassCfg kClasses[kNumClasses] = {{2, 8, 4}, {3, 8, 8}, {4, 16, 8}, {5, 16, 16}, {6, 16, 16}};
 constexpr int kBondStride = 64;  // bonds[i * 64 + l], l = 0..n
 
+// Team classes: one instance per team of TW threads (several teams share a 64-lane wave
+// when TW < 64; a team of TW > 64 spans TW/64 waves of one workgroup). Inside a team the
+// tile columns sit on column slots and the rows of a column are spread over the lanes of
+// its slot, so column sums are short butterflies and all columns are updated at once.
+struct WideCfg {
+  int CM, TW;
+};
+constexpr int kWideBase = 8;  // class ids kWideBase + w select kWide[w]
+constexpr int kNumWide = 6;
+constexpr WideCfg kWide[kNumWide] = {{2, 16}, {3, 32}, {5, 64}, {8, 64}, {17, 192}, {32, 256}};
+__host__ __device__ constexpr bool is_wide(int cls) { return cls >= kWideBase; }
+__host__ __device__ constexpr int class_cm(int cls) {
+  return cls >= kWideBase ? kWide[cls - kWideBase].CM : kClasses[cls].CM;
+}
+// Jacobi columns of a class (the QR rank bound CM+1, rounded up to even).
+__host__ __device__ constexpr int class_kj(int CM) { return ((CM + 1) + 1) & ~1; }
+// Doubles of one team-class warm-start record: r (as a double), a pad double, then the
+// KJ x KJ complex unitary, row-major.
+__host__ __device__ constexpr int64_t wide_warm_doubles(int CM) { return 2 + 2 * (int64_t)class_kj(CM) * class_kj(CM); }
+
 // Elements of one site slot: (D, 2, D) with row stride 2*D and physical stride D.
 __host__ __device__ constexpr int slot_elems(int CM) { return (2 * CM) * 2 * (2 * CM); }
 
@@ -69,7 +89,7 @@ struct IterParams {
   double rank_tol;   // relative trailing norm at which the QR sweep stops (numerical rank)
   int32_t max_sweeps;
   int32_t stoch_round;  // mixed path: stochastic rounding of FP64 results stored as complex64
-  WarmRec* warm;        // warm-start records (null: every Jacobi starts from the identity)
+  void* warm;           // warm-start records (null: every Jacobi starts from the identity)
 };
 
 }  // namespace gmps

@@ -1,0 +1,1095 @@
+// Team iterate kernel of libgmps, device part: iterative Grover search on matrix product
+// states (gfx950). Instantiated by gmps_team64.hip, gmps_team192.hip and gmps_team256.hip.
+//
+// One instance per team of TW threads. Teams of 16 or 32 threads share a 64-lane wave
+// (a bundle of instances with the same n, M and k), a team of 192 or 256 threads spans
+// the waves of one workgroup. Where the lane-group kernel keeps one tile row per lane and
+// loops over columns, a team keeps the tile columns side by side:
+//   QR layout      lane = PQ * slot + part (PQ = 4): slot c holds column c of the QR tile,
+//                  its rows part, part + PQ, ... in registers (RQ of them).
+//   Jacobi layout  lane = PJ * slot + part: slot c holds column c of M^H and column c of the
+//                  accumulated unitary, rows strided by PJ.
+// A column sum is then a butterfly over the PQ (PJ) lanes of a slot, and every column of a
+// Householder update or a Jacobi round is processed at the same time. What one slot has to
+// tell the others (a Householder vector, a Jacobi partner column, column norms for pivots
+// and truncation) goes through LDS between barriers; all lanes of a team read the same LDS
+// values and make the same team-wide decisions.
+//
+// The method is the one of the lane-group kernel (Section III-B): each reflection
+// c0*I + c1*(P_0 x ... x P_{n-1}) is applied as a bond-2 MPO fused into a QR
+// left-canonicalisation sweep, followed by a truncated-SVD sweep (one-sided Jacobi on
+// M^H) and the renormalisation of site 0 after the diffusion. QR, SVD and norms are FP64;
+// S (double or float) is the storage and contraction type.
+#pragma once
+#include "gmps_device.h"
+
+namespace gmps {
+
+template <int CM, int TW>
+struct TeamShape {
+  static constexpr int D = 2 * CM;                 // largest bond after a bond-2 MPO
+  static constexpr int KQ = CM + 1;                // rank bound of a QR tile
+  static constexpr int KJ = class_kj(CM);          // Jacobi columns (even)
+  static constexpr int PQ = 4;                     // lanes per column slot, QR layout
+  static constexpr int SQ = TW / PQ;               // column slots, QR layout
+  static constexpr int RQ = (2 * KQ + PQ - 1) / PQ;
+  static constexpr int PJ = (KJ * 16 <= TW) ? 16 : (KJ * 8 <= TW) ? 8 : (KJ * 4 <= TW) ? 4 : 2;
+  static constexpr int RJ = (D + PJ - 1) / PJ;     // rows of M^H per lane
+  static constexpr int RU = (KJ + PJ - 1) / PJ;    // rows of the Jacobi unitary per lane
+  static constexpr int NT = TW < 64 ? 64 : TW;     // threads of the workgroup
+  static constexpr int NBUF = CM >= 24 ? 1 : 2;    // Jacobi exchange buffers (LDS budget)
+  static constexpr int TEAMS = NT / TW;
+  static_assert(SQ >= D, "a QR tile column per slot");
+  static_assert(KJ * PJ <= TW, "a Jacobi column per slot");
+  static_assert(TW % 64 == 0 || 64 % TW == 0, "teams tile the workgroup");
+  static_assert(PJ * RU >= KJ, "the warm start's Gram matrix fits the exchange buffer");
+};
+
+template <class S, int CM, int TW>
+struct TeamLds {
+  using T = TeamShape<CM, TW>;
+  union {
+    struct {                                  // QR sweep
+      cx<S> A[CM][2][CM];                     // staged site tensor
+      cd R[T::KQ][T::D];                      // R of the previous step, original column order
+      cd V[T::KQ][T::PQ * T::RQ];             // Householder vectors of this step
+      double tau[T::KQ];
+    } q;
+    struct {                                  // SVD sweep
+      cx<S> Q[T::KQ][2][T::KQ];               // staged left-orthonormal site tensor
+      cd Y[T::KQ][CM];                        // U Sigma of the previous step
+      cd XA[T::NBUF][T::KJ][T::PJ * T::RJ];   // Jacobi partner exchange
+      cd XU[T::NBUF][T::KJ][T::PJ * T::RU];   // (its first buffer also holds the Gram matrix
+      double XN[T::NBUF][T::KJ];              //  of the warm start, before the Jacobi runs)
+      cd W[T::KJ][T::KJ];                     // warm-start unitary
+    } s;
+  } u;
+  double colv[TW];  // per-slot values (norms, singular values)
+  double colf[TW];  // per-slot flags
+  int32_t colr[TW];
+  int32_t bond[kBondStride];
+  int32_t rdim[kBondStride];
+};
+
+// Orders LDS and global-memory traffic of the workgroup: global stores of one wave are
+// complete and visible to the others after it (site tensors written in one sweep are read
+// by other waves in the next).
+__device__ __forceinline__ void team_sync_global() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// ------------------------------------------------------------------ wave collectives
+// A team that fits one wave (TW <= 64) exchanges values between its lanes without LDS
+// round trips or barriers: butterflies over DPP / swizzle for sums and maxima (every lane
+// ends with the same bits), ds_bpermute for reading another lane's register, and ballots.
+__device__ __forceinline__ double shfl_f64(double v, int src_lane) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, lo);
+  hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, hi);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ cd shfl_cd(cd v, int src_lane) { return {shfl_f64(v.re, src_lane), shfl_f64(v.im, src_lane)}; }
+
+template <int G>
+__device__ __forceinline__ double gmax(double v) {
+  static_assert(G == 2 || G == 4 || G == 8 || G == 16 || G == 32, "group size");
+  v = fmax(v, dpp_f64<0xB1>(v));
+  if (G > 2) v = fmax(v, dpp_f64<0x4E>(v));
+  if (G > 4) v = fmax(v, dpp_f64<0x141>(v));
+  if (G > 8) v = fmax(v, dpp_f64<0x140>(v));
+  if (G > 16) v = fmax(v, swap16_f64(v));
+  return v;
+}
+// sum / maximum over the TW lanes of a team (TW <= 64, teams aligned to TW lanes)
+template <int TW>
+__device__ __forceinline__ double tsum(double v) {
+  if constexpr (TW <= 32) {
+    return gsum<TW>(v);
+  } else {
+    v = gsum<32>(v);
+    return v + shfl_f64(v, __lane_id() ^ 32);
+  }
+}
+template <int TW>
+__device__ __forceinline__ double tmax(double v) {
+  if constexpr (TW <= 32) {
+    return gmax<TW>(v);
+  } else {
+    v = gmax<32>(v);
+    return fmax(v, shfl_f64(v, __lane_id() ^ 32));
+  }
+}
+// lanes of the team (first lane base) for which pred holds, as a wave lane mask
+template <int TW>
+__device__ __forceinline__ uint64_t tballot(bool pred, int base) {
+  const uint64_t all = __ballot(pred);
+  if constexpr (TW >= 64) return all;
+  else return all & (((1ull << TW) - 1ull) << base);
+}
+
+// Jacobi rotation of the pair (i, j) with gamma = a_i^H a_j, |a_i|^2 = ni, |a_j|^2 = nj:
+// with h = (nj - ni)/2 the rotation tangent is t = sign(h) |gamma| / (|h| + sqrt(h^2 + |gamma|^2)),
+// the smaller root of the usual quadratic. Writing t = |gamma| r, the cosine 1/sqrt(1 + t^2) and
+// s e^{i phi} = c r gamma involve no 1/|gamma|, and c^2 + |s|^2 = 1 to rounding however
+// accurate r is (r only sets the angle), so r comes from the hardware estimates and one
+// Newton step while c is refined to working precision. tg = t |gamma| is the squared norm
+// the pair exchanges.
+__device__ __forceinline__ void jacobi_rotation(cd g, double g2, double ni, double nj, double* cs, cd* se, double* tg) {
+  const double h = 0.5 * (nj - ni);
+  const double q2 = fma(h, h, g2);
+  const double den = fabs(h) + q2 * __builtin_amdgcn_rsq(q2);
+  double rr = __builtin_amdgcn_rcp(den);
+  rr = fma(rr, fma(-den, rr, 1.0), rr);
+  rr = copysign(rr, h);
+  const double c = rsqrt_acc(fma(g2 * rr, rr, 1.0));
+  *cs = c;
+  *se = {c * rr * g.re, c * rr * g.im};
+  *tg = g2 * rr;
+}
+
+// ----------------------------------------------------------------------- prefetched loads
+// The Q_i tile (r_i, 2, r_{i+1}) of the SVD sweep, loaded by the team one site ahead.
+template <class S, int KQ, int CM, int TW>
+struct TeamQPre {
+  static constexpr int NE = (KQ * 2 * KQ + TW - 1) / TW;
+  cx<S> v[NE];
+  __device__ __forceinline__ void load(const cx<S>* slot, int tl, int ri, int rn) {
+    constexpr int D = 2 * CM;
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tl + t * TW;
+      const int a = e / (2 * KQ), s = (e / KQ) & 1, b = e % KQ;
+      v[t] = (e < KQ * 2 * KQ && a < ri && b < rn) ? slot[a * 2 * D + s * D + b] : czero<S>();
+    }
+  }
+  __device__ __forceinline__ void stage(cx<S>* lds_q, int tl) const {
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tl + t * TW;
+      if (e < KQ * 2 * KQ) lds_q[e] = v[t];
+    }
+  }
+};
+
+// A warm-start record: r (as a double), a pad double, then the KJ x KJ unitary.
+template <int KJ, int TW>
+struct TeamWPre {
+  static constexpr int NE = (KJ * KJ + TW - 1) / TW;
+  cd v[NE];
+  int r;
+  __device__ __forceinline__ void load(const double* w, int tl, int ncj) {
+    r = w ? (int)w[0] : 0;
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tl + t * TW;
+      const int ra = e / KJ, ca = e % KJ;
+      v[t] = (w && e < KJ * KJ && ra < ncj && ca < ncj) ? cd{w[2 + 2 * e], w[3 + 2 * e]} : cd{0.0, 0.0};
+    }
+  }
+  __device__ __forceinline__ void stage(cd* lds_w, int tl) const {
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tl + t * TW;
+      if (e < KJ * KJ) lds_w[e] = v[t];
+    }
+  }
+};
+
+// ------------------------------------------------------------------------------- QR
+// Householder QR of the m x c tile X in the QR layout (x[e] = X[part + PQ*e][slot], zero
+// outside the tile), with the rank stop and the projector-block pivoting of the lane-group
+// kernel: columns below npiv (the A block, full rank) are eliminated in their own order;
+// from step npiv on, the remaining column with the largest residual norm is taken, and
+// the factorisation ends when that norm falls to rank2 * ||X||^2 or after min(m, c, KQ)
+// steps. Columns never move: when it returns, x[] of every slot holds its column of R
+// (rows below the rank k, original column order) and q[] of slots < k holds that column
+// of the thin Q, so X = Q R + E with ||E||^2 = *dropped * ||X||^2. Returns k.
+template <int PQ, int RQ, int KQ>
+__device__ __forceinline__ int team_qr_lds(cd (&x)[RQ], cd (&q)[RQ], int qc, int qh, int m, int c, int npiv,
+                                       double rank2, double* dropped, cd (*V)[PQ * RQ], double* tau,
+                                       double* colv) {
+  const bool colok = qc < c;
+  double p0 = 0.0;
+#pragma unroll
+  for (int e = 0; e < RQ; ++e) p0 += norm2(x[e]);
+  p0 = gsum<PQ>(p0);
+  if (qh == 0) colv[qc] = colok ? p0 : 0.0;
+  lds_sync();
+  double t0 = 0.0;
+  for (int k = 0; k < c; ++k) t0 += colv[k];
+  const int kmax = min(min(m, c), KQ);
+  int kr = kmax;
+  bool used = false;
+  lds_sync();
+  for (int j = 0; j < kmax; ++j) {
+    int p = j;
+    if (j >= npiv) {
+      double rn = 0.0;
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) rn += (qh + PQ * e >= j) ? norm2(x[e]) : 0.0;
+      rn = gsum<PQ>(rn);
+      if (qh == 0) colv[qc] = (colok && !used) ? rn : -1.0;
+      lds_sync();
+      double best = -1.0;
+      for (int k = 0; k < c; ++k) {
+        const double v = colv[k];
+        if (v > best) {
+          best = v;
+          p = k;
+        }
+      }
+      if (best <= rank2 * t0) {
+        kr = j;
+        break;
+      }
+    }
+    const bool piv = qc == p;
+    cd xj = {0.0, 0.0};
+    double sub = 0.0;
+#pragma unroll
+    for (int e = 0; e < RQ; ++e) {
+      const int row = qh + PQ * e;
+      if (row == j) xj = x[e];
+      sub += (row > j && row < m) ? norm2(x[e]) : 0.0;
+    }
+    const cd alpha = gsum<PQ>(xj);
+    sub = gsum<PQ>(sub);
+    const double a2 = norm2(alpha);
+    const bool refl = sub > 0.0;
+    const double ra = a2 > 0.0 ? rsqrt_acc(a2) : 0.0;
+    const double aa = a2 * ra;                          // |alpha|
+    const double n2 = a2 + sub;
+    const double nrm = refl ? n2 * rsqrt_acc(n2) : aa;  // norm of the column from row j down
+    const cd ph = a2 > 0.0 ? cd{alpha.re * ra, alpha.im * ra} : cd{1.0, 0.0};
+    const cd beta = {-ph.re * nrm, -ph.im * nrm};
+    const double t = refl ? rcp_acc(nrm * (nrm + aa)) : 0.0;
+    if (piv) {
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) {
+        const int row = qh + PQ * e;
+        V[j][row] = !refl ? cd{0.0, 0.0} : (row == j ? alpha - beta : ((row > j && row < m) ? x[e] : cd{0.0, 0.0}));
+        if (refl) x[e] = (row == j) ? beta : ((row > j) ? cd{0.0, 0.0} : x[e]);
+      }
+      if (qh == 0) tau[j] = t;
+      used = true;
+    }
+    lds_sync();
+    if (!piv && !used && colok) {
+      const double tj = tau[j];
+      if (tj != 0.0) {
+        cd v[RQ];
+        cd w = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) {
+          v[e] = V[j][qh + PQ * e];
+          w = w + cmulc(v[e], x[e]);
+        }
+        w = gsum<PQ>(w);
+        const cd tw = tj * w;
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) x[e] = x[e] - v[e] * tw;
+      }
+    }
+  }
+  lds_sync();
+  double tr = 0.0;
+#pragma unroll
+  for (int e = 0; e < RQ; ++e) {
+    const int row = qh + PQ * e;
+    tr += (row >= kr && row < m) ? norm2(x[e]) : 0.0;
+  }
+  tr = gsum<PQ>(tr);
+  if (qh == 0) colv[qc] = (colok && !used) ? tr : 0.0;
+  lds_sync();
+  double tk = 0.0;
+  for (int k = 0; k < c; ++k) tk += colv[k];
+  *dropped = t0 > 0.0 ? tk / t0 : 0.0;
+  // thin Q = H_0 ... H_{k-1} [I; 0]; column t is untouched by H_j for j > t
+#pragma unroll
+  for (int e = 0; e < RQ; ++e) q[e] = {(qh + PQ * e == qc && qc < kr) ? 1.0 : 0.0, 0.0};
+  for (int j = kr - 1; j >= 0; --j) {
+    if (qc >= j && qc < kr) {
+      const double tj = tau[j];
+      if (tj != 0.0) {
+        cd v[RQ];
+        cd w = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) {
+          v[e] = V[j][qh + PQ * e];
+          w = w + cmulc(v[e], q[e]);
+        }
+        w = gsum<PQ>(w);
+        const cd tw = tj * w;
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) q[e] = q[e] - v[e] * tw;
+      }
+    }
+  }
+  return kr;
+}
+
+// ---------------------------------------------------------------------------- Jacobi SVD
+// One-sided Jacobi on the first ncj (even) columns of a tile in the Jacobi layout
+// (a[e] = row part + PJ*e of this slot's column), accumulating the unitary (u[e], same
+// layout). Same rotation, skip and stopping rules as the lane-group kernel's jacobi_fixed;
+// in round r of the round-robin schedule every slot meets its partner: the pair exchanges
+// columns through LDS, both members form the same inner product with the same operand
+// order, and each applies its half of the rotation to its own column. Returns the sweeps.
+template <int PJ, int RJ, int RU, int KJ, int NBUF>
+__device__ __forceinline__ int team_jacobi_lds(cd (&a)[RJ], cd (&u)[RU], int jc, int jh, int ncj, double tol2,
+                                           double skip2, int max_sweeps, cd (*XA)[KJ][PJ * RJ],
+                                           cd (*XU)[KJ][PJ * RU], double (*XN)[KJ], double* colv, double* colf) {
+  const bool colok = jc < ncj;
+  const int lastc = ncj - 1;
+  int sweeps = 0;
+  bool more = true;
+  while (more && sweeps < max_sweeps) {
+    ++sweeps;
+    double nrm = 0.0;
+#pragma unroll
+    for (int e = 0; e < RJ; ++e) nrm += norm2(a[e]);
+    nrm = gsum<PJ>(nrm);
+    if (jh == 0) colv[jc] = colok ? nrm : 0.0;
+    lds_sync();
+    double amax = 0.0;
+    for (int k = 0; k < ncj; ++k) amax = fmax(amax, colv[k]);
+    const double floor2 = skip2 * amax;
+    bool mv = false;
+    for (int r = 0; r < lastc; ++r) {
+      const int buf = NBUF == 2 ? (r & 1) : 0;
+      const int pt = jc == lastc ? r : (jc == r ? lastc : (2 * r - jc + 2 * lastc) % lastc);
+      if (colok) {
+#pragma unroll
+        for (int e = 0; e < RJ; ++e) XA[buf][jc][jh + PJ * e] = a[e];
+#pragma unroll
+        for (int e = 0; e < RU; ++e) XU[buf][jc][jh + PJ * e] = u[e];
+        if (jh == 0) XN[buf][jc] = nrm;
+      }
+      lds_sync();
+      cd b[RJ], ub[RU];
+      double nb = 0.0;
+      if (colok) {
+#pragma unroll
+        for (int e = 0; e < RJ; ++e) b[e] = XA[buf][pt][jh + PJ * e];
+#pragma unroll
+        for (int e = 0; e < RU; ++e) ub[e] = XU[buf][pt][jh + PJ * e];
+        nb = XN[buf][pt];
+      }
+      // a single buffer is rewritten next round; every wave of the team takes this barrier
+      if (NBUF == 1) lds_sync();
+      if (colok) {
+        const bool lo = jc < pt;
+        cd g = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < RJ; ++e) g = g + (lo ? cmulc(a[e], b[e]) : cmulc(b[e], a[e]));
+        g = gsum<PJ>(g);
+        const double ni = lo ? nrm : nb, nj = lo ? nb : nrm;
+        const double g2 = norm2(g);
+        const double ab = ni * nj;
+        if (g2 > tol2 * ab && fmin(ni, nj) > floor2 && g2 > 1e-300) {
+          mv |= g2 > 1e-20 * ab;
+          double cs, tg;
+          cd se;
+          jacobi_rotation(g, g2, ni, nj, &cs, &se, &tg);
+          // lower column x: c x - conj(se) y; upper column y: se x + c y
+          if (lo) {
+#pragma unroll
+            for (int e = 0; e < RJ; ++e) {
+              const cd x0 = a[e], y0 = b[e];
+              a[e].re = fma(cs, x0.re, fma(-se.re, y0.re, -se.im * y0.im));
+              a[e].im = fma(cs, x0.im, fma(-se.re, y0.im, se.im * y0.re));
+            }
+#pragma unroll
+            for (int e = 0; e < RU; ++e) {
+              const cd x0 = u[e], y0 = ub[e];
+              u[e].re = fma(cs, x0.re, fma(-se.re, y0.re, -se.im * y0.im));
+              u[e].im = fma(cs, x0.im, fma(-se.re, y0.im, se.im * y0.re));
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < RJ; ++e) {
+              const cd x0 = b[e], y0 = a[e];
+              a[e].re = fma(cs, y0.re, fma(se.re, x0.re, -se.im * x0.im));
+              a[e].im = fma(cs, y0.im, fma(se.re, x0.im, se.im * x0.re));
+            }
+#pragma unroll
+            for (int e = 0; e < RU; ++e) {
+              const cd x0 = ub[e], y0 = u[e];
+              u[e].re = fma(cs, y0.re, fma(se.re, x0.re, -se.im * x0.im));
+              u[e].im = fma(cs, y0.im, fma(se.re, x0.im, se.im * x0.re));
+            }
+          }
+          nrm = lo ? nrm - tg : nrm + tg;
+        }
+      }
+    }
+    if (jh == 0) colf[jc] = (colok && mv) ? 1.0 : 0.0;
+    lds_sync();
+    more = false;
+    for (int k = 0; k < ncj; ++k) more |= colf[k] != 0.0;
+  }
+  return sweeps;
+}
+
+// The lower column x of a rotated pair becomes c x - conj(se) y, the upper column y becomes
+// se x + c y; own is this slot's column, oth the partner's.
+template <int R>
+__device__ __forceinline__ void rot_apply(cd (&own)[R], const cd (&oth)[R], bool lo, double cs, cd se) {
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    const cd o = own[e], p = oth[e];
+    if (lo) {
+      own[e].re = fma(cs, o.re, fma(-se.re, p.re, -se.im * p.im));
+      own[e].im = fma(cs, o.im, fma(-se.re, p.im, se.im * p.re));
+    } else {
+      own[e].re = fma(cs, o.re, fma(se.re, p.re, -se.im * p.im));
+      own[e].im = fma(cs, o.im, fma(se.re, p.im, se.im * p.re));
+    }
+  }
+}
+
+// team_qr_lds for a team inside one wave: the same factorisation, with the pivot column
+// read from its slot's lanes by ds_bpermute (every slot then forms the same Householder
+// vector itself), the pivot search as a team maximum plus a ballot, and column sums as
+// butterflies, so the steps need neither LDS round trips nor barriers. Only the pivot
+// slot writes its Householder vector to V, for the formation of Q at the end.
+template <int TW, int PQ, int RQ, int KQ>
+__device__ __forceinline__ int team_qr_wave(cd (&x)[RQ], cd (&q)[RQ], int base, int qc, int qh, int m, int c,
+                                            int npiv, double rank2, double* dropped, cd (*V)[PQ * RQ],
+                                            double* tau) {
+  const bool colok = qc < c;
+  double p0 = 0.0;
+#pragma unroll
+  for (int e = 0; e < RQ; ++e) p0 += norm2(x[e]);
+  const double t0 = tsum<TW>(colok ? p0 : 0.0);
+  const int kmax = min(min(m, c), KQ);
+  int kr = kmax;
+  bool used = false;
+  for (int j = 0; j < kmax; ++j) {
+    int p = j;
+    if (j >= npiv) {
+      double rn = 0.0;
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) rn += (qh + PQ * e >= j) ? norm2(x[e]) : 0.0;
+      rn = gsum<PQ>(rn);
+      const double key = (colok && !used) ? rn : -1.0;
+      const double best = tmax<TW>(key);
+      // the lowest slot attaining the maximum
+      const uint64_t hit = tballot<TW>(qh == 0 && key == best, base);
+      if (hit) p = (__ffsll((long long)hit) - 1 - base) / PQ;
+      if (best <= rank2 * t0) {
+        kr = j;
+        break;
+      }
+    }
+    cd v[RQ];
+    const int src = base + p * PQ + qh;
+#pragma unroll
+    for (int e = 0; e < RQ; ++e) v[e] = shfl_cd(x[e], src);
+    cd xj = {0.0, 0.0};
+    double sub = 0.0;
+#pragma unroll
+    for (int e = 0; e < RQ; ++e) {
+      const int row = qh + PQ * e;
+      if (row == j) xj = v[e];
+      sub += (row > j && row < m) ? norm2(v[e]) : 0.0;
+    }
+    const cd alpha = gsum<PQ>(xj);
+    sub = gsum<PQ>(sub);
+    const double a2 = norm2(alpha);
+    const bool refl = sub > 0.0;
+    const double ra = a2 > 0.0 ? rsqrt_acc(a2) : 0.0;
+    const double aa = a2 * ra;                          // |alpha|
+    const double n2 = a2 + sub;
+    const double nrm = refl ? n2 * rsqrt_acc(n2) : aa;  // norm of the column from row j down
+    const cd ph = a2 > 0.0 ? cd{alpha.re * ra, alpha.im * ra} : cd{1.0, 0.0};
+    const cd beta = {-ph.re * nrm, -ph.im * nrm};
+    const double t = refl ? rcp_acc(nrm * (nrm + aa)) : 0.0;
+#pragma unroll
+    for (int e = 0; e < RQ; ++e) {
+      const int row = qh + PQ * e;
+      v[e] = !refl ? cd{0.0, 0.0} : (row == j ? alpha - beta : ((row > j && row < m) ? v[e] : cd{0.0, 0.0}));
+    }
+    if (qc == p) {
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) {
+        const int row = qh + PQ * e;
+        V[j][row] = v[e];
+        if (refl) x[e] = (row == j) ? beta : ((row > j) ? cd{0.0, 0.0} : x[e]);
+      }
+      if (qh == 0) tau[j] = t;
+      used = true;
+    } else if (!used && colok && t != 0.0) {
+      cd w = {0.0, 0.0};
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) w = w + cmulc(v[e], x[e]);
+      w = gsum<PQ>(w);
+      const cd tw = t * w;
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) x[e] = x[e] - v[e] * tw;
+    }
+  }
+  double tr = 0.0;
+#pragma unroll
+  for (int e = 0; e < RQ; ++e) {
+    const int row = qh + PQ * e;
+    tr += (row >= kr && row < m) ? norm2(x[e]) : 0.0;
+  }
+  const double tk = tsum<TW>((colok && !used) ? tr : 0.0);
+  *dropped = t0 > 0.0 ? tk / t0 : 0.0;
+  lds_sync();  // V and tau of every step, read by all slots below
+#pragma unroll
+  for (int e = 0; e < RQ; ++e) q[e] = {(qh + PQ * e == qc && qc < kr) ? 1.0 : 0.0, 0.0};
+  for (int j = kr - 1; j >= 0; --j) {
+    if (qc >= j && qc < kr) {
+      const double tj = tau[j];
+      if (tj != 0.0) {
+        cd v[RQ];
+        cd w = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) {
+          v[e] = V[j][qh + PQ * e];
+          w = w + cmulc(v[e], q[e]);
+        }
+        w = gsum<PQ>(w);
+        const cd tw = tj * w;
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) q[e] = q[e] - v[e] * tw;
+      }
+    }
+  }
+  return kr;
+}
+
+// team_jacobi_lds for a team inside one wave: partners read each other's columns with
+// ds_bpermute, the column maximum and the continue flag are team reductions.
+template <int TW, int PJ, int RJ, int RU>
+__device__ __forceinline__ int team_jacobi_wave(cd (&a)[RJ], cd (&u)[RU], int base, int jc, int jh, int ncj,
+                                                double tol2, double skip2, int max_sweeps) {
+  const bool colok = jc < ncj;
+  const int lastc = ncj - 1;
+  int sweeps = 0;
+  bool more = true;
+  while (more && sweeps < max_sweeps) {
+    ++sweeps;
+    double nrm = 0.0;
+#pragma unroll
+    for (int e = 0; e < RJ; ++e) nrm += norm2(a[e]);
+    nrm = gsum<PJ>(nrm);
+    const double floor2 = skip2 * tmax<TW>(colok ? nrm : 0.0);
+    bool mv = false;
+    for (int r = 0; r < lastc; ++r) {
+      const int pt = !colok ? jc : (jc == lastc ? r : (jc == r ? lastc : (2 * r - jc + 2 * lastc) % lastc));
+      const int src = base + pt * PJ + jh;
+      cd b[RJ], ub[RU];
+#pragma unroll
+      for (int e = 0; e < RJ; ++e) b[e] = shfl_cd(a[e], src);
+#pragma unroll
+      for (int e = 0; e < RU; ++e) ub[e] = shfl_cd(u[e], src);
+      const double nb = shfl_f64(nrm, src);
+      if (colok) {
+        const bool lo = jc < pt;
+        cd g = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < RJ; ++e) g = g + (lo ? cmulc(a[e], b[e]) : cmulc(b[e], a[e]));
+        g = gsum<PJ>(g);
+        const double ni = lo ? nrm : nb, nj = lo ? nb : nrm;
+        const double g2 = norm2(g);
+        const double ab = ni * nj;
+        if (g2 > tol2 * ab && fmin(ni, nj) > floor2 && g2 > 1e-300) {
+          mv |= g2 > 1e-20 * ab;
+          double cs, tg;
+          cd se;
+          jacobi_rotation(g, g2, ni, nj, &cs, &se, &tg);
+          rot_apply<RJ>(a, b, lo, cs, se);
+          rot_apply<RU>(u, ub, lo, cs, se);
+          nrm = lo ? nrm - tg : nrm + tg;
+        }
+      }
+    }
+    more = tballot<TW>(mv, base) != 0ull;
+  }
+  return sweeps;
+}
+
+// ------------------------------------------------------------------------------- one team
+template <class S, int CM, int TW>
+__device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base) {
+  using T = TeamShape<CM, TW>;
+  constexpr int D = T::D, KQ = T::KQ, KJ = T::KJ;
+  constexpr int PQ = T::PQ, RQ = T::RQ, PJ = T::PJ, RJ = T::RJ, RU = T::RU;
+  constexpr int SLOT = slot_elems(CM);
+  constexpr bool kMixed = sizeof(S) == sizeof(float);
+  constexpr int64_t WREC = wide_warm_doubles(CM);
+  const int tid = threadIdx.x;
+  const int team = tid / TW;
+  const int tl = tid % TW;
+  const int qc = tl / PQ, qh = tl % PQ;  // QR layout
+  const int jc = tl / PJ, jh = tl % PJ;  // Jacobi layout
+  const int base = tid - tl;             // first thread of the team (a lane, for TW <= 64)
+  const bool real = team < bdp->count;
+  // inst[] is indexed per lane: read it from memory, not from a register copy
+  const int me = bdp->inst[real ? team : 0];
+  TeamLds<S, CM, TW>& L = reinterpret_cast<TeamLds<S, CM, TW>*>(lds_base)[team];
+  InstDev* I = P.inst + me;
+  const int n = I->n;
+  const int M = I->M;
+  const int cap = I->cap < CM ? I->cap : CM;
+  const int64_t k = bdp->k;
+  cx<S>* arena = reinterpret_cast<cx<S>*>(P.arena) + I->site_off;
+  const uint64_t* W = P.marked + I->marked_off;
+  const double tol2 = P.trunc_tol * P.trunc_tol;
+  const double rank2 = P.rank_tol * P.rank_tol;
+  const double skip2 = P.skip_tol * P.skip_tol;
+  const bool sr = P.stoch_round != 0;
+  double* warm = P.warm ? reinterpret_cast<double*>(reinterpret_cast<char*>(P.warm) + I->warm_off) : nullptr;
+  uint64_t rs_state = mix64(((uint64_t)me << 32) ^ ((uint64_t)I->k_done * 0x9E3779B97F4A7C15ull) ^ (uint64_t)tl);
+
+  for (int l = tl; l < kBondStride; l += TW) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
+  lds_sync();
+
+  double f64 = 0.0, f32 = 0.0, drift = 0.0, truncw = 0.0;
+  int status = 0;
+
+  if (n == 1) {
+    // A single site: the reflection is the 2x2 operator c0 I + c1 P itself.
+    for (int64_t it = 0; it < k; ++it) {
+      for (int j = 0; j <= M; ++j) {
+        const bool diff = (j == M);
+        const int xb = diff ? 0 : (int)(W[j] & 1);
+        const double c0 = diff ? -1.0 : 1.0, c1 = diff ? 2.0 : -2.0;
+        const cx<S> a0 = arena[0], a1 = arena[D];
+        cx<S> o = czero<S>();
+        if (tl < 2) {
+          const cx<S> pa = proj_apply<S>(a0, a1, tl, diff, xb);
+          const cx<S> as = sel(a0, a1, tl);
+          o = {(S)c0 * as.re + (S)c1 * pa.re, (S)c0 * as.im + (S)c1 * pa.im};
+        }
+        const double nn = gsum<PQ>(tl < 2 ? norm2(up(o)) : 0.0);
+        if (diff) {
+          const double nr = sqrt(nn);
+          drift = fmax(drift, fabs(nr - 1.0));
+          if (!(nn > 0.0) || !isfinite(nn)) status |= GMPS_ST_NAN;
+          o = down<S>((1.0 / nr) * up(o));
+        }
+        team_sync_global();
+        if (real && tl < 2) arena[tl * D] = o;
+        team_sync_global();
+      }
+    }
+  } else {
+    for (int64_t it = 0; it < k; ++it) {
+      for (int j = 0; j <= M; ++j) {
+        const bool diff = (j == M);
+        const uint64_t xw = diff ? 0ull : W[j];
+        const double c0 = diff ? -1.0 : 1.0, c1 = diff ? 2.0 : -2.0;
+
+        // ---------------------------------------------- QR sweep with the MPO fused
+        int r = 1;
+        if (tl == 0) L.rdim[0] = 1;
+        APrefetch<S, CM, TW> apre;
+        apre.load(arena, tl, L.bond[0], L.bond[1]);
+        lds_sync();
+        for (int i = 0; i < n; ++i) {
+          const int chl = L.bond[i], chr = L.bond[i + 1];
+          const bool first = (i == 0), last = (i == n - 1);
+          const int xb = diff ? 0 : (int)((xw >> (n - 1 - i)) & 1ull);
+          const int Dl = first ? 1 : 2 * chl;
+          const int Dr = last ? 1 : 2 * chr;
+          cx<S>* slot = arena + (int64_t)i * SLOT;
+          apre.stage(&L.u.q.A[0][0][0], tl);
+          if (i + 1 < n) apre.load(arena + (int64_t)(i + 1) * SLOT, tl, L.bond[i + 1], L.bond[i + 2]);
+          lds_sync();
+          // X = R_{i-1} * MPO(A_i): this slot's column, rows (a, s) = part + PQ*e
+          cd x[RQ];
+          {
+            const int beta = (!last && qc >= chr) ? 1 : 0;
+            const int bcol = qc - beta * chr;
+#pragma unroll
+            for (int e = 0; e < RQ; ++e) {
+              const int row = qh + PQ * e;
+              const int a = row >> 1, s = row & 1;
+              cx<S> acc = czero<S>();
+              if (row < 2 * r && qc < Dr) {
+                if (last) {
+#pragma unroll
+                  for (int al = 0; al < 2; ++al) {
+                    const S cal = (S)(al == 0 ? c0 : c1);
+#pragma unroll
+                    for (int ap = 0; ap < CM; ++ap)
+                      if (ap < chl) {
+                        const cx<S> a0 = L.u.q.A[ap][0][0], a1 = L.u.q.A[ap][1][0];
+                        const cx<S> wa = al == 0 ? sel(a0, a1, s) : proj_apply<S>(a0, a1, s, diff, xb);
+                        acc = cfma(acc, down<S>(L.u.q.R[a][al * chl + ap]), cal * wa);
+                      }
+                  }
+                } else if (first) {
+                  const cx<S> a0 = L.u.q.A[0][0][bcol], a1 = L.u.q.A[0][1][bcol];
+                  acc = beta == 0 ? sel(a0, a1, s) : proj_apply<S>(a0, a1, s, diff, xb);
+                } else {
+#pragma unroll
+                  for (int ap = 0; ap < CM; ++ap)
+                    if (ap < chl) {
+                      const cx<S> a0 = L.u.q.A[ap][0][bcol], a1 = L.u.q.A[ap][1][bcol];
+                      const cx<S> wa = beta == 0 ? sel(a0, a1, s) : proj_apply<S>(a0, a1, s, diff, xb);
+                      acc = cfma(acc, down<S>(L.u.q.R[a][beta * chl + ap]), wa);
+                    }
+                }
+              }
+              x[e] = up(acc);
+            }
+          }
+          const double macs = (double)r * Dl * 2.0 * Dr;
+          if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+          if (last) {
+            if (real && qc == 0) {
+#pragma unroll
+              for (int e = 0; e < RQ; ++e) {
+                const int row = qh + PQ * e;
+                if (row < 2 * r) slot[(row >> 1) * 2 * D + (row & 1) * D] = store_cast<S>(x[e], rs_state, sr);
+              }
+            }
+            if (tl == 0) {
+              L.rdim[n - 1] = r;
+              L.rdim[n] = 1;
+            }
+            break;
+          }
+          const int m = 2 * r;
+          cd q[RQ];
+          double qdrop = 0.0;
+          int kr;
+          if constexpr (TW <= 64)
+            kr = team_qr_wave<TW, PQ, RQ, KQ>(x, q, base, qc, qh, m, Dr, chr, rank2, &qdrop, L.u.q.V, L.u.q.tau);
+          else
+            kr = team_qr_lds<PQ, RQ, KQ>(x, q, qc, qh, m, Dr, chr, rank2, &qdrop, L.u.q.V, L.u.q.tau, L.colv);
+          truncw = fmax(truncw, qdrop);
+          {
+            const double mm = m, cc = Dr, kk = kr;
+            f64 += 8.0 * (2.0 * mm * cc * kk - (mm + cc) * kk * kk + 2.0 * kk * kk * kk / 3.0) +
+                   8.0 * (2.0 * mm * kk * kk - 2.0 * kk * kk * kk / 3.0);
+          }
+          if (real && qc < kr) {
+#pragma unroll
+            for (int e = 0; e < RQ; ++e) {
+              const int row = qh + PQ * e;
+              if (row < m) slot[(row >> 1) * 2 * D + (row & 1) * D + qc] = store_cast<S>(q[e], rs_state, sr);
+            }
+          }
+          if (qc < Dr) {
+#pragma unroll
+            for (int e = 0; e < RQ; ++e) {
+              const int row = qh + PQ * e;
+              if (row < kr) L.u.q.R[row][qc] = x[e];
+            }
+          }
+          if (tl == 0) L.rdim[i + 1] = kr;
+          r = kr;
+          lds_sync();
+        }
+        // the QR sweep's site tensors are read by every wave of the team from here on
+        team_sync_global();
+
+        // ---------------------------------------------- truncated-SVD sweep
+        // At site i the tile is M = Q_i (U Sigma)_{i+1} reshaped (r_i, 2 chi'); Jacobi runs on
+        // the r_i columns of M^H: M^H J = V Sigma with J = U, so V^H = Sigma^{-1} (M^H J)^H
+        // stays in site i and U Sigma = J Sigma moves left.
+        if (tl == 0) L.u.s.Y[0][0] = {1.0, 0.0};
+        TeamQPre<S, KQ, CM, TW> qpre;
+        TeamWPre<KJ, TW> wpre;
+        qpre.load(arena + (int64_t)(n - 1) * SLOT, tl, L.rdim[n - 1], L.rdim[n]);
+        wpre.load(warm ? warm + ((int64_t)j * n + (n - 1)) * WREC : nullptr, tl, (L.rdim[n - 1] + 1) & ~1);
+        for (int i = n - 1; i >= 1; --i) {
+          const int ri = L.rdim[i], rn = L.rdim[i + 1];
+          const int chn = L.bond[i + 1];
+          const int c = 2 * chn;
+          const int ncj = (ri + 1) & ~1;
+          cx<S>* slot = arena + (int64_t)i * SLOT;
+          double* wrec = warm ? warm + ((int64_t)j * n + i) * WREC : nullptr;
+          const bool use_warm = wrec && wpre.r == ncj;
+          // the stored unitary is a product of exact rotations, so its unitarity drifts by
+          // ~1e-16 per use; one Newton-Schulz step every 64 iterations keeps it below ~1e-13
+          const bool renorm_warm = use_warm && (((uint64_t)I->k_done + (uint64_t)it) & 63ull) == 0ull;
+          qpre.stage(&L.u.s.Q[0][0][0], tl);
+          if (use_warm) wpre.stage(&L.u.s.W[0][0], tl);
+          if (i - 1 >= 1) {
+            qpre.load(arena + (int64_t)(i - 1) * SLOT, tl, L.rdim[i - 1], L.rdim[i]);
+            wpre.load(warm ? warm + ((int64_t)j * n + (i - 1)) * WREC : nullptr, tl, (L.rdim[i - 1] + 1) & ~1);
+          }
+          lds_sync();
+          // column jc of M^H: M^H[(s, jj)][a] = conj(sum_b Q[a][s][b] Y[b][jj])
+          cd a[RJ];
+#pragma unroll
+          for (int e = 0; e < RJ; ++e) {
+            const int row = jh + PJ * e;
+            const int s = row >= chn ? 1 : 0;
+            const int jj = row - s * chn;
+            cx<S> acc = czero<S>();
+            if (jc < ri && row < c) {
+#pragma unroll
+              for (int b = 0; b < KQ; ++b)
+                if (b < rn) acc = cfma(acc, L.u.s.Q[jc][s][b], down<S>(L.u.s.Y[b][jj]));
+            }
+            a[e] = conj(up(acc));
+          }
+          {
+            const double macs = (double)ri * 2.0 * rn * chn;
+            if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+          }
+          if (renorm_warm) {
+            // one Newton-Schulz polar step W <- W (3I - W^H W) / 2 (error e -> O(e^2))
+            cd* WG = &L.u.s.XU[0][0][0];  // KJ x KJ, row-major
+            for (int e = tl; e < KJ * KJ; e += TW) {
+              const int ra = e / KJ, ca = e % KJ;
+              cd g = {0.0, 0.0};
+              for (int b = 0; b < ncj; ++b) g = g + cmulc(L.u.s.W[b][ra], L.u.s.W[b][ca]);
+              WG[e] = g;
+            }
+            lds_sync();
+            constexpr int NW = (KJ * KJ + TW - 1) / TW;
+            cd wn[NW];
+#pragma unroll
+            for (int t = 0; t < NW; ++t) {
+              const int e = tl + t * TW;
+              const int ra = e / KJ, ca = e % KJ;
+              cd acc = {0.0, 0.0};
+              if (e < KJ * KJ)
+                for (int b = 0; b < ncj; ++b) acc = cfma(acc, L.u.s.W[ra][b], WG[b * KJ + ca]);
+              wn[t] = (e < KJ * KJ) ? 1.5 * L.u.s.W[ra][ca] - 0.5 * acc : cd{0.0, 0.0};
+            }
+            lds_sync();
+#pragma unroll
+            for (int t = 0; t < NW; ++t) {
+              const int e = tl + t * TW;
+              if (e < KJ * KJ) L.u.s.W[e / KJ][e % KJ] = wn[t];
+            }
+            lds_sync();
+          }
+          cd uu[RU];
+          if (use_warm) {
+            // start from the previous iteration's unitary: M^H <- M^H W
+            if (jc < KJ) {
+#pragma unroll
+              for (int e = 0; e < RJ; ++e) L.u.s.XA[0][jc][jh + PJ * e] = a[e];
+            }
+            lds_sync();
+#pragma unroll
+            for (int e = 0; e < RJ; ++e) {
+              const int row = jh + PJ * e;
+              cd acc = {0.0, 0.0};
+              if (jc < ncj)
+                for (int b = 0; b < ncj; ++b) acc = cfma(acc, L.u.s.XA[0][b][row], L.u.s.W[b][jc]);
+              a[e] = acc;
+            }
+#pragma unroll
+            for (int e = 0; e < RU; ++e) {
+              const int row = jh + PJ * e;
+              uu[e] = (jc < ncj && row < ncj) ? L.u.s.W[row][jc] : cd{0.0, 0.0};
+            }
+            lds_sync();
+          } else {
+#pragma unroll
+            for (int e = 0; e < RU; ++e) uu[e] = {(jh + PJ * e == jc && jc < ncj) ? 1.0 : 0.0, 0.0};
+          }
+          int sweeps;
+          if constexpr (TW <= 64)
+            sweeps = team_jacobi_wave<TW, PJ, RJ, RU>(a, uu, base, jc, jh, ncj, kJacobiTol2, skip2, P.max_sweeps);
+          else
+            sweeps = team_jacobi_lds<PJ, RJ, RU, KJ, T::NBUF>(a, uu, jc, jh, ncj, kJacobiTol2, skip2, P.max_sweeps,
+                                                              L.u.s.XA, L.u.s.XU, L.u.s.XN, L.colv, L.colf);
+          f64 += (double)sweeps * ri * (ri - 1) / 2.0 * 56.0 * c;
+          // singular values, truncation and the kept order
+          const bool colok = jc < ncj;
+          double sg = 0.0;
+#pragma unroll
+          for (int e = 0; e < RJ; ++e) sg += norm2(a[e]);
+          sg = gsum<PJ>(sg);
+          // kept columns stay in their index order (so the bond basis, and the next warm
+          // start, does not jump when Schmidt values are degenerate); dropped ones follow
+          double stot, dropped;
+          int chi_new, pos;
+          bool keep;
+          if constexpr (TW <= 64) {
+            const double mine = colok ? sg : 0.0;
+            const double smax = tmax<TW>(mine);
+            stot = tsum<TW>(jh == 0 ? mine : 0.0);
+            const int above = (int)tsum<TW>((jh == 0 && mine > 0.0 && mine >= tol2 * smax) ? 1.0 : 0.0);
+            int rk = 0;
+            for (int o = 0; o < ncj; ++o) {
+              const double v = shfl_f64(mine, base + o * PJ);
+              rk += (v > sg || (v == sg && o < jc)) ? 1 : 0;
+            }
+            chi_new = above < cap ? above : cap;
+            if (chi_new < 1) chi_new = 1;
+            keep = colok && rk < chi_new;
+            const uint64_t kept = tballot<TW>(jh == 0 && keep, base);
+            const int nk = __popcll(kept & ((1ull << (base + jc * PJ)) - 1ull));
+            pos = keep ? nk : chi_new + (jc - nk);
+            dropped = tsum<TW>((jh == 0 && colok && !keep) ? sg : 0.0);
+          } else {
+            if (jh == 0) L.colv[jc] = colok ? sg : 0.0;
+            lds_sync();
+            double smax = 0.0;
+            stot = 0.0;
+            for (int o = 0; o < ncj; ++o) {
+              const double v = L.colv[o];
+              smax = fmax(smax, v);
+              stot += v;
+            }
+            int above = 0, rk = 0;
+            for (int o = 0; o < ncj; ++o) {
+              const double v = L.colv[o];
+              above += (v > 0.0 && v >= tol2 * smax) ? 1 : 0;
+              rk += (v > sg || (v == sg && o < jc)) ? 1 : 0;
+            }
+            chi_new = above < cap ? above : cap;
+            if (chi_new < 1) chi_new = 1;
+            if (jh == 0) L.colr[jc] = colok ? rk : KJ + jc;
+            lds_sync();
+            dropped = 0.0;
+            int nk = 0, nd = 0;
+            for (int o = 0; o < ncj; ++o) {
+              const bool ko = L.colr[o] < chi_new;
+              if (!ko) dropped += L.colv[o];
+              if (o < jc) {
+                nk += ko ? 1 : 0;
+                nd += ko ? 0 : 1;
+              }
+            }
+            keep = colok && rk < chi_new;
+            pos = keep ? nk : chi_new + nd;
+          }
+          if (stot > 0.0) truncw = fmax(truncw, dropped / stot);
+          if (!isfinite(stot)) status |= GMPS_ST_NAN;
+          if (wrec && real) {
+            // keep J with its columns in the kept order for the next iteration
+            if (colok) {
+#pragma unroll
+              for (int e = 0; e < RU; ++e) {
+                const int row = jh + PJ * e;
+                if (row < ncj) {
+                  wrec[2 + 2 * (row * KJ + pos)] = uu[e].re;
+                  wrec[3 + 2 * (row * KJ + pos)] = uu[e].im;
+                }
+              }
+            }
+            if (tl == 0) wrec[0] = (double)ncj;
+          }
+          if (keep) {
+            const double rs = rsqrt_acc(sg);  // 1/sigma
+            if (real) {
+#pragma unroll
+              for (int e = 0; e < RJ; ++e) {
+                const int row = jh + PJ * e;
+                if (row < c) {
+                  const int s = row >= chn ? 1 : 0;
+                  const int jp = row - s * chn;
+                  slot[pos * 2 * D + s * D + jp] = store_cast<S>(rs * conj(a[e]), rs_state, sr);
+                }
+              }
+            }
+#pragma unroll
+            for (int e = 0; e < RU; ++e) {
+              const int row = jh + PJ * e;
+              if (row < ri) L.u.s.Y[row][pos] = (sg * rs) * uu[e];
+            }
+          }
+          if (tl == 0) L.bond[i] = chi_new;
+          lds_sync();
+        }
+        // ---------------------------------------------- site 0 (holds the norm)
+        team_sync_global();
+        {
+          const int rn = L.rdim[1], chn = L.bond[1];
+          cx<S>* slot = arena;
+          cx<S> acc = czero<S>();
+          const bool act = tl < 2 * chn;
+          const int s = tl >= chn ? 1 : 0;
+          const int jj = tl - s * chn;
+          if (act) {
+#pragma unroll
+            for (int b = 0; b < KQ; ++b)
+              if (b < rn) acc = cfma(acc, slot[s * D + b], down<S>(L.u.s.Y[b][jj]));
+          }
+          const double macs = 2.0 * rn * chn;
+          if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+          double nn = 0.0;
+          if constexpr (TW <= 64) {
+            nn = tsum<TW>(act ? norm2(up(acc)) : 0.0);
+          } else {
+            L.colv[tl] = act ? norm2(up(acc)) : 0.0;
+            lds_sync();
+            for (int o = 0; o < 2 * chn; ++o) nn += L.colv[o];
+          }
+          if (!isfinite(nn) || !(nn > 0.0)) status |= GMPS_ST_NAN;
+          const double nr = sqrt(nn);
+          if (diff) drift = fmax(drift, fabs(nr - 1.0));
+          const cx<S> out = store_cast<S>((diff ? 1.0 / nr : 1.0) * up(acc), rs_state, sr);
+          lds_sync();
+          if (real && act) slot[s * D + jj] = out;
+          if (tl == 0) L.bond[0] = 1;
+          team_sync_global();
+        }
+      }
+    }
+  }
+
+  // ------------------------------------------------------------------ write back
+  if (real) {
+    for (int l = tl; l < kBondStride; l += TW) P.bonds[(int64_t)me * kBondStride + l] = L.bond[l];
+    if (tl == 0) {
+      I->k_done += k;
+      I->flops64 += f64;
+      I->flops32 += f32;
+      I->drift = fmax(I->drift, drift);
+      I->trunc_w = fmax(I->trunc_w, truncw);
+      if (drift > 1e-3) status |= GMPS_ST_DRIFT;
+      if (truncw > 1e-8) status |= GMPS_ST_TRUNC;
+      I->status |= status;
+    }
+  }
+  team_sync_global();
+}
+
+// Persistent kernel of one team class W: a workgroup takes bundles from the class's queue
+// until it is empty.
+template <class S, int W>
+__global__ __launch_bounds__(kWide[W].TW < 64 ? 64 : kWide[W].TW) void grover_team_kernel(IterParams P) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ unsigned int next_bundle;
+  for (;;) {
+    if (threadIdx.x == 0) next_bundle = atomicAdd(&P.queue->next, 1u);
+    lds_sync();
+    const unsigned int bi = next_bundle;
+    lds_sync();
+    if ((int)bi >= P.queue->nbundles) break;
+    run_team<S, kWide[W].CM, kWide[W].TW>(P, P.bundles + bi, lds);
+  }
+}
+
+// Launch and occupancy of class W, defined in the class's own translation unit.
+template <int W>
+hipError_t launch_team_w(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st);
+template <int W>
+hipError_t occupancy_team_w(bool mixed, size_t lds, int* blocks_per_cu);
+
+#define GMPS_TEAM_CLASS(W)                                                                           \
+  template <>                                                                                        \
+  hipError_t launch_team_w<W>(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st) { \
+    constexpr int nt = kWide[W].TW < 64 ? 64 : kWide[W].TW;                                           \
+    if (mixed)                                                                                       \
+      grover_team_kernel<float, W><<<grid, nt, lds, st>>>(P);                                         \
+    else                                                                                             \
+      grover_team_kernel<double, W><<<grid, nt, lds, st>>>(P);                                        \
+    return hipGetLastError();                                                                        \
+  }                                                                                                  \
+  template <>                                                                                        \
+  hipError_t occupancy_team_w<W>(bool mixed, size_t lds, int* blocks_per_cu) {                      \
+    constexpr int nt = kWide[W].TW < 64 ? 64 : kWide[W].TW;                                           \
+    return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_team_kernel<float, W>, nt, lds) \
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_team_kernel<double, W>, nt, lds); \
+  }
+
+}  // namespace gmps

@@ -25,6 +25,7 @@ GMPS_E_UNSUPPORTED = -4
 GMPS_E_NUMERIC = -5
 ST_NAN, ST_DRIFT, ST_TRUNC = 1, 2, 4
 BOND_STRIDE = 64
+KERNELS = {"auto": 0, "group": 1, "team": 2}
 
 EXPORTED = ("gmps_workspace_bytes", "gmps_create", "mps_init_uniform", "grover_iterate", "marked_prob",
             "sample_shots", "gmps_amplitudes", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
@@ -40,7 +41,7 @@ class GmpsOptions(ctypes.Structure):
     _fields_ = [("trunc_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("round_mode", ctypes.c_int32), ("jacobi_warm", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class GmpsError(RuntimeError):
@@ -137,7 +138,8 @@ class Batch:
 
     def __init__(self, instances: Sequence, precision: str = "fp64", trunc_tol: float = 0.0,
                  max_sweeps: int = 0, waves_per_cu: int = 0, use_graph: bool = True, stream=None,
-                 device=None, stochastic_rounding: bool = True, jacobi_warm: Optional[bool] = None):
+                 device=None, stochastic_rounding: bool = True, jacobi_warm: Optional[bool] = None,
+                 kernel: str = "auto"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libgmps needs a ROCm GPU; none is visible")
@@ -161,6 +163,7 @@ class Batch:
         opt.use_graph = 1 if use_graph else -1
         opt.round_mode = 1 if stochastic_rounding else -1
         opt.jacobi_warm = 0 if jacobi_warm is None else (1 if jacobi_warm else -1)
+        opt.kernel = KERNELS[kernel]
         self._opt = opt
         h = ctypes.c_void_p()
         rc = self.lib.gmps_create(ctypes.byref(h), self._arr, self.B, _ptr(self._marked, ctypes.c_uint64), prec,

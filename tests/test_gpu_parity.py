@@ -20,12 +20,19 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-10, "mixed": 1e-6}
 
 
+@pytest.fixture(params=["group", "team"])
+def kernel(request):
+    """Both iterate kernels run every parity case."""
+    return request.param
+
+
 def say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
 
 
 def run(instances, precision, k=None, **kw):
+    kw.setdefault("kernel", "auto")
     b = gmps.Batch(instances, precision, **kw)
     b.init_uniform()
     b.iterate([i.k for i in instances] if k is None else k)
@@ -44,10 +51,10 @@ def check_sampling(bits, n, W, k, shots, seed, inst, tie_tol):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_c1_full_statevector(gpu, precision):
-    say("case: C1 n=10 k=25 %s" % precision)
+def test_c1_full_statevector(gpu, kernel, precision):
+    say("case: C1 n=10 k=25 %s %s" % (precision, kernel))
     inst = inputs.config_c1().instances[0]
-    b = run([inst], precision)
+    b = run([inst], precision, kernel=kernel)
     p = b.marked_prob()[0]
     assert abs(p - cf.p_marked(10, 1, 25)) < TOL[precision]
     psi = sv.grover_sv(10, inst.marked, 25)
@@ -62,10 +69,10 @@ def test_c1_full_statevector(gpu, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_ragged_batch_small_n(gpu, precision):
-    say("case: ragged batch n in [2,14], M in {1..4}, %s" % precision)
+def test_ragged_batch_small_n(gpu, kernel, precision):
+    say("case: ragged batch n in [2,14], M in {1..4}, %s %s" % (precision, kernel))
     insts = inputs.random_batch(37, 2, 14, (1, 2, 3, 4), seed=31, cap_extra=1)
-    b = run(insts, precision)
+    b = run(insts, precision, kernel=kernel)
     p = b.marked_prob()
     for i, inst in enumerate(insts):
         assert abs(p[i] - cf.p_marked(inst.n, inst.M, inst.k)) < TOL[precision], (i, inst.n, inst.M, inst.k)
@@ -82,14 +89,14 @@ def test_ragged_batch_small_n(gpu, precision):
             assert prof[l] <= min(2 ** l, 2 ** (inst.n - l), inst.M + 1)
 
 
-def test_edge_cases(gpu):
-    say("case: edge cases n=1, n=2, M=N-1, k=0, extra cap")
+def test_edge_cases(gpu, kernel):
+    say("case: edge cases n=1, n=2, M=N-1, k=0, extra cap, %s" % kernel)
     insts = [inputs.Instance(1, np.array([1], np.uint64), 1, 2),
              inputs.Instance(2, np.array([2], np.uint64), 1, 2),
              inputs.Instance(3, np.arange(7, dtype=np.uint64), 3, 6),
              inputs.Instance(6, np.array([0, 63], np.uint64), 0, 3),
              inputs.Instance(7, np.array([5], np.uint64), 4, 6)]
-    b = run(insts, "fp64")
+    b = run(insts, "fp64", kernel=kernel)
     p = b.marked_prob()
     for i, inst in enumerate(insts):
         assert abs(p[i] - cf.p_marked(inst.n, inst.M, inst.k)) < 1e-12, i
@@ -99,25 +106,25 @@ def test_edge_cases(gpu):
     assert p[1] == pytest.approx(1.0, abs=1e-14)  # N=4 textbook case
 
 
-def test_iterate_is_additive(gpu):
-    say("case: additivity 5+7 == 12")
+def test_iterate_is_additive(gpu, kernel):
+    say("case: additivity 5+7 == 12, %s" % kernel)
     insts = inputs.random_batch(9, 8, 13, (1, 2), seed=8)
-    a = gmps.Batch(insts, "fp64")
+    a = gmps.Batch(insts, "fp64", kernel=kernel)
     a.init_uniform()
     a.iterate(5)
     a.iterate(7)
-    c = run(insts, "fp64", k=12)
+    c = run(insts, "fp64", k=12, kernel=kernel)
     assert np.max(np.abs(a.marked_prob() - c.marked_prob())) < 1e-13
     assert list(a.diagnostics()["k_done"]) == [12] * 9
     for i, inst in enumerate(insts):
         assert abs(c.marked_prob()[i] - cf.p_marked(inst.n, inst.M, 12)) < 1e-10
 
 
-def test_cap_below_rank_is_flagged(gpu):
-    say("case: cap below exact rank")
+def test_cap_below_rank_is_flagged(gpu, kernel):
+    say("case: cap below exact rank, %s" % kernel)
     n, M = 10, 3
     W = inputs.draw_marked(n, M, inputs.SplitMix64(77))
-    b = run([inputs.Instance(n, W, 3, 2)], "fp64")
+    b = run([inputs.Instance(n, W, 3, 2)], "fp64", kernel=kernel)
     d = b.diagnostics()
     assert d["status"][0] & gmps.ST_TRUNC
     assert d["trunc_weight"][0] > 1e-8
@@ -129,11 +136,11 @@ def test_cap_below_rank_is_flagged(gpu):
     assert abs(p - ref.marked_prob()) < 1e-10
 
 
-def test_c2_with_sampling(gpu):
-    say("case: C2 n=20 k=804 fp64 + 4096 shots")
+def test_c2_with_sampling(gpu, kernel):
+    say("case: C2 n=20 k=804 fp64 + 4096 shots, %s" % kernel)
     w = inputs.config_c2()
     inst = w.instances[0]
-    b = run([inst], "fp64")
+    b = run([inst], "fp64", kernel=kernel)
     p = b.marked_prob()[0]
     assert abs(p - cf.p_marked(20, 1, 804)) < 1e-10
     xs = np.array([int(inst.marked[0]), 0, 12345, (1 << 20) - 1], dtype=np.uint64)
@@ -147,11 +154,11 @@ def test_c2_with_sampling(gpu):
     assert hits[0] >= 4090
 
 
-def test_sampling_many_instances_matches_oracle(gpu):
-    say("case: sampling replay, 12 instances x 64 shots, fp64 and mixed")
+def test_sampling_many_instances_matches_oracle(gpu, kernel):
+    say("case: sampling replay, 12 instances x 64 shots, fp64 and mixed, %s" % kernel)
     insts = inputs.random_batch(12, 5, 12, (1, 2, 4), seed=99)
     for precision, tie in (("fp64", 1e-9), ("mixed", 1e-5)):
-        b = run(insts, precision)
+        b = run(insts, precision, kernel=kernel)
         bits, hits = b.sample(64, 4242)
         for i, inst in enumerate(insts):
             check_sampling(bits[i], inst.n, inst.marked, inst.k, 64, 4242, i, tie)
