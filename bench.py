@@ -5,7 +5,8 @@ reset to |s> (mps_init_uniform), iterated to its own k (grover_iterate, one pers
 launch), read out (marked_prob) and sampled (sample_shots). value = sum_i k_i / step time.
 The accuracy gate requires |P_i - sin^2((2k_i+1) theta_i)| <= 1e-6 for every instance.
 
-    python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--workload c4|c2|c3]
+    python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--workload c4|c2|c3] [--kernel auto|team|group]
+                    [--c5-k 48] [--no-plain] [--no-cpu] [--no-fp64-batch]
 
 Prints one JSON line. See the design doc for the roofline and baseline definitions.
 """
@@ -28,6 +29,7 @@ from paper_2601_03832_amd import inputs  # noqa: E402
 
 FP64_VECTOR_PEAK = 78.6e12    # MI355X published FP64 vector rate, FLOP/s
 FP32_VECTOR_PEAK = 157.3e12   # MI355X published FP32 vector rate, FLOP/s
+HBM_PEAK = 8.0e12             # MI355X published HBM3E bandwidth, bytes/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grover_kernel.json")
 # the iterate kernel each --kernel choice runs (the library's choice is the team kernel)
 KERNEL_NAME = {"auto": "grover_team_kernel", "team": "grover_team_kernel", "group": "grover_group_kernel"}
@@ -141,6 +143,69 @@ def cpu_baseline(w, iters_per_stratum: int = 100):
                       % (iters_per_stratum, len(strata), wall, est)}
 
 
+def c5_prefix(k: int, kernel: str):
+    """256 instances at n=40, M=16, cap 32 (bond 17), mixed, for a prefix of k iterations:
+    the full k=205887 takes hours, so the rate and the accuracy are reported on the prefix."""
+    import torch
+    from paper_2601_03832_amd import gmps
+    w = inputs.config_c5(k=k)
+    b = gmps.Batch(w.instances, w.precision, kernel=kernel)
+    b.init_uniform()
+    b.iterate(k)  # warm (graph capture)
+    torch.cuda.synchronize()
+    b.init_uniform()
+    t0 = time.perf_counter()
+    b.iterate(k)
+    p = b.marked_prob(allow_numeric=True)
+    t1 = time.perf_counter()
+    err = float(np.max(np.abs(p - exact_p(40, 16, k))))
+    frac = {}
+    for shots in w.shots:
+        _, hits = b.sample(shots, w.shot_seed)
+        frac[str(shots)] = float(np.mean(hits / shots))
+    kms = b.last_iterate_ms()
+    b.close()
+    n_inst = len(w.instances)
+    return {"value": n_inst * k / (t1 - t0), "unit": "iterations/s", "instances": n_inst, "k_prefix": k,
+            "seconds": t1 - t0, "kernel_ms": kms, "max_abs_err_p": err, "p_exact": exact_p(40, 16, k),
+            "mean_hit_fraction": frac,
+            "note": "256 x (n=40, M=16, cap 32) for the first %d of k=205887 iterations, mixed; not extrapolated" % k}
+
+
+def statevector_leg(n: int, k: int):
+    """The dense-statevector backend (the paper's comparison, Section III-A) on one instance
+    of the workload's largest n, FP64 and FP32 vectors, for a prefix of k iterations, next to
+    the MPS path (FP64, B=1) on the same instance and prefix. One statevector iteration
+    streams the vector once in and once out: 2 * 2^n * (8 or 4) bytes."""
+    import torch
+    from paper_2601_03832_amd import gmps
+    inst = [i for i in inputs.config_c4().instances if i.n == n and i.M == 1][0]
+    out = {"n": n, "M": 1, "k_prefix": k,
+           "note": "one instance of the n=%d, M=1 stratum; rates over the first %d iterations" % (n, k)}
+    for prec, nbytes in (("fp64", 8), ("mixed", 4)):
+        s = gmps.StateVector(n, inst.marked, prec)
+        s.init_uniform()
+        s.iterate(2)  # warm
+        s.init_uniform()
+        torch.cuda.synchronize()
+        s.iterate(k)
+        ms = s.last_iterate_ms()
+        p = s.marked_prob()
+        s.close()
+        gbs = 2.0 * (1 << n) * nbytes * k / (ms / 1e3) / 1e9
+        out["sv_" + prec] = {"value": k / (ms / 1e3), "unit": "iterations/s", "ms": ms, "hbm_gb_per_s": gbs,
+                             "hbm_frac": gbs / (HBM_PEAK / 1e9), "max_abs_err_p": abs(p - exact_p(n, 1, k))}
+    b = gmps.Batch([inst], "fp64")
+    b.init_uniform()
+    b.iterate(k)
+    ms = b.last_iterate_ms()
+    out["mps_fp64"] = {"value": k / (ms / 1e3), "unit": "iterations/s", "ms": ms,
+                       "max_abs_err_p": abs(b.marked_prob()[0] - exact_p(n, 1, k))}
+    b.close()
+    out["mps_over_sv_fp64"] = out["mps_fp64"]["value"] / out["sv_fp64"]["value"]
+    return out
+
+
 def traffic_record():
     try:
         with open(TRAFFIC_FILE) as f:
@@ -163,6 +228,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64-batch", action="store_true")
     ap.add_argument("--shots", type=int, default=None)
+    ap.add_argument("--c5-k", type=int, default=48, help="iterations of the n=40, M=16 prefix leg (0: skip)")
+    ap.add_argument("--sv-k", type=int, default=500, help="iterations of the statevector comparison leg (0: skip)")
     ap.add_argument("--kernel", default="auto", choices=sorted(["auto", "group", "team"]),
                     help="iterate kernel: lane-group, team, or the library's choice")
     args = ap.parse_args()
@@ -256,6 +323,12 @@ def main():
                                 "note": "same workload and step through the FP64 path (one untimed-warmup-free step)"}
         b64.close()
         print("bench: batched fp64 leg done", file=sys.stderr, flush=True)
+    if args.c5_k > 0 and args.workload == "c4":
+        line["c5_prefix"] = c5_prefix(args.c5_k, args.kernel)
+        print("bench: c5 prefix leg done", file=sys.stderr, flush=True)
+    if args.sv_k > 0 and args.workload == "c4":
+        line["statevector"] = statevector_leg(28, args.sv_k)
+        print("bench: statevector leg done", file=sys.stderr, flush=True)
     if not args.no_plain:
         line["plain_fp64"] = plain_fp64_rate(w, args.plain_budget)
         line["plain_fp64"]["speedup_of_batched_mixed"] = line["value"] / line["plain_fp64"]["value"]

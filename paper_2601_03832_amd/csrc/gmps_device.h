@@ -191,20 +191,29 @@ template <class S, int CM, int G>
 struct APrefetch {
   static constexpr int NE = (CM * 2 * CM + G - 1) / G;
   cx<S> v[NE];
+  int chl_, chr_;
+  // The loads are unconditional (element indices are clamped into the box, which lies
+  // inside the slot) and the unused elements are masked only when the tile is staged: a
+  // load under a branch, or a use of its value right away, would make the compiler wait
+  // for the load there instead of one site later.
   __device__ __forceinline__ void load(const cx<S>* slot, int gl, int chl, int chr) {
     constexpr int D = 2 * CM;
+    chl_ = chl;
+    chr_ = chr;
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = gl + t * G;
-      const int a = e / (2 * CM), s = (e / CM) & 1, b = e % CM;
-      v[t] = (e < CM * 2 * CM && a < chl && b < chr) ? slot[a * 2 * D + s * D + b] : czero<S>();
+      const int ec = e < CM * 2 * CM ? e : CM * 2 * CM - 1;
+      const int a = ec / (2 * CM), s = (ec / CM) & 1, b = ec % CM;
+      v[t] = slot[a * 2 * D + s * D + b];
     }
   }
   __device__ __forceinline__ void stage(cx<S>* lds_a, int gl) const {
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = gl + t * G;
-      if (e < CM * 2 * CM) lds_a[e] = v[t];
+      const int a = e / (2 * CM), b = e % CM;
+      if (e < CM * 2 * CM) lds_a[e] = (a < chl_ && b < chr_) ? v[t] : czero<S>();
     }
   }
 };

@@ -263,7 +263,12 @@ struct QPrefetch {
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int b = 0; b < KQ; ++b) v[s][b] = (gl < ri && b < rn) ? slot[gl * 2 * D + s * D + b] : czero<S>();
+      for (int b = 0; b < KQ; ++b) {
+        // unconditional load from a row inside the slot, masked afterwards (see APrefetch)
+        const int gr = gl < D ? gl : D - 1;
+        const cx<S> val = slot[gr * 2 * D + s * D + b];
+        v[s][b] = (gl < ri && b < rn) ? val : czero<S>();
+      }
   }
 };
 
@@ -313,7 +318,9 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
   const double rank2 = P.rank_tol * P.rank_tol;
   const bool sr = P.stoch_round != 0;
   WarmRec* warm = P.warm ? reinterpret_cast<WarmRec*>(reinterpret_cast<char*>(P.warm) + I->warm_off) : nullptr;
-  uint64_t rs_state = mix64(((uint64_t)me << 32) ^ ((uint64_t)I->k_done * 0x9E3779B97F4A7C15ull) ^ (uint64_t)gl);
+  // read once: a global load inside the sweeps would be waited for at its use
+  const uint64_t k_done0 = (uint64_t)I->k_done;
+  uint64_t rs_state = mix64(((uint64_t)me << 32) ^ (k_done0 * 0x9E3779B97F4A7C15ull) ^ (uint64_t)gl);
 
   for (int l = gl; l < kBondStride; l += G) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
   lds_sync();
@@ -516,7 +523,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
           const bool use_warm = wrec && wcur.r == ncj;
           // the stored unitary is a product of exact rotations, so its unitarity drifts by
           // ~1e-16 per use; one Newton-Schulz step every 64 iterations keeps it below ~1e-13
-          const bool renorm_warm = use_warm && (((uint64_t)I->k_done + (uint64_t)it) & 63ull) == 0ull;
+          const bool renorm_warm = use_warm && ((k_done0 + (uint64_t)it) & 63ull) == 0ull;
           if (use_warm) {
 #pragma unroll
             for (int t = 0; t < WPrefetch<KJ, G>::NE; ++t) {

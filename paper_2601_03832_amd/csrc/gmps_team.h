@@ -50,7 +50,7 @@ struct TeamLds {
   using T = TeamShape<CM, TW>;
   union {
     struct {                                  // QR sweep
-      cx<S> A[CM][2][CM];                     // staged site tensor
+      cx<S> W[2][CM][2][CM];                  // staged MPO blocks [c0 A | c1 P A] of the site
       cd R[T::KQ][T::D];                      // R of the previous step, original column order
       cd V[T::KQ][T::PQ * T::RQ];             // Householder vectors of this step
       double tau[T::KQ];
@@ -150,49 +150,104 @@ __device__ __forceinline__ void jacobi_rotation(cd g, double g2, double ni, doub
 }
 
 // ----------------------------------------------------------------------- prefetched loads
+// The site tensor A_i of the QR sweep, loaded one site ahead as (a, b) pairs with both
+// physical values, so that staging can write both blocks of the bond-2 MPO applied to it:
+// W[0][a][s][b] = c0 A[a][s][b] and W[1][a][s][b] = c1 (P A)[a][s][b], with (c0, c1) the
+// reflection's coefficients at the last site and (1, 1) elsewhere. The contraction with R
+// then reads W directly. Loads are unconditional, masked when staged (see APrefetch).
+template <class S, int CM, int TW>
+struct TeamAPre {
+  static constexpr int NE = (CM * CM + TW - 1) / TW;
+  cx<S> v0[NE], v1[NE];
+  int chl_, chr_;
+  __device__ __forceinline__ void load(const cx<S>* slot, int tl, int chl, int chr) {
+    constexpr int D = 2 * CM;
+    chl_ = chl;
+    chr_ = chr;
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tl + t * TW;
+      const int ec = e < CM * CM ? e : CM * CM - 1;
+      const int a = ec / CM, b = ec % CM;
+      v0[t] = slot[a * 2 * D + b];
+      v1[t] = slot[a * 2 * D + D + b];
+    }
+  }
+  __device__ __forceinline__ void stage(cx<S> (*W)[CM][2][CM], int tl, bool diff, int xb, S c0, S c1) const {
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tl + t * TW;
+      if (e < CM * CM) {
+        const int a = e / CM, b = e % CM;
+        const bool ok = a < chl_ && b < chr_;
+        const cx<S> a0 = ok ? v0[t] : czero<S>(), a1 = ok ? v1[t] : czero<S>();
+        W[0][a][0][b] = c0 * a0;
+        W[0][a][1][b] = c0 * a1;
+        W[1][a][0][b] = c1 * proj_apply<S>(a0, a1, 0, diff, xb);
+        W[1][a][1][b] = c1 * proj_apply<S>(a0, a1, 1, diff, xb);
+      }
+    }
+  }
+};
+
 // The Q_i tile (r_i, 2, r_{i+1}) of the SVD sweep, loaded by the team one site ahead.
 template <class S, int KQ, int CM, int TW>
 struct TeamQPre {
   static constexpr int NE = (KQ * 2 * KQ + TW - 1) / TW;
   cx<S> v[NE];
+  int ri_, rn_;
+  // unconditional loads from clamped indices, masked when staged (see APrefetch)
   __device__ __forceinline__ void load(const cx<S>* slot, int tl, int ri, int rn) {
     constexpr int D = 2 * CM;
+    ri_ = ri;
+    rn_ = rn;
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = tl + t * TW;
-      const int a = e / (2 * KQ), s = (e / KQ) & 1, b = e % KQ;
-      v[t] = (e < KQ * 2 * KQ && a < ri && b < rn) ? slot[a * 2 * D + s * D + b] : czero<S>();
+      const int ec = e < KQ * 2 * KQ ? e : KQ * 2 * KQ - 1;
+      const int a = ec / (2 * KQ), s = (ec / KQ) & 1, b = ec % KQ;
+      v[t] = slot[a * 2 * D + s * D + b];
     }
   }
   __device__ __forceinline__ void stage(cx<S>* lds_q, int tl) const {
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = tl + t * TW;
-      if (e < KQ * 2 * KQ) lds_q[e] = v[t];
+      const int a = e / (2 * KQ), b = e % KQ;
+      if (e < KQ * 2 * KQ) lds_q[e] = (a < ri_ && b < rn_) ? v[t] : czero<S>();
     }
   }
 };
 
-// A warm-start record: r (as a double), a pad double, then the KJ x KJ unitary.
+// A warm-start record: r (as a double), a pad double, then the KJ x KJ unitary. w is always
+// readable (without warm starts it points at a dummy record and on is false); the loads are
+// unconditional, masked when staged (see APrefetch).
 template <int KJ, int TW>
 struct TeamWPre {
   static constexpr int NE = (KJ * KJ + TW - 1) / TW;
   cd v[NE];
-  int r;
-  __device__ __forceinline__ void load(const double* w, int tl, int ncj) {
-    r = w ? (int)w[0] : 0;
+  double r0;
+  bool on_;
+  int ncj_;
+  __device__ __forceinline__ void load(const double* w, bool on, int tl, int ncj) {
+    on_ = on;
+    ncj_ = ncj;
+    r0 = w[0];
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = tl + t * TW;
-      const int ra = e / KJ, ca = e % KJ;
-      v[t] = (w && e < KJ * KJ && ra < ncj && ca < ncj) ? cd{w[2 + 2 * e], w[3 + 2 * e]} : cd{0.0, 0.0};
+      const int ec = e < KJ * KJ ? e : KJ * KJ - 1;
+      v[t] = {w[2 + 2 * ec], w[3 + 2 * ec]};
     }
   }
+  // the dimension the record holds (0 when warm starts are off)
+  __device__ __forceinline__ int r() const { return on_ ? (int)r0 : 0; }
   __device__ __forceinline__ void stage(cd* lds_w, int tl) const {
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = tl + t * TW;
-      if (e < KJ * KJ) lds_w[e] = v[t];
+      const int ra = e / KJ, ca = e % KJ;
+      if (e < KJ * KJ) lds_w[e] = (ra < ncj_ && ca < ncj_) ? v[t] : cd{0.0, 0.0};
     }
   }
 };
@@ -435,18 +490,15 @@ __device__ __forceinline__ int team_jacobi_lds(cd (&a)[RJ], cd (&u)[RU], int jc,
 
 // The lower column x of a rotated pair becomes c x - conj(se) y, the upper column y becomes
 // se x + c y; own is this slot's column, oth the partner's.
+// Both are own' = c own + f oth with f = -conj(se) for the lower column and se for the upper.
 template <int R>
 __device__ __forceinline__ void rot_apply(cd (&own)[R], const cd (&oth)[R], bool lo, double cs, cd se) {
+  const double fre = lo ? -se.re : se.re, fim = se.im;
 #pragma unroll
   for (int e = 0; e < R; ++e) {
     const cd o = own[e], p = oth[e];
-    if (lo) {
-      own[e].re = fma(cs, o.re, fma(-se.re, p.re, -se.im * p.im));
-      own[e].im = fma(cs, o.im, fma(-se.re, p.im, se.im * p.re));
-    } else {
-      own[e].re = fma(cs, o.re, fma(se.re, p.re, -se.im * p.im));
-      own[e].im = fma(cs, o.im, fma(se.re, p.im, se.im * p.re));
-    }
+    own[e].re = fma(cs, o.re, fma(fre, p.re, -fim * p.im));
+    own[e].im = fma(cs, o.im, fma(fre, p.im, fim * p.re));
   }
 }
 
@@ -507,29 +559,30 @@ __device__ __forceinline__ int team_qr_wave(cd (&x)[RQ], cd (&q)[RQ], int base, 
     const cd ph = a2 > 0.0 ? cd{alpha.re * ra, alpha.im * ra} : cd{1.0, 0.0};
     const cd beta = {-ph.re * nrm, -ph.im * nrm};
     const double t = refl ? rcp_acc(nrm * (nrm + aa)) : 0.0;
+    // reflector rows (rows >= m of the tile are zero; with no reflection t = 0 and v is unused)
 #pragma unroll
     for (int e = 0; e < RQ; ++e) {
       const int row = qh + PQ * e;
-      v[e] = !refl ? cd{0.0, 0.0} : (row == j ? alpha - beta : ((row > j && row < m) ? v[e] : cd{0.0, 0.0}));
+      v[e] = row > j ? v[e] : (row == j ? alpha - beta : cd{0.0, 0.0});
     }
-    if (qc == p) {
-#pragma unroll
-      for (int e = 0; e < RQ; ++e) {
-        const int row = qh + PQ * e;
-        V[j][row] = v[e];
-        if (refl) x[e] = (row == j) ? beta : ((row > j) ? cd{0.0, 0.0} : x[e]);
-      }
-      if (qh == 0) tau[j] = t;
-      used = true;
-    } else if (!used && colok && t != 0.0) {
+    // every slot of the trailing columns, the pivot included, applies H_j (no divergence);
+    // the pivot column becomes (beta, ~0, ...) and is not touched again
+    {
       cd w = {0.0, 0.0};
 #pragma unroll
       for (int e = 0; e < RQ; ++e) w = w + cmulc(v[e], x[e]);
       w = gsum<PQ>(w);
-      const cd tw = t * w;
+      const cd tw = (!used && colok) ? t * w : cd{0.0, 0.0};
 #pragma unroll
       for (int e = 0; e < RQ; ++e) x[e] = x[e] - v[e] * tw;
     }
+    const bool piv = qc == p;
+    if (piv) {
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) V[j][qh + PQ * e] = v[e];
+      if (qh == 0) tau[j] = t;
+    }
+    used = used || piv;
   }
   double tr = 0.0;
 #pragma unroll
@@ -580,8 +633,12 @@ __device__ __forceinline__ int team_jacobi_wave(cd (&a)[RJ], cd (&u)[RU], int ba
     nrm = gsum<PJ>(nrm);
     const double floor2 = skip2 * tmax<TW>(colok ? nrm : 0.0);
     bool mv = false;
+    // round r: slot lastc meets r, slot r meets lastc, slot c meets (2r - c) mod lastc
+    int t2 = colok && jc < lastc ? (lastc - jc) % lastc : 0;
     for (int r = 0; r < lastc; ++r) {
-      const int pt = !colok ? jc : (jc == lastc ? r : (jc == r ? lastc : (2 * r - jc + 2 * lastc) % lastc));
+      const int pt = !colok ? jc : (jc == lastc ? r : (jc == r ? lastc : t2));
+      t2 += 2;
+      if (t2 >= lastc) t2 -= lastc;
       const int src = base + pt * PJ + jh;
       cd b[RJ], ub[RU];
 #pragma unroll
@@ -645,7 +702,12 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
   const double skip2 = P.skip_tol * P.skip_tol;
   const bool sr = P.stoch_round != 0;
   double* warm = P.warm ? reinterpret_cast<double*>(reinterpret_cast<char*>(P.warm) + I->warm_off) : nullptr;
-  uint64_t rs_state = mix64(((uint64_t)me << 32) ^ ((uint64_t)I->k_done * 0x9E3779B97F4A7C15ull) ^ (uint64_t)tl);
+  // without warm starts the record loads read this instance's own records area: the site
+  // slots, which hold at least one record's worth of elements (never used)
+  const double* wdummy = reinterpret_cast<const double*>(reinterpret_cast<cx<S>*>(P.arena) + I->site_off);
+  // read once: a global load inside the sweeps would be waited for at its use
+  const uint64_t k_done0 = (uint64_t)I->k_done;
+  uint64_t rs_state = mix64(((uint64_t)me << 32) ^ (k_done0 * 0x9E3779B97F4A7C15ull) ^ (uint64_t)tl);
 
   for (int l = tl; l < kBondStride; l += TW) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
   lds_sync();
@@ -688,8 +750,13 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
 
         // ---------------------------------------------- QR sweep with the MPO fused
         int r = 1;
-        if (tl == 0) L.rdim[0] = 1;
-        APrefetch<S, CM, TW> apre;
+        if (tl == 0) {
+          L.rdim[0] = 1;
+          // the first site's tile is [A | P A] itself: R = [1 1] over the two MPO blocks
+          L.u.q.R[0][0] = {1.0, 0.0};
+          L.u.q.R[0][1] = {1.0, 0.0};
+        }
+        TeamAPre<S, CM, TW> apre;
         apre.load(arena, tl, L.bond[0], L.bond[1]);
         lds_sync();
         for (int i = 0; i < n; ++i) {
@@ -699,7 +766,7 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
           const int Dl = first ? 1 : 2 * chl;
           const int Dr = last ? 1 : 2 * chr;
           cx<S>* slot = arena + (int64_t)i * SLOT;
-          apre.stage(&L.u.q.A[0][0][0], tl);
+          apre.stage(L.u.q.W, tl, diff, xb, (S)(last ? c0 : 1.0), (S)(last ? c1 : 1.0));
           if (i + 1 < n) apre.load(arena + (int64_t)(i + 1) * SLOT, tl, L.bond[i + 1], L.bond[i + 2]);
           lds_sync();
           // X = R_{i-1} * MPO(A_i): this slot's column, rows (a, s) = part + PQ*e
@@ -713,29 +780,14 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
               const int a = row >> 1, s = row & 1;
               cx<S> acc = czero<S>();
               if (row < 2 * r && qc < Dr) {
-                if (last) {
+                // the last site sums both MPO blocks into its one column
 #pragma unroll
-                  for (int al = 0; al < 2; ++al) {
-                    const S cal = (S)(al == 0 ? c0 : c1);
+                for (int bl = 0; bl < 2; ++bl) {
+                  if (last || bl == beta) {
 #pragma unroll
                     for (int ap = 0; ap < CM; ++ap)
-                      if (ap < chl) {
-                        const cx<S> a0 = L.u.q.A[ap][0][0], a1 = L.u.q.A[ap][1][0];
-                        const cx<S> wa = al == 0 ? sel(a0, a1, s) : proj_apply<S>(a0, a1, s, diff, xb);
-                        acc = cfma(acc, down<S>(L.u.q.R[a][al * chl + ap]), cal * wa);
-                      }
+                      if (ap < chl) acc = cfma(acc, down<S>(L.u.q.R[a][bl * chl + ap]), L.u.q.W[bl][ap][s][bcol]);
                   }
-                } else if (first) {
-                  const cx<S> a0 = L.u.q.A[0][0][bcol], a1 = L.u.q.A[0][1][bcol];
-                  acc = beta == 0 ? sel(a0, a1, s) : proj_apply<S>(a0, a1, s, diff, xb);
-                } else {
-#pragma unroll
-                  for (int ap = 0; ap < CM; ++ap)
-                    if (ap < chl) {
-                      const cx<S> a0 = L.u.q.A[ap][0][bcol], a1 = L.u.q.A[ap][1][bcol];
-                      const cx<S> wa = beta == 0 ? sel(a0, a1, s) : proj_apply<S>(a0, a1, s, diff, xb);
-                      acc = cfma(acc, down<S>(L.u.q.R[a][beta * chl + ap]), wa);
-                    }
                 }
               }
               x[e] = up(acc);
@@ -800,7 +852,7 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
         TeamQPre<S, KQ, CM, TW> qpre;
         TeamWPre<KJ, TW> wpre;
         qpre.load(arena + (int64_t)(n - 1) * SLOT, tl, L.rdim[n - 1], L.rdim[n]);
-        wpre.load(warm ? warm + ((int64_t)j * n + (n - 1)) * WREC : nullptr, tl, (L.rdim[n - 1] + 1) & ~1);
+        wpre.load(warm ? warm + ((int64_t)j * n + (n - 1)) * WREC : wdummy, warm != nullptr, tl, (L.rdim[n - 1] + 1) & ~1);
         for (int i = n - 1; i >= 1; --i) {
           const int ri = L.rdim[i], rn = L.rdim[i + 1];
           const int chn = L.bond[i + 1];
@@ -808,15 +860,16 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
           const int ncj = (ri + 1) & ~1;
           cx<S>* slot = arena + (int64_t)i * SLOT;
           double* wrec = warm ? warm + ((int64_t)j * n + i) * WREC : nullptr;
-          const bool use_warm = wrec && wpre.r == ncj;
+          const bool use_warm = wrec && wpre.r() == ncj;
           // the stored unitary is a product of exact rotations, so its unitarity drifts by
           // ~1e-16 per use; one Newton-Schulz step every 64 iterations keeps it below ~1e-13
-          const bool renorm_warm = use_warm && (((uint64_t)I->k_done + (uint64_t)it) & 63ull) == 0ull;
+          const bool renorm_warm = use_warm && ((k_done0 + (uint64_t)it) & 63ull) == 0ull;
           qpre.stage(&L.u.s.Q[0][0][0], tl);
           if (use_warm) wpre.stage(&L.u.s.W[0][0], tl);
           if (i - 1 >= 1) {
             qpre.load(arena + (int64_t)(i - 1) * SLOT, tl, L.rdim[i - 1], L.rdim[i]);
-            wpre.load(warm ? warm + ((int64_t)j * n + (i - 1)) * WREC : nullptr, tl, (L.rdim[i - 1] + 1) & ~1);
+            wpre.load(warm ? warm + ((int64_t)j * n + (i - 1)) * WREC : wdummy, warm != nullptr, tl,
+                      (L.rdim[i - 1] + 1) & ~1);
           }
           lds_sync();
           // column jc of M^H: M^H[(s, jj)][a] = conj(sum_b Q[a][s][b] Y[b][jj])

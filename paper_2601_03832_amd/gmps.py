@@ -29,7 +29,8 @@ KERNELS = {"auto": 0, "group": 1, "team": 2}
 
 EXPORTED = ("gmps_workspace_bytes", "gmps_create", "mps_init_uniform", "grover_iterate", "marked_prob",
             "sample_shots", "gmps_amplitudes", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
-            "gmps_strerror")
+            "gmps_strerror", "gsv_workspace_bytes", "gsv_create", "gsv_init_uniform", "gsv_iterate",
+            "gsv_marked_prob", "gsv_amplitudes", "gsv_last_iterate_ms", "gsv_destroy")
 
 
 class GmpsInstance(ctypes.Structure):
@@ -88,6 +89,21 @@ def load(path: Optional[str] = None):
     lib.gmps_destroy.argtypes = [P]
     lib.gmps_strerror.restype = ctypes.c_char_p
     lib.gmps_strerror.argtypes = [ctypes.c_int]
+    lib.gsv_workspace_bytes.restype = ctypes.c_size_t
+    lib.gsv_workspace_bytes.argtypes = [i32, i32, ctypes.c_int]
+    lib.gsv_create.restype = ctypes.c_int
+    lib.gsv_create.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(u64), i32, ctypes.c_int, P, ctypes.c_size_t, P]
+    for name in ("gsv_init_uniform", "gsv_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+        getattr(lib, name).argtypes = [P]
+    lib.gsv_iterate.restype = ctypes.c_int
+    lib.gsv_iterate.argtypes = [P, i64]
+    lib.gsv_marked_prob.restype = ctypes.c_int
+    lib.gsv_marked_prob.argtypes = [P, ctypes.POINTER(dbl)]
+    lib.gsv_amplitudes.restype = ctypes.c_int
+    lib.gsv_amplitudes.argtypes = [P, ctypes.POINTER(u64), i64, ctypes.POINTER(dbl)]
+    lib.gsv_last_iterate_ms.restype = ctypes.c_int
+    lib.gsv_last_iterate_ms.argtypes = [P, ctypes.POINTER(dbl)]
     _lib = lib
     return lib
 
@@ -242,4 +258,70 @@ class Batch:
     def last_iterate_ms(self) -> float:
         v = ctypes.c_double()
         self._check(self.lib.gmps_last_iterate_ms(self.handle, ctypes.byref(v)), "gmps_last_iterate_ms")
+        return v.value
+
+
+class StateVector:
+    """Dense-statevector iterative Grover (include/gsv.h) for one instance on the current GPU:
+    the paper's comparison backend. precision 'fp64' (FP64 vector) or 'mixed' (FP32 vector,
+    FP64 sums)."""
+
+    def __init__(self, n: int, marked, precision: str = "fp64", stream=None, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libgmps needs a ROCm GPU; none is visible")
+        self.lib = load()
+        self.n = int(n)
+        self.marked = np.ascontiguousarray(np.asarray(marked, dtype=np.uint64))
+        prec = _prec(precision)
+        nbytes = int(self.lib.gsv_workspace_bytes(self.n, len(self.marked), prec))
+        if nbytes == 0:
+            raise GmpsError(GMPS_E_ARG, "gsv_workspace_bytes")
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        rc = self.lib.gsv_create(ctypes.byref(h), self.n, _ptr(self.marked, ctypes.c_uint64), len(self.marked), prec,
+                                 ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != GMPS_OK:
+            raise GmpsError(rc, "gsv_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gsv_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != GMPS_OK:
+            raise GmpsError(rc, what)
+
+    def init_uniform(self):
+        self._check(self.lib.gsv_init_uniform(self.handle), "gsv_init_uniform")
+
+    def iterate(self, k: int):
+        self._check(self.lib.gsv_iterate(self.handle, int(k)), "gsv_iterate")
+
+    def marked_prob(self) -> float:
+        v = ctypes.c_double()
+        self._check(self.lib.gsv_marked_prob(self.handle, ctypes.byref(v)), "gsv_marked_prob")
+        return v.value
+
+    def amplitudes(self, xs) -> np.ndarray:
+        xs = np.ascontiguousarray(np.asarray(xs, dtype=np.uint64))
+        out = np.zeros(len(xs), dtype=np.float64)
+        self._check(self.lib.gsv_amplitudes(self.handle, _ptr(xs, ctypes.c_uint64), len(xs),
+                                            _ptr(out, ctypes.c_double)), "gsv_amplitudes")
+        return out
+
+    def last_iterate_ms(self) -> float:
+        v = ctypes.c_double()
+        self._check(self.lib.gsv_last_iterate_ms(self.handle, ctypes.byref(v)), "gsv_last_iterate_ms")
         return v.value

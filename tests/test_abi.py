@@ -11,10 +11,11 @@ from paper_2601_03832_amd import gmps, inputs
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "gmps.h")
+SV_HEADER = os.path.join(ROOT, "include", "gsv.h")
 
 
-def _declared():
-    text = open(HEADER).read()
+def _declared(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", text, flags=re.M)))
 
@@ -34,9 +35,37 @@ def test_header_declares_the_hot_path_calls():
 
 
 def test_library_exports_every_declared_symbol(lib):
-    for name in _declared():
+    declared = _declared() + _declared(SV_HEADER)
+    for name in declared:
         assert hasattr(lib, name), name
-    assert set(gmps.EXPORTED) <= set(_declared())
+    assert set(gmps.EXPORTED) <= set(declared)
+
+
+def test_statevector_workspace_and_argument_checks(lib):
+    lib.gsv_workspace_bytes.restype = ctypes.c_size_t
+    b64 = lib.gsv_workspace_bytes(20, 1, gmps.GMPS_FP64)
+    b32 = lib.gsv_workspace_bytes(20, 1, gmps.GMPS_MIXED)
+    assert b64 >= 8 << 20 and b32 >= 4 << 20 and b64 > b32 and b64 % 256 == 0
+    assert lib.gsv_workspace_bytes(34, 1, gmps.GMPS_FP64) >= 8 << 34
+    for n, M in ((0, 1), (35, 1), (3, 8), (3, 0)):
+        assert lib.gsv_workspace_bytes(n, M, gmps.GMPS_FP64) == 0
+    h = ctypes.c_void_p()
+    P64 = ctypes.POINTER(ctypes.c_uint64)
+    dup = np.array([3, 3], dtype=np.uint64)
+    big = np.array([1 << 10], dtype=np.uint64)
+    ok = np.array([3], dtype=np.uint64)
+    assert lib.gsv_create(ctypes.byref(h), 10, dup.ctypes.data_as(P64), 2, gmps.GMPS_FP64, ctypes.c_void_p(256),
+                          1 << 30, None) == gmps.GMPS_E_ARG
+    assert lib.gsv_create(ctypes.byref(h), 10, big.ctypes.data_as(P64), 1, gmps.GMPS_FP64, ctypes.c_void_p(256),
+                          1 << 30, None) == gmps.GMPS_E_ARG
+    assert lib.gsv_create(ctypes.byref(h), 10, ok.ctypes.data_as(P64), 1, gmps.GMPS_FP64, ctypes.c_void_p(0),
+                          1 << 30, None) == gmps.GMPS_E_WORKSPACE
+    assert lib.gsv_create(ctypes.byref(h), 10, ok.ctypes.data_as(P64), 1, gmps.GMPS_FP64, ctypes.c_void_p(256),
+                          16, None) == gmps.GMPS_E_WORKSPACE
+    for fn in ("gsv_init_uniform", "gsv_destroy"):
+        getattr(lib, fn).argtypes = [ctypes.c_void_p]
+    assert lib.gsv_init_uniform(None) == gmps.GMPS_E_ARG
+    assert lib.gsv_destroy(None) == gmps.GMPS_OK
 
 
 def test_strerror_names_every_code(lib):

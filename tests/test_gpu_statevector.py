@@ -1,0 +1,68 @@
+"""Parity of the dense-statevector backend (include/gsv.h) with the closed form of Eq. (5)-(6)
+and with the oracle's statevector iteration (Eqs. (3)-(4)).
+
+FP64: P within 1e-10 and every amplitude within 1e-12 of the oracle (n <= 16). The FP32
+vector (FP64 sums) rounds every amplitude once per iteration; at n=24 its P error is
+reported and bounded loosely (1e-3): the paper's Fig. 3 shows FP32 degrading from n~18 on."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import closed_form as cf
+from oracle import statevector as sv
+from paper_2601_03832_amd import gmps, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("n,M", [(1, 1), (2, 1), (3, 7), (10, 1), (12, 4), (16, 3)])
+def test_small_statevector_matches_oracle(gpu, n, M):
+    say("case: statevector n=%d M=%d" % (n, M))
+    W = inputs.draw_marked(n, M, inputs.SplitMix64(900 + n * 7 + M))
+    k = inputs.k_rule(n, M)
+    s = gmps.StateVector(n, W, "fp64")
+    s.init_uniform()
+    s.iterate(k)
+    assert abs(s.marked_prob() - cf.p_marked(n, M, k)) < 1e-10
+    amps = s.amplitudes(np.arange(1 << n, dtype=np.uint64))
+    assert np.max(np.abs(amps - sv.grover_sv(n, W, k).real)) < 1e-12
+
+
+def test_iterate_additive_and_k0(gpu):
+    say("case: statevector additivity and k=0")
+    n, W = 14, inputs.draw_marked(14, 2, inputs.SplitMix64(5))
+    a = gmps.StateVector(n, W, "fp64")
+    a.init_uniform()
+    assert abs(a.marked_prob() - 2.0 / (1 << n)) < 1e-15
+    a.iterate(0)
+    a.iterate(7)
+    a.iterate(13)
+    b = gmps.StateVector(n, W, "fp64")
+    b.init_uniform()
+    b.iterate(20)
+    xs = np.arange(1 << n, dtype=np.uint64)
+    assert np.max(np.abs(a.amplitudes(xs) - b.amplitudes(xs))) < 1e-14
+    assert abs(a.marked_prob() - cf.p_marked(n, 2, 20)) < 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
+def test_n24_full_k(gpu, precision, tol):
+    n, M = 24, 1
+    W = inputs.draw_marked(n, M, inputs.SplitMix64(24))
+    k = inputs.k_rule(n, M)
+    say("case: statevector n=24 k=%d %s" % (k, precision))
+    s = gmps.StateVector(n, W, precision)
+    s.init_uniform()
+    s.iterate(k)
+    p = s.marked_prob()
+    say("   |dP| = %.3e" % abs(p - cf.p_marked(n, M, k)))
+    assert abs(p - cf.p_marked(n, M, k)) < tol, p
+    am, au = cf.amplitudes_wr(n, M, k)
+    got = s.amplitudes(np.array([W[0], 0, 12345, (1 << n) - 1], dtype=np.uint64))
+    assert abs(got[0] - am) < tol and np.max(np.abs(got[1:] - au)) < 10 * tol * abs(au)
