@@ -87,15 +87,33 @@ typedef struct {
                            -1: round to nearest                                         */
   int32_t jacobi_warm;  /* 1: each Jacobi SVD starts from the unitary it produced at the
                            same (reflection, site) one iteration earlier, which keeps the
-                           bond bases continuous across iterations (it lowers the mixed
-                           path's error several-fold); -1: start from the identity;
-                           0: default, on for GMPS_MIXED and off for GMPS_FP64          */
+                           bond bases continuous across iterations; -1: start from the
+                           identity; 0: default: off for GMPS_FP64, on for GMPS_MIXED (it
+                           removes a systematic drift at M = 1 and keeps single marked
+                           amplitudes together), except with precontract, where it is on
+                           for bond caps of 2 only: there the bond basis of a (reflection,
+                           site) is not continuous across iterations at larger caps, and
+                           the warm start costs time and accuracy                         */
   int32_t kernel;       /* iterate kernel: 1 = lane-group kernel (a tile row per lane, up to 8
                            instances per wave; bond caps up to 6, larger caps go to the team
                            kernel), 2 = team kernel (a tile column per lane slot, one instance per
                            team of 16-256 threads; bond caps up to 32), 0 = library choice
                            (the team kernel) */
-  int32_t reserved[2];
+  int32_t precontract;  /* 1: projector pre-contraction, a recompression variant of Section III-B
+                           (team kernel only; with kernel = 1: GMPS_E_UNSUPPORTED; instances
+                           whose effective bond cap exceeds 17 keep the bond-2 MPOs). A reflection
+                           c0 I + c1 sum_t |p_t><p_t| over product states p_t (Eqs. (3)-(4): the
+                           marked basis states for O, |s> for D) maps psi to
+                           c0 psi + c1 sum_t <p_t|psi> p_t, an MPS of bond chi + T built from
+                           the site tensors and the overlaps <p_t|psi> (contracted during the
+                           QR sweep), instead of a bond-2 MPO per projector (bond 2 chi).
+                           When the bond cap is lossless (chi_cap >= min(M+1, 2^floor(n/2)))
+                           and M fits the tile class, O is one reflection with T = M, so an
+                           iteration takes two QR+SVD sweeps instead of M+1; otherwise each
+                           marked index is one reflection with T = 1. Same result up to
+                           rounding; 0 or -1 (default): one bond-2 MPO per projector, as in
+                           the paper. */
+  int32_t reserved[1];
 } gmps_options;
 
 /* Bytes of device workspace gmps_create() needs for this batch with either iterate kernel

@@ -19,9 +19,9 @@ hipError_t launch_group(bool mixed, const IterParams& P, int grid, size_t lds, h
 hipError_t group_occupancy(bool mixed, size_t lds, int* blocks_per_cu);
 size_t group_lds_bytes(bool mixed, int cls);
 int team_per_bundle(int cls);
-size_t team_lds_bytes(bool mixed, int cls);
-hipError_t launch_team(bool mixed, int cls, const IterParams& P, int grid, size_t lds, hipStream_t st);
-hipError_t team_occupancy(bool mixed, int cls, size_t lds, int* blocks_per_cu);
+size_t team_lds_bytes(bool mixed, bool pc, int cls);
+hipError_t launch_team(bool mixed, bool pc, int cls, const IterParams& P, int grid, size_t lds, hipStream_t st);
+hipError_t team_occupancy(bool mixed, bool pc, int cls, size_t lds, int* blocks_per_cu);
 hipError_t launch_queue_reset(QueueState* q, hipStream_t st);
 hipError_t launch_init(bool mixed, InstDev* inst, int B, const int64_t* site_start, int32_t* bonds, void* arena,
                        int64_t total_sites, char* warm, hipStream_t st);
@@ -141,6 +141,7 @@ struct gmps_batch {
   bool use_graph = true;
   bool stoch_round = true;
   int jacobi_warm = 0;  // 0: library default (mixed path only), 1 on, -1 off
+  bool precontract = false;  // reflections as psi + product terms (team kernel only)
   int path = kPathGroup;
   int max_cm = 0;       // largest class bond of the batch (read-out register sizing)
   int num_cus = 0;
@@ -227,6 +228,8 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     if (!valid_instance(inst[i])) return GMPS_E_ARG;
   if (opt && (opt->kernel < 0 || opt->kernel > kPathTeam)) return GMPS_E_ARG;
   const int path = resolve_path(opt ? opt->kernel : kPathAuto);
+  const bool precontract = opt && opt->precontract > 0;
+  if (precontract && path != kPathTeam) return GMPS_E_UNSUPPORTED;
   Layout L;
   std::vector<int> cls;
   std::vector<int64_t> site_off, warm_off;
@@ -272,6 +275,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     if (opt->round_mode < 0) b->stoch_round = false;
     b->jacobi_warm = opt->jacobi_warm;
   }
+  b->precontract = precontract;
   hipGetDevice(&b->device);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
@@ -290,6 +294,10 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     d.M = inst[i].M;
     d.cap = effective_cap(inst[i].n, inst[i].M, inst[i].chi_cap);
     d.cls = cls[i];
+    // one reflection for the whole oracle: the cap keeps every exact Schmidt rank (so no
+    // state exceeds rank M+1) and chi + M columns fit the class tile
+    d.whole = (precontract && is_wide(cls[i]) && team_pc_class(cls[i] - kWideBase) &&
+               d.cap == effective_cap(inst[i].n, inst[i].M, INT32_MAX) && inst[i].M <= class_cm(cls[i])) ? 1 : 0;
     d.marked_off = moff;
     d.site_off = site_off[i];
     d.warm_off = warm_off[i];
@@ -362,10 +370,11 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
   // estimated cost, longest first, so the persistent queue hands out the long serial
   // chains early.
   struct Key {
-    int cls, n, M;
+    int cls, n, M, whole;
     int64_t k;
     bool operator<(const Key& o) const {
       if (cls != o.cls) return cls < o.cls;
+      if (whole != o.whole) return whole < o.whole;
       if (n != o.n) return n < o.n;
       if (M != o.M) return M < o.M;
       return k < o.k;
@@ -376,7 +385,7 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
     const int64_t ki = k[k_len == 1 ? 0 : i];
     if (ki == 0) continue;
     const InstDev& d = b->inst_h[i];
-    groups[{d.cls, d.n, d.M, ki}].push_back(i);
+    groups[{d.cls, d.n, d.M, d.whole, ki}].push_back(i);
   }
   if (b->staging_pending) {
     GMPS_HIP(hipEventSynchronize(b->staging_done));
@@ -391,8 +400,9 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
     const int kind = team ? 1 + (cls - kWideBase) : 0;
     const int per = team ? team_per_bundle(cls) : 64 / kClasses[cls].G;
     // a site step of either kernel takes roughly (CM + 1) times a fixed latency
-    const double cost = (double)g.first.k * (g.first.M + 1) * std::max(1, g.first.n - 1) * (class_cm(cls) + 1.0);
-    lds[kind] = std::max(lds[kind], team ? team_lds_bytes(b->mixed, cls) : group_lds_bytes(b->mixed, cls) * per);
+    const int refl = g.first.whole ? 2 : g.first.M + 1;  // reflections per iteration
+    const double cost = (double)g.first.k * refl * std::max(1, g.first.n - 1) * (class_cm(cls) + 1.0);
+    lds[kind] = std::max(lds[kind], team ? team_lds_bytes(b->mixed, b->precontract, cls) : group_lds_bytes(b->mixed, cls) * per);
     for (size_t s = 0; s < g.second.size(); s += per) {
       Bundle bd;
       std::memset(&bd, 0, sizeof(bd));
@@ -436,7 +446,7 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
     if (count[kd] == 0) continue;
     int per_cu = 0;
     if (kd == 0) GMPS_HIP(group_occupancy(b->mixed, lds[kd], &per_cu));
-    else GMPS_HIP(team_occupancy(b->mixed, kWideBase + kd - 1, lds[kd], &per_cu));
+    else GMPS_HIP(team_occupancy(b->mixed, b->precontract, kWideBase + kd - 1, lds[kd], &per_cu));
     if (b->waves_per_cu > 0) per_cu = std::min(per_cu, b->waves_per_cu);
     per_cu = std::max(per_cu, 1);
     cap_wg[kd] = per_cu * b->num_cus;
@@ -478,8 +488,13 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
       IterParams P = b->params;
       P.bundles = dev_bundles + first[kd];
       P.queue = dev_queue + kd;
+      // library default for pre-contracted reflections: warm starts for the bond-2 class
+      // only (above it the bond basis of a (reflection, site) changes between iterations,
+      // the previous unitary does not shorten the Jacobi, and on the 4096-instance workload
+      // it raised the largest mixed-precision error of P from 7e-7 to 1.3e-6)
+      if (kd > 0 && b->precontract && b->jacobi_warm == 0 && kWide[kd - 1].CM > 2) P.warm = nullptr;
       e = kd == 0 ? launch_group(b->mixed, P, grid[kd], lds[kd], ks)
-                  : launch_team(b->mixed, kWideBase + kd - 1, P, grid[kd], lds[kd], ks);
+                  : launch_team(b->mixed, b->precontract, kWideBase + kd - 1, P, grid[kd], lds[kd], ks);
       if (e == hipSuccess && !on_main) {
         e = hipEventRecord(b->join_ev[kd], ks);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join_ev[kd], 0);

@@ -182,6 +182,7 @@ __device__ __forceinline__ cx<S> proj_apply(cx<S> a0, cx<S> a1, int s, bool diff
   return s == xb ? sel(a0, a1, xb) : czero<S>();
 }
 
+constexpr double kInvSqrt2 = 0.70710678118654752440;  // |+> = (|0> + |1>) / sqrt(2)
 constexpr double kJacobiTol2 = 1e-30;  // (relative off-diagonal 1e-15)^2
 
 

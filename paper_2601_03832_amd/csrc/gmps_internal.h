@@ -10,7 +10,8 @@ struct InstDev {
   int64_t marked_off;      // first marked index in the marked[] array
   int64_t site_off;        // complex-element offset of site 0's slot in the arena
   int64_t k_done;          // iterations applied since init
-  int32_t status, pad;     // GMPS_ST_* bits
+  int32_t status;          // GMPS_ST_* bits
+  int32_t whole;           // pre-contracted path: the M oracle terms form one reflection
   double drift;            // largest |norm - 1| before a renormalisation
   double trunc_w;          // largest dropped-weight fraction of one truncation
   double flops64, flops32; // algorithmic flops spent so far
@@ -67,6 +68,8 @@ __host__ __device__ constexpr int class_cm(int cls) {
 __host__ __device__ constexpr int class_kj(int CM) { return ((CM + 1) + 1) & ~1; }
 // Doubles of one team-class warm-start record: r (as a double), a pad double, then the
 // KJ x KJ complex unitary, row-major.
+// Team classes with a pre-contracted reflection kernel (bond caps up to 17).
+__host__ __device__ constexpr bool team_pc_class(int w) { return kWide[w].CM <= 17; }
 __host__ __device__ constexpr int64_t wide_warm_doubles(int CM) { return 2 + 2 * (int64_t)class_kj(CM) * class_kj(CM); }
 
 // Elements of one site slot: (D, 2, D) with row stride 2*D and physical stride D.

@@ -71,6 +71,17 @@ struct TeamLds {
   int32_t rdim[kBondStride];
 };
 
+// LDS of a team's pre-contracted reflections, placed after the TeamLds of every team of the
+// workgroup (launches of the pre-contracted kernels only).
+template <int CM>
+struct PcLds {
+  cd ov[CM][CM];                // running overlap rows <p_t| psi>_{0..i} (double-buffered with
+                                // the MPO block W[1], which these reflections leave unused)
+  cd ovs[CM];                   // c1 <p_t|psi>
+  uint32_t xbits[kBondStride];  // bit t of site i: qubit value of marked index t at site i
+};
+
+
 // Orders LDS and global-memory traffic of the workgroup: global stores of one wave are
 // complete and visible to the others after it (site tensors written in one sweep are read
 // by other waves in the next).
@@ -185,6 +196,19 @@ struct TeamAPre {
         W[0][a][1][b] = c0 * a1;
         W[1][a][0][b] = c1 * proj_apply<S>(a0, a1, 0, diff, xb);
         W[1][a][1][b] = c1 * proj_apply<S>(a0, a1, 1, diff, xb);
+      }
+    }
+  }
+  // the site tensor alone, scaled by c0 (pre-contracted reflections)
+  __device__ __forceinline__ void stage_a(cx<S> (*W)[CM][2][CM], int tl, S c0) const {
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tl + t * TW;
+      if (e < CM * CM) {
+        const int a = e / CM, b = e % CM;
+        const bool ok = a < chl_ && b < chr_;
+        W[0][a][0][b] = c0 * (ok ? v0[t] : czero<S>());
+        W[0][a][1][b] = c0 * (ok ? v1[t] : czero<S>());
       }
     }
   }
@@ -1122,6 +1146,573 @@ __global__ __launch_bounds__(kWide[W].TW < 64 ? 64 : kWide[W].TW) void grover_te
   }
 }
 
+// The pre-contracted reflections' version of run_team (classes with bond caps up to 17).
+template <class S, int CM, int TW>
+__device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_base) {
+  using T = TeamShape<CM, TW>;
+  constexpr int D = T::D, KQ = T::KQ, KJ = T::KJ;
+  constexpr int PQ = T::PQ, RQ = T::RQ, PJ = T::PJ, RJ = T::RJ, RU = T::RU;
+  constexpr int SLOT = slot_elems(CM);
+  constexpr bool kMixed = sizeof(S) == sizeof(float);
+  constexpr int64_t WREC = wide_warm_doubles(CM);
+  const int tid = threadIdx.x;
+  const int team = tid / TW;
+  const int tl = tid % TW;
+  const int qc = tl / PQ, qh = tl % PQ;  // QR layout
+  const int jc = tl / PJ, jh = tl % PJ;  // Jacobi layout
+  const int base = tid - tl;             // first thread of the team (a lane, for TW <= 64)
+  const bool real = team < bdp->count;
+  // inst[] is indexed per lane: read it from memory, not from a register copy
+  const int me = bdp->inst[real ? team : 0];
+  TeamLds<S, CM, TW>& L = reinterpret_cast<TeamLds<S, CM, TW>*>(lds_base)[team];
+  // pre-contracted kernels only: the extra block behind the teams' TeamLds
+  PcLds<CM>& X = reinterpret_cast<PcLds<CM>*>(lds_base + T::TEAMS * sizeof(TeamLds<S, CM, TW>))[team];
+  InstDev* I = P.inst + me;
+  const int n = I->n;
+  const int M = I->M;
+  const int cap = I->cap < CM ? I->cap : CM;
+  const int64_t k = bdp->k;
+  cx<S>* arena = reinterpret_cast<cx<S>*>(P.arena) + I->site_off;
+  const uint64_t* W = P.marked + I->marked_off;
+  const double tol2 = P.trunc_tol * P.trunc_tol;
+  const double rank2 = P.rank_tol * P.rank_tol;
+  const double skip2 = P.skip_tol * P.skip_tol;
+  const bool sr = P.stoch_round != 0;
+  double* warm = P.warm ? reinterpret_cast<double*>(reinterpret_cast<char*>(P.warm) + I->warm_off) : nullptr;
+  // without warm starts the record loads read this instance's own records area: the site
+  // slots, which hold at least one record's worth of elements (never used)
+  const double* wdummy = reinterpret_cast<const double*>(reinterpret_cast<cx<S>*>(P.arena) + I->site_off);
+  // read once: a global load inside the sweeps would be waited for at its use
+  const uint64_t k_done0 = (uint64_t)I->k_done;
+  uint64_t rs_state = mix64(((uint64_t)me << 32) ^ (k_done0 * 0x9E3779B97F4A7C15ull) ^ (uint64_t)tl);
+
+  for (int l = tl; l < kBondStride; l += TW) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
+  lds_sync();
+
+  double f64 = 0.0, f32 = 0.0, drift = 0.0, truncw = 0.0;
+  int status = 0;
+
+  if (n == 1) {
+    // A single site: the reflection is the 2x2 operator c0 I + c1 P itself.
+    for (int64_t it = 0; it < k; ++it) {
+      for (int j = 0; j <= M; ++j) {
+        const bool diff = (j == M);
+        const int xb = diff ? 0 : (int)(W[j] & 1);
+        const double c0 = diff ? -1.0 : 1.0, c1 = diff ? 2.0 : -2.0;
+        const cx<S> a0 = arena[0], a1 = arena[D];
+        cx<S> o = czero<S>();
+        if (tl < 2) {
+          const cx<S> pa = proj_apply<S>(a0, a1, tl, diff, xb);
+          const cx<S> as = sel(a0, a1, tl);
+          o = {(S)c0 * as.re + (S)c1 * pa.re, (S)c0 * as.im + (S)c1 * pa.im};
+        }
+        const double nn = gsum<PQ>(tl < 2 ? norm2(up(o)) : 0.0);
+        if (diff) {
+          const double nr = sqrt(nn);
+          drift = fmax(drift, fabs(nr - 1.0));
+          if (!(nn > 0.0) || !isfinite(nn)) status |= GMPS_ST_NAN;
+          o = down<S>((1.0 / nr) * up(o));
+        }
+        team_sync_global();
+        if (real && tl < 2) arena[tl * D] = o;
+        team_sync_global();
+      }
+    }
+  } else {
+    // Pre-contracted reflections (see the option's description): a reflection
+    // c0 I + c1 sum_t |p_t><p_t| with product states p_t maps psi to c0 psi + c1 sum_t
+    // <p_t|psi> p_t, an MPS of bond chi + T (T terms) whose site blocks are diag(A_i, e_t(i))
+    // with e_t(i) the one-site factor of p_t. A left-to-right pass contracts the overlaps
+    // first, and c1 <p_t|psi> enters at the first site, so every term column of the QR tiles
+    // carries its physical weight: with unit-weight columns the QR would measure them against
+    // the rounding noise of psi's small Schmidt directions and keep spurious ranks. All M
+    // oracle terms go into one reflection when the bond cap is lossless (every state then has
+    // rank <= M+1) and chi + M fits the tile; otherwise each marked index is its own
+    // reflection (T = 1).
+    constexpr bool sumv = true;
+    const bool whole = sumv && I->whole != 0;
+    if (whole) {
+      for (int l = tl; l < n; l += TW) {
+        uint32_t bits = 0u;
+        for (int t = 0; t < M; ++t) bits |= (uint32_t)((W[t] >> (n - 1 - l)) & 1ull) << t;
+        X.xbits[l] = bits;
+      }
+      lds_sync();
+    }
+    constexpr int NV = (CM * CM + TW - 1) / TW;  // overlap elements per thread
+    static_assert(sizeof(L.u.q.W[1]) >= sizeof(X.ov), "second overlap buffer fits W[1]");
+    static_assert(sizeof(L.u.q.R) >= sizeof(L.u.q.W[0]), "second staging buffer fits R");
+    cd (*const ovb[2])[CM] = {X.ov, reinterpret_cast<cd (*)[CM]>(&L.u.q.W[1][0][0][0])};
+    cx<S> (*const stg[2])[CM][2][CM] = {L.u.q.W, reinterpret_cast<cx<S> (*)[CM][2][CM]>(&L.u.q.R[0][0])};
+    const int nref = whole ? 2 : M + 1;
+    for (int64_t it = 0; it < k; ++it) {
+      for (int j = 0; j < nref; ++j) {
+        const bool diff = (j == nref - 1);
+        const uint64_t xw = (diff || whole) ? 0ull : W[j];
+        const double c0 = diff ? -1.0 : 1.0, c1 = diff ? 2.0 : -2.0;
+        const int T = !sumv ? 0 : (diff || !whole) ? 1 : M;
+
+        if (sumv) {
+          // ---------------------------------------------- overlaps <p_t|psi>, left to right:
+          // v_t <- v_t A_i[:, p_t(i), :]; site tensors staged alternately in W[0] and in the
+          // R block (free until the QR sweep), rows alternately in the two overlap buffers,
+          // so one barrier per site orders every write after the reads it replaces
+          if (tl < T) X.ov[tl][0] = {1.0, 0.0};
+          TeamAPre<S, CM, TW> opre;
+          opre.load(arena, tl, L.bond[0], L.bond[1]);
+          for (int i = 0; i < n; ++i) {
+            const int chl = L.bond[i], chr = L.bond[i + 1];
+            const int xb = diff ? 0 : (int)((xw >> (n - 1 - i)) & 1ull);
+            const uint32_t tb = whole ? X.xbits[i] : (uint32_t)xb;
+            cx<S> (*const A)[CM][2][CM] = stg[i & 1];
+            opre.stage_a(A, tl, (S)1.0);
+            if (i + 1 < n) opre.load(arena + (int64_t)(i + 1) * SLOT, tl, L.bond[i + 1], L.bond[i + 2]);
+            lds_sync();
+            cd (*const vin)[CM] = ovb[i & 1];
+            cd (*const vout)[CM] = ovb[(i + 1) & 1];
+            for (int t = 0; t < NV; ++t) {
+              const int el = tl + t * TW;
+              const int tt = el / CM, col = el % CM;
+              if (tt < T && col < chr) {
+                const int xs = (int)((tb >> tt) & 1u);
+                cd acc = {0.0, 0.0};
+                for (int b = 0; b < chl; ++b) {
+                  const cd a0 = up(A[0][b][0][col]), a1 = up(A[0][b][1][col]);
+                  const cd av = diff ? kInvSqrt2 * (a0 + a1) : (xs ? a1 : a0);
+                  acc = cfma(acc, vin[tt][b], av);
+                }
+                vout[tt][col] = acc;
+              }
+            }
+            f64 += 8.0 * (double)T * chl * chr;
+          }
+          lds_sync();
+          if (tl < T) X.ovs[tl] = c1 * ovb[n & 1][tl][0];
+          lds_sync();
+        }
+
+        // ---------------------------------------------- QR sweep with the MPO fused
+        int r = 1;
+        if (tl == 0) {
+          L.rdim[0] = 1;
+          // the first site's tile is [A | P A] itself: R = [1 1] over the two MPO blocks
+          // (pre-contracted: [A | e_1 .. e_T], R = [1, c1 <p_1|psi>, .., c1 <p_T|psi>])
+          L.u.q.R[0][0] = {1.0, 0.0};
+          if (sumv)
+            for (int t = 0; t < T; ++t) L.u.q.R[0][1 + t] = X.ovs[t];
+          else
+            L.u.q.R[0][1] = {1.0, 0.0};
+        }
+        TeamAPre<S, CM, TW> apre;
+        apre.load(arena, tl, L.bond[0], L.bond[1]);
+        lds_sync();
+        for (int i = 0; i < n; ++i) {
+          const int chl = L.bond[i], chr = L.bond[i + 1];
+          const bool first = (i == 0), last = (i == n - 1);
+          const int xb = diff ? 0 : (int)((xw >> (n - 1 - i)) & 1ull);
+          // qubit values of the terms at this site (oracle terms; unused by the diffusion)
+          const uint32_t tb = whole ? X.xbits[i] : (uint32_t)xb;
+          const int Dl = first ? 1 : (sumv ? chl + T : 2 * chl);
+          const int Dr = last ? 1 : (sumv ? chr + T : 2 * chr);
+          cx<S>* slot = arena + (int64_t)i * SLOT;
+          if (sumv) {
+            apre.stage_a(L.u.q.W, tl, (S)(last ? c0 : 1.0));
+          } else {
+            apre.stage(L.u.q.W, tl, diff, xb, (S)(last ? c0 : 1.0), (S)(last ? c1 : 1.0));
+          }
+          if (i + 1 < n) apre.load(arena + (int64_t)(i + 1) * SLOT, tl, L.bond[i + 1], L.bond[i + 2]);
+          lds_sync();
+          // X = R_{i-1} * MPO(A_i): this slot's column, rows (a, s) = part + PQ*e
+          cd x[RQ];
+          if (!sumv) {
+            const int beta = (!last && qc >= chr) ? 1 : 0;
+            const int bcol = qc - beta * chr;
+#pragma unroll
+            for (int e = 0; e < RQ; ++e) {
+              const int row = qh + PQ * e;
+              const int a = row >> 1, s = row & 1;
+              cx<S> acc = czero<S>();
+              if (row < 2 * r && qc < Dr) {
+                // the last site sums both MPO blocks into its one column
+#pragma unroll
+                for (int bl = 0; bl < 2; ++bl) {
+                  if (last || bl == beta) {
+#pragma unroll
+                    for (int ap = 0; ap < CM; ++ap)
+                      if (ap < chl) acc = cfma(acc, down<S>(L.u.q.R[a][bl * chl + ap]), L.u.q.W[bl][ap][s][bcol]);
+                  }
+                }
+              }
+              x[e] = up(acc);
+            }
+          } else {
+            // columns < chr (or the last site's one column): R_A A_i in the storage
+            // precision; term columns chr + t: R[:, chl + t] e_t(s), exact in FP64 (the last
+            // site adds them to its one column)
+            const bool acol = last || qc < chr;
+            const int ct = qc - chr;
+#pragma unroll
+            for (int e = 0; e < RQ; ++e) {
+              const int row = qh + PQ * e;
+              const int a = row >> 1, s = row & 1;
+              cd xv = {0.0, 0.0};
+              if (row < 2 * r && qc < Dr) {
+                if (acol) {
+                  const int bcol = last ? 0 : qc;
+                  cx<S> acc = czero<S>();
+#pragma unroll
+                  for (int ap = 0; ap < CM; ++ap)
+                    if (ap < chl) acc = cfma(acc, down<S>(L.u.q.R[a][ap]), L.u.q.W[0][ap][s][bcol]);
+                  xv = up(acc);
+                  if (last) {
+                    for (int t = 0; t < T; ++t) {
+                      const double es = diff ? kInvSqrt2 : ((int)((tb >> t) & 1u) == s ? 1.0 : 0.0);
+                      xv = xv + es * L.u.q.R[a][chl + t];
+                    }
+                  }
+                } else {
+                  const double es = diff ? kInvSqrt2 : ((int)((tb >> ct) & 1u) == s ? 1.0 : 0.0);
+                  xv = es * L.u.q.R[a][chl + ct];
+                }
+              }
+              x[e] = xv;
+            }
+          }
+          if (sumv) {
+            const double macs = (double)r * chl * 2.0 * (last ? 1 : chr);
+            if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+          } else {
+            const double macs = (double)r * Dl * 2.0 * Dr;
+            if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+          }
+          if (last) {
+            if (real && qc == 0) {
+#pragma unroll
+              for (int e = 0; e < RQ; ++e) {
+                const int row = qh + PQ * e;
+                if (row < 2 * r) slot[(row >> 1) * 2 * D + (row & 1) * D] = store_cast<S>(x[e], rs_state, sr);
+              }
+            }
+            if (tl == 0) {
+              L.rdim[n - 1] = r;
+              L.rdim[n] = 1;
+            }
+            break;
+          }
+          const int m = 2 * r;
+          cd q[RQ];
+          double qdrop = 0.0;
+          int kr;
+          if constexpr (TW <= 64)
+            kr = team_qr_wave<TW, PQ, RQ, KQ>(x, q, base, qc, qh, m, Dr, chr, rank2, &qdrop, L.u.q.V, L.u.q.tau);
+          else
+            kr = team_qr_lds<PQ, RQ, KQ>(x, q, qc, qh, m, Dr, chr, rank2, &qdrop, L.u.q.V, L.u.q.tau, L.colv);
+          truncw = fmax(truncw, qdrop);
+          {
+            const double mm = m, cc = Dr, kk = kr;
+            f64 += 8.0 * (2.0 * mm * cc * kk - (mm + cc) * kk * kk + 2.0 * kk * kk * kk / 3.0) +
+                   8.0 * (2.0 * mm * kk * kk - 2.0 * kk * kk * kk / 3.0);
+          }
+          if (real && qc < kr) {
+#pragma unroll
+            for (int e = 0; e < RQ; ++e) {
+              const int row = qh + PQ * e;
+              if (row < m) slot[(row >> 1) * 2 * D + (row & 1) * D + qc] = store_cast<S>(q[e], rs_state, sr);
+            }
+          }
+          if (qc < Dr) {
+#pragma unroll
+            for (int e = 0; e < RQ; ++e) {
+              const int row = qh + PQ * e;
+              if (row < kr) L.u.q.R[row][qc] = x[e];
+            }
+          }
+          if (tl == 0) L.rdim[i + 1] = kr;
+          r = kr;
+          lds_sync();
+        }
+        // the QR sweep's site tensors are read by every wave of the team from here on
+        team_sync_global();
+
+        // ---------------------------------------------- truncated-SVD sweep
+        // At site i the tile is M = Q_i (U Sigma)_{i+1} reshaped (r_i, 2 chi'); Jacobi runs on
+        // the r_i columns of M^H: M^H J = V Sigma with J = U, so V^H = Sigma^{-1} (M^H J)^H
+        // stays in site i and U Sigma = J Sigma moves left.
+        if (tl == 0) L.u.s.Y[0][0] = {1.0, 0.0};
+        TeamQPre<S, KQ, CM, TW> qpre;
+        TeamWPre<KJ, TW> wpre;
+        qpre.load(arena + (int64_t)(n - 1) * SLOT, tl, L.rdim[n - 1], L.rdim[n]);
+        wpre.load(warm ? warm + ((int64_t)j * n + (n - 1)) * WREC : wdummy, warm != nullptr, tl, (L.rdim[n - 1] + 1) & ~1);
+        for (int i = n - 1; i >= 1; --i) {
+          const int ri = L.rdim[i], rn = L.rdim[i + 1];
+          const int chn = L.bond[i + 1];
+          const int c = 2 * chn;
+          const int ncj = (ri + 1) & ~1;
+          cx<S>* slot = arena + (int64_t)i * SLOT;
+          double* wrec = warm ? warm + ((int64_t)j * n + i) * WREC : nullptr;
+          const bool use_warm = wrec && wpre.r() == ncj;
+          // the stored unitary is a product of exact rotations, so its unitarity drifts by
+          // ~1e-16 per use; one Newton-Schulz step every 64 iterations keeps it below ~1e-13
+          const bool renorm_warm = use_warm && ((k_done0 + (uint64_t)it) & 63ull) == 0ull;
+          qpre.stage(&L.u.s.Q[0][0][0], tl);
+          if (use_warm) wpre.stage(&L.u.s.W[0][0], tl);
+          if (i - 1 >= 1) {
+            qpre.load(arena + (int64_t)(i - 1) * SLOT, tl, L.rdim[i - 1], L.rdim[i]);
+            wpre.load(warm ? warm + ((int64_t)j * n + (i - 1)) * WREC : wdummy, warm != nullptr, tl,
+                      (L.rdim[i - 1] + 1) & ~1);
+          }
+          lds_sync();
+          // column jc of M^H: M^H[(s, jj)][a] = conj(sum_b Q[a][s][b] Y[b][jj])
+          cd a[RJ];
+#pragma unroll
+          for (int e = 0; e < RJ; ++e) {
+            const int row = jh + PJ * e;
+            const int s = row >= chn ? 1 : 0;
+            const int jj = row - s * chn;
+            cx<S> acc = czero<S>();
+            if (jc < ri && row < c) {
+#pragma unroll
+              for (int b = 0; b < KQ; ++b)
+                if (b < rn) acc = cfma(acc, L.u.s.Q[jc][s][b], down<S>(L.u.s.Y[b][jj]));
+            }
+            a[e] = conj(up(acc));
+          }
+          {
+            const double macs = (double)ri * 2.0 * rn * chn;
+            if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+          }
+          if (renorm_warm) {
+            // one Newton-Schulz polar step W <- W (3I - W^H W) / 2 (error e -> O(e^2))
+            cd* WG = &L.u.s.XU[0][0][0];  // KJ x KJ, row-major
+            for (int e = tl; e < KJ * KJ; e += TW) {
+              const int ra = e / KJ, ca = e % KJ;
+              cd g = {0.0, 0.0};
+              for (int b = 0; b < ncj; ++b) g = g + cmulc(L.u.s.W[b][ra], L.u.s.W[b][ca]);
+              WG[e] = g;
+            }
+            lds_sync();
+            constexpr int NW = (KJ * KJ + TW - 1) / TW;
+            cd wn[NW];
+#pragma unroll
+            for (int t = 0; t < NW; ++t) {
+              const int e = tl + t * TW;
+              const int ra = e / KJ, ca = e % KJ;
+              cd acc = {0.0, 0.0};
+              if (e < KJ * KJ)
+                for (int b = 0; b < ncj; ++b) acc = cfma(acc, L.u.s.W[ra][b], WG[b * KJ + ca]);
+              wn[t] = (e < KJ * KJ) ? 1.5 * L.u.s.W[ra][ca] - 0.5 * acc : cd{0.0, 0.0};
+            }
+            lds_sync();
+#pragma unroll
+            for (int t = 0; t < NW; ++t) {
+              const int e = tl + t * TW;
+              if (e < KJ * KJ) L.u.s.W[e / KJ][e % KJ] = wn[t];
+            }
+            lds_sync();
+          }
+          cd uu[RU];
+          if (use_warm) {
+            // start from the previous iteration's unitary: M^H <- M^H W
+            if (jc < KJ) {
+#pragma unroll
+              for (int e = 0; e < RJ; ++e) L.u.s.XA[0][jc][jh + PJ * e] = a[e];
+            }
+            lds_sync();
+#pragma unroll
+            for (int e = 0; e < RJ; ++e) {
+              const int row = jh + PJ * e;
+              cd acc = {0.0, 0.0};
+              if (jc < ncj)
+                for (int b = 0; b < ncj; ++b) acc = cfma(acc, L.u.s.XA[0][b][row], L.u.s.W[b][jc]);
+              a[e] = acc;
+            }
+#pragma unroll
+            for (int e = 0; e < RU; ++e) {
+              const int row = jh + PJ * e;
+              uu[e] = (jc < ncj && row < ncj) ? L.u.s.W[row][jc] : cd{0.0, 0.0};
+            }
+            lds_sync();
+          } else {
+#pragma unroll
+            for (int e = 0; e < RU; ++e) uu[e] = {(jh + PJ * e == jc && jc < ncj) ? 1.0 : 0.0, 0.0};
+          }
+          int sweeps;
+          if constexpr (TW <= 64)
+            sweeps = team_jacobi_wave<TW, PJ, RJ, RU>(a, uu, base, jc, jh, ncj, kJacobiTol2, skip2, P.max_sweeps);
+          else
+            sweeps = team_jacobi_lds<PJ, RJ, RU, KJ, T::NBUF>(a, uu, jc, jh, ncj, kJacobiTol2, skip2, P.max_sweeps,
+                                                              L.u.s.XA, L.u.s.XU, L.u.s.XN, L.colv, L.colf);
+          f64 += (double)sweeps * ri * (ri - 1) / 2.0 * 56.0 * c;
+          // singular values, truncation and the kept order
+          const bool colok = jc < ncj;
+          double sg = 0.0;
+#pragma unroll
+          for (int e = 0; e < RJ; ++e) sg += norm2(a[e]);
+          sg = gsum<PJ>(sg);
+          // kept columns stay in their index order (so the bond basis, and the next warm
+          // start, does not jump when Schmidt values are degenerate); dropped ones follow
+          double stot, dropped;
+          int chi_new, pos;
+          bool keep;
+          if constexpr (TW <= 64) {
+            const double mine = colok ? sg : 0.0;
+            const double smax = tmax<TW>(mine);
+            stot = tsum<TW>(jh == 0 ? mine : 0.0);
+            const int above = (int)tsum<TW>((jh == 0 && mine > 0.0 && mine >= tol2 * smax) ? 1.0 : 0.0);
+            int rk = 0;
+            for (int o = 0; o < ncj; ++o) {
+              const double v = shfl_f64(mine, base + o * PJ);
+              rk += (v > sg || (v == sg && o < jc)) ? 1 : 0;
+            }
+            chi_new = above < cap ? above : cap;
+            if (chi_new < 1) chi_new = 1;
+            keep = colok && rk < chi_new;
+            const uint64_t kept = tballot<TW>(jh == 0 && keep, base);
+            const int nk = __popcll(kept & ((1ull << (base + jc * PJ)) - 1ull));
+            pos = keep ? nk : chi_new + (jc - nk);
+            dropped = tsum<TW>((jh == 0 && colok && !keep) ? sg : 0.0);
+          } else {
+            if (jh == 0) L.colv[jc] = colok ? sg : 0.0;
+            lds_sync();
+            double smax = 0.0;
+            stot = 0.0;
+            for (int o = 0; o < ncj; ++o) {
+              const double v = L.colv[o];
+              smax = fmax(smax, v);
+              stot += v;
+            }
+            int above = 0, rk = 0;
+            for (int o = 0; o < ncj; ++o) {
+              const double v = L.colv[o];
+              above += (v > 0.0 && v >= tol2 * smax) ? 1 : 0;
+              rk += (v > sg || (v == sg && o < jc)) ? 1 : 0;
+            }
+            chi_new = above < cap ? above : cap;
+            if (chi_new < 1) chi_new = 1;
+            if (jh == 0) L.colr[jc] = colok ? rk : KJ + jc;
+            lds_sync();
+            dropped = 0.0;
+            int nk = 0, nd = 0;
+            for (int o = 0; o < ncj; ++o) {
+              const bool ko = L.colr[o] < chi_new;
+              if (!ko) dropped += L.colv[o];
+              if (o < jc) {
+                nk += ko ? 1 : 0;
+                nd += ko ? 0 : 1;
+              }
+            }
+            keep = colok && rk < chi_new;
+            pos = keep ? nk : chi_new + nd;
+          }
+          if (stot > 0.0) truncw = fmax(truncw, dropped / stot);
+          if (!isfinite(stot)) status |= GMPS_ST_NAN;
+          if (wrec && real) {
+            // keep J with its columns in the kept order for the next iteration
+            if (colok) {
+#pragma unroll
+              for (int e = 0; e < RU; ++e) {
+                const int row = jh + PJ * e;
+                if (row < ncj) {
+                  wrec[2 + 2 * (row * KJ + pos)] = uu[e].re;
+                  wrec[3 + 2 * (row * KJ + pos)] = uu[e].im;
+                }
+              }
+            }
+            if (tl == 0) wrec[0] = (double)ncj;
+          }
+          if (keep) {
+            const double rs = rsqrt_acc(sg);  // 1/sigma
+            if (real) {
+#pragma unroll
+              for (int e = 0; e < RJ; ++e) {
+                const int row = jh + PJ * e;
+                if (row < c) {
+                  const int s = row >= chn ? 1 : 0;
+                  const int jp = row - s * chn;
+                  slot[pos * 2 * D + s * D + jp] = store_cast<S>(rs * conj(a[e]), rs_state, sr);
+                }
+              }
+            }
+#pragma unroll
+            for (int e = 0; e < RU; ++e) {
+              const int row = jh + PJ * e;
+              if (row < ri) L.u.s.Y[row][pos] = (sg * rs) * uu[e];
+            }
+          }
+          if (tl == 0) L.bond[i] = chi_new;
+          lds_sync();
+        }
+        // ---------------------------------------------- site 0 (holds the norm)
+        team_sync_global();
+        {
+          const int rn = L.rdim[1], chn = L.bond[1];
+          cx<S>* slot = arena;
+          cx<S> acc = czero<S>();
+          const bool act = tl < 2 * chn;
+          const int s = tl >= chn ? 1 : 0;
+          const int jj = tl - s * chn;
+          if (act) {
+#pragma unroll
+            for (int b = 0; b < KQ; ++b)
+              if (b < rn) acc = cfma(acc, slot[s * D + b], down<S>(L.u.s.Y[b][jj]));
+          }
+          const double macs = 2.0 * rn * chn;
+          if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+          double nn = 0.0;
+          if constexpr (TW <= 64) {
+            nn = tsum<TW>(act ? norm2(up(acc)) : 0.0);
+          } else {
+            L.colv[tl] = act ? norm2(up(acc)) : 0.0;
+            lds_sync();
+            for (int o = 0; o < 2 * chn; ++o) nn += L.colv[o];
+          }
+          if (!isfinite(nn) || !(nn > 0.0)) status |= GMPS_ST_NAN;
+          const double nr = sqrt(nn);
+          if (diff) drift = fmax(drift, fabs(nr - 1.0));
+          const cx<S> out = store_cast<S>((diff ? 1.0 / nr : 1.0) * up(acc), rs_state, sr);
+          lds_sync();
+          if (real && act) slot[s * D + jj] = out;
+          if (tl == 0) L.bond[0] = 1;
+          team_sync_global();
+        }
+      }
+    }
+  }
+
+  // ------------------------------------------------------------------ write back
+  if (real) {
+    for (int l = tl; l < kBondStride; l += TW) P.bonds[(int64_t)me * kBondStride + l] = L.bond[l];
+    if (tl == 0) {
+      I->k_done += k;
+      I->flops64 += f64;
+      I->flops32 += f32;
+      I->drift = fmax(I->drift, drift);
+      I->trunc_w = fmax(I->trunc_w, truncw);
+      if (drift > 1e-3) status |= GMPS_ST_DRIFT;
+      if (truncw > 1e-8) status |= GMPS_ST_TRUNC;
+      I->status |= status;
+    }
+  }
+  team_sync_global();
+}
+
+// Persistent kernel of one team class W: a workgroup takes bundles from the class's queue
+// until it is empty.
+// Persistent kernel of the pre-contracted reflections for team class W.
+template <class S, int W>
+__global__ __launch_bounds__(kWide[W].TW < 64 ? 64 : kWide[W].TW) void grover_team_pc_kernel(IterParams P) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ unsigned int next_bundle;
+  for (;;) {
+    if (threadIdx.x == 0) next_bundle = atomicAdd(&P.queue->next, 1u);
+    lds_sync();
+    const unsigned int bi = next_bundle;
+    lds_sync();
+    if ((int)bi >= P.queue->nbundles) break;
+    run_team_pc<S, kWide[W].CM, kWide[W].TW>(P, P.bundles + bi, lds);
+  }
+}
+
 // Launch and occupancy of class W, defined in the class's own translation unit.
 template <int W>
 hipError_t launch_team_w(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st);
@@ -1143,6 +1734,29 @@ hipError_t occupancy_team_w(bool mixed, size_t lds, int* blocks_per_cu);
     constexpr int nt = kWide[W].TW < 64 ? 64 : kWide[W].TW;                                           \
     return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_team_kernel<float, W>, nt, lds) \
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_team_kernel<double, W>, nt, lds); \
+  }
+
+// The pre-contracted kernels of a class (classes with bond caps up to 17).
+template <int W>
+hipError_t launch_team_pc_w(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st);
+template <int W>
+hipError_t occupancy_team_pc_w(bool mixed, size_t lds, int* blocks_per_cu);
+
+#define GMPS_TEAM_PC_CLASS(W)                                                                        \
+  template <>                                                                                        \
+  hipError_t launch_team_pc_w<W>(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st) { \
+    constexpr int nt = kWide[W].TW < 64 ? 64 : kWide[W].TW;                                           \
+    if (mixed)                                                                                       \
+      grover_team_pc_kernel<float, W><<<grid, nt, lds, st>>>(P);                                      \
+    else                                                                                             \
+      grover_team_pc_kernel<double, W><<<grid, nt, lds, st>>>(P);                                     \
+    return hipGetLastError();                                                                        \
+  }                                                                                                  \
+  template <>                                                                                        \
+  hipError_t occupancy_team_pc_w<W>(bool mixed, size_t lds, int* blocks_per_cu) {                   \
+    constexpr int nt = kWide[W].TW < 64 ? 64 : kWide[W].TW;                                           \
+    return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_team_pc_kernel<float, W>, nt, lds) \
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_team_pc_kernel<double, W>, nt, lds); \
   }
 
 }  // namespace gmps

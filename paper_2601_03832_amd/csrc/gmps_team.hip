@@ -10,27 +10,49 @@ int team_per_bundle(int cls) {
 }
 
 // every class fits the 160 KiB of LDS of a gfx950 compute unit (with the kernel's own
-// bundle index and the FP64 storage type, the larger of the two)
-static_assert(sizeof(TeamLds<double, 2, 16>) * 4 <= 160 * 1024 - 64, "LDS");
-static_assert(sizeof(TeamLds<double, 3, 32>) * 2 <= 160 * 1024 - 64, "LDS");
-static_assert(sizeof(TeamLds<double, 8, 64>) <= 160 * 1024 - 64, "LDS");
-static_assert(sizeof(TeamLds<double, 17, 192>) <= 160 * 1024 - 64, "LDS");
+// bundle index and the FP64 storage type, the larger of the two), with the pre-contracted
+// reflections' block where the class has them
+static_assert((sizeof(TeamLds<double, 2, 16>) + sizeof(PcLds<2>)) * 4 <= 160 * 1024 - 64, "LDS");
+static_assert((sizeof(TeamLds<double, 3, 32>) + sizeof(PcLds<3>)) * 2 <= 160 * 1024 - 64, "LDS");
+static_assert(sizeof(TeamLds<double, 5, 64>) + sizeof(PcLds<5>) <= 160 * 1024 - 64, "LDS");
+static_assert(sizeof(TeamLds<double, 8, 64>) + sizeof(PcLds<8>) <= 160 * 1024 - 64, "LDS");
+static_assert(sizeof(TeamLds<double, 17, 192>) + sizeof(PcLds<17>) <= 160 * 1024 - 64, "LDS");
 static_assert(sizeof(TeamLds<double, 32, 256>) <= 160 * 1024 - 64, "LDS");
 
-size_t team_lds_bytes(bool mixed, int cls) {
+template <int W>
+static size_t class_lds(bool mixed, bool pc) {
+  constexpr int CM = kWide[W].CM, TW = kWide[W].TW;
+  constexpr int teams = TeamShape<CM, TW>::TEAMS;
+  size_t per = mixed ? sizeof(TeamLds<float, CM, TW>) : sizeof(TeamLds<double, CM, TW>);
+  if (pc && team_pc_class(W)) per += sizeof(PcLds<CM>);
+  return per * teams;
+}
+
+size_t team_lds_bytes(bool mixed, bool pc, int cls) {
   switch (cls - kWideBase) {
-    case 0: return (mixed ? sizeof(TeamLds<float, 2, 16>) : sizeof(TeamLds<double, 2, 16>)) * 4;
-    case 1: return (mixed ? sizeof(TeamLds<float, 3, 32>) : sizeof(TeamLds<double, 3, 32>)) * 2;
-    case 2: return mixed ? sizeof(TeamLds<float, 5, 64>) : sizeof(TeamLds<double, 5, 64>);
-    case 3: return mixed ? sizeof(TeamLds<float, 8, 64>) : sizeof(TeamLds<double, 8, 64>);
-    case 4: return mixed ? sizeof(TeamLds<float, 17, 192>) : sizeof(TeamLds<double, 17, 192>);
-    case 5: return mixed ? sizeof(TeamLds<float, 32, 256>) : sizeof(TeamLds<double, 32, 256>);
+    case 0: return class_lds<0>(mixed, pc);
+    case 1: return class_lds<1>(mixed, pc);
+    case 2: return class_lds<2>(mixed, pc);
+    case 3: return class_lds<3>(mixed, pc);
+    case 4: return class_lds<4>(mixed, pc);
+    case 5: return class_lds<5>(mixed, pc);
   }
   return 0;
 }
 
-hipError_t launch_team(bool mixed, int cls, const IterParams& P, int grid, size_t lds, hipStream_t st) {
-  switch (cls - kWideBase) {
+hipError_t launch_team(bool mixed, bool pc, int cls, const IterParams& P, int grid, size_t lds, hipStream_t st) {
+  const int w = cls - kWideBase;
+  if (pc && w >= 0 && w < kNumWide && team_pc_class(w)) {
+    switch (w) {
+      case 0: return launch_team_pc_w<0>(mixed, P, grid, lds, st);
+      case 1: return launch_team_pc_w<1>(mixed, P, grid, lds, st);
+      case 2: return launch_team_pc_w<2>(mixed, P, grid, lds, st);
+      case 3: return launch_team_pc_w<3>(mixed, P, grid, lds, st);
+      case 4: return launch_team_pc_w<4>(mixed, P, grid, lds, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  switch (w) {
     case 0: return launch_team_w<0>(mixed, P, grid, lds, st);
     case 1: return launch_team_w<1>(mixed, P, grid, lds, st);
     case 2: return launch_team_w<2>(mixed, P, grid, lds, st);
@@ -41,8 +63,19 @@ hipError_t launch_team(bool mixed, int cls, const IterParams& P, int grid, size_
   return hipErrorInvalidValue;
 }
 
-hipError_t team_occupancy(bool mixed, int cls, size_t lds, int* blocks_per_cu) {
-  switch (cls - kWideBase) {
+hipError_t team_occupancy(bool mixed, bool pc, int cls, size_t lds, int* blocks_per_cu) {
+  const int w = cls - kWideBase;
+  if (pc && w >= 0 && w < kNumWide && team_pc_class(w)) {
+    switch (w) {
+      case 0: return occupancy_team_pc_w<0>(mixed, lds, blocks_per_cu);
+      case 1: return occupancy_team_pc_w<1>(mixed, lds, blocks_per_cu);
+      case 2: return occupancy_team_pc_w<2>(mixed, lds, blocks_per_cu);
+      case 3: return occupancy_team_pc_w<3>(mixed, lds, blocks_per_cu);
+      case 4: return occupancy_team_pc_w<4>(mixed, lds, blocks_per_cu);
+    }
+    return hipErrorInvalidValue;
+  }
+  switch (w) {
     case 0: return occupancy_team_w<0>(mixed, lds, blocks_per_cu);
     case 1: return occupancy_team_w<1>(mixed, lds, blocks_per_cu);
     case 2: return occupancy_team_w<2>(mixed, lds, blocks_per_cu);

@@ -3,4 +3,5 @@
 
 namespace gmps {
 GMPS_TEAM_CLASS(1)
+GMPS_TEAM_PC_CLASS(1)
 }  // namespace gmps

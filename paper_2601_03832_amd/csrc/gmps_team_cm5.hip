@@ -3,4 +3,5 @@
 
 namespace gmps {
 GMPS_TEAM_CLASS(2)
+GMPS_TEAM_PC_CLASS(2)
 }  // namespace gmps

@@ -42,7 +42,8 @@ class GmpsOptions(ctypes.Structure):
     _fields_ = [("trunc_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("round_mode", ctypes.c_int32), ("jacobi_warm", ctypes.c_int32),
-                ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("kernel", ctypes.c_int32), ("precontract", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class GmpsError(RuntimeError):
@@ -155,7 +156,7 @@ class Batch:
     def __init__(self, instances: Sequence, precision: str = "fp64", trunc_tol: float = 0.0,
                  max_sweeps: int = 0, waves_per_cu: int = 0, use_graph: bool = True, stream=None,
                  device=None, stochastic_rounding: bool = True, jacobi_warm: Optional[bool] = None,
-                 kernel: str = "auto"):
+                 kernel: str = "auto", precontract: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libgmps needs a ROCm GPU; none is visible")
@@ -180,6 +181,7 @@ class Batch:
         opt.round_mode = 1 if stochastic_rounding else -1
         opt.jacobi_warm = 0 if jacobi_warm is None else (1 if jacobi_warm else -1)
         opt.kernel = KERNELS[kernel]
+        opt.precontract = 1 if precontract else -1
         self._opt = opt
         h = ctypes.c_void_p()
         rc = self.lib.gmps_create(ctypes.byref(h), self._arr, self.B, _ptr(self._marked, ctypes.c_uint64), prec,

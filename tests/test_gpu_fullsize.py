@@ -24,10 +24,11 @@ def say(msg):
     sys.stdout.flush()
 
 
-def test_batched_mixed_full_size(gpu):
-    say("case: 4096-instance mixed batch at full k")
+@pytest.mark.parametrize("pc", [False, True], ids=["mpo", "precontract"])
+def test_batched_mixed_full_size(gpu, pc):
+    say("case: 4096-instance mixed batch at full k, precontract=%s" % pc)
     w = inputs.config_c4()
-    b = gmps.Batch(w.instances, "mixed")
+    b = gmps.Batch(w.instances, "mixed", precontract=pc)
     b.init_uniform()
     b.iterate([i.k for i in w.instances])
     p = b.marked_prob(allow_numeric=True)

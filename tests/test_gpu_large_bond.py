@@ -30,15 +30,16 @@ def bound_ok(prof, n, M):
     return all(prof[l] <= min(2 ** l, 2 ** (n - l), M + 1) for l in range(1, n))
 
 
+@pytest.mark.parametrize("pc", [False, True], ids=["mpo", "precontract"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_large_cap_small_n_statevector(gpu, precision):
-    say("case: large caps at small n, %s" % precision)
+def test_large_cap_small_n_statevector(gpu, precision, pc):
+    say("case: large caps at small n, %s, precontract=%s" % (precision, pc))
     rng = inputs.SplitMix64(4711)
     insts = []
     for n, M, extra in ((9, 7, 1), (10, 9, 2), (10, 16, 1), (11, 13, 4), (12, 24, 3), (12, 31, 1), (6, 5, 30)):
         W = inputs.draw_marked(n, M, rng)
         insts.append(inputs.Instance(n, W, inputs.k_rule(n, M), M + extra))
-    b = gmps.Batch(insts, precision, kernel="team")
+    b = gmps.Batch(insts, precision, kernel="team", precontract=pc)
     b.init_uniform()
     b.iterate([i.k for i in insts])
     p = b.marked_prob()
@@ -62,13 +63,14 @@ def test_large_cap_small_n_statevector(gpu, precision):
         assert d["status"][i] == 0
 
 
+@pytest.mark.parametrize("pc", [False, True], ids=["mpo", "precontract"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_n40_m16_prefix(gpu, precision):
+def test_n40_m16_prefix(gpu, precision, pc):
     k = 6
-    say("case: n=40 M=16 cap 32, 8 instances, k=%d, %s" % (k, precision))
+    say("case: n=40 M=16 cap 32, 8 instances, k=%d, %s, precontract=%s" % (k, precision, pc))
     w = inputs.config_c5(count=8, k=k)
     insts = w.instances
-    b = gmps.Batch(insts, precision)
+    b = gmps.Batch(insts, precision, precontract=pc)
     b.init_uniform()
     b.iterate(k)
     p = b.marked_prob()

@@ -20,10 +20,18 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-10, "mixed": 1e-6}
 
 
-@pytest.fixture(params=["group", "team"])
+@pytest.fixture(params=["group", "team", "team-pc"])
 def kernel(request):
-    """Both iterate kernels run every parity case."""
+    """Both iterate kernels, and the team kernel's pre-contracted reflections, run every
+    parity case."""
     return request.param
+
+
+def batch_kw(kernel):
+    """Batch keywords of a kernel variant name."""
+    if kernel == "team-pc":
+        return {"kernel": "team", "precontract": True}
+    return {"kernel": kernel}
 
 
 def say(msg):
@@ -31,9 +39,8 @@ def say(msg):
     sys.stdout.flush()
 
 
-def run(instances, precision, k=None, **kw):
-    kw.setdefault("kernel", "auto")
-    b = gmps.Batch(instances, precision, **kw)
+def run(instances, precision, k=None, kernel="auto", **kw):
+    b = gmps.Batch(instances, precision, **batch_kw(kernel), **kw)
     b.init_uniform()
     b.iterate([i.k for i in instances] if k is None else k)
     return b
@@ -109,7 +116,7 @@ def test_edge_cases(gpu, kernel):
 def test_iterate_is_additive(gpu, kernel):
     say("case: additivity 5+7 == 12, %s" % kernel)
     insts = inputs.random_batch(9, 8, 13, (1, 2), seed=8)
-    a = gmps.Batch(insts, "fp64", kernel=kernel)
+    a = gmps.Batch(insts, "fp64", **batch_kw(kernel))
     a.init_uniform()
     a.iterate(5)
     a.iterate(7)
@@ -176,3 +183,30 @@ def test_bad_arguments_through_binding(gpu):
         b.iterate([1, 2, 3])
     with pytest.raises(gmps.GmpsError):
         b.amplitudes(0, [1 << 40])
+
+
+def test_precontract_needs_the_team_kernel(gpu):
+    say("case: pre-contraction on the lane-group kernel is refused")
+    insts = inputs.random_batch(2, 4, 6, (1,), seed=3)
+    with pytest.raises(gmps.GmpsError) as e:
+        gmps.Batch(insts, "fp64", kernel="group", precontract=True)
+    assert e.value.code == gmps.GMPS_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_precontract_matches_mpo_path(gpu, precision):
+    say("case: pre-contracted vs bond-2 MPO reflections, ragged n 3..16, M 1..6, %s" % precision)
+    insts = inputs.random_batch(41, 3, 16, (1, 2, 3, 4, 5, 6), seed=57, cap_extra=1)
+    a = run(insts, precision, kernel="team")
+    c = run(insts, precision, kernel="team-pc")
+    pa, pc = a.marked_prob(), c.marked_prob()
+    for i, inst in enumerate(insts):
+        ex = cf.p_marked(inst.n, inst.M, inst.k)
+        assert abs(pc[i] - ex) < TOL[precision], (i, inst.n, inst.M, inst.k)
+    assert np.max(np.abs(pa - pc)) < 2 * TOL[precision]
+    da, dc = a.diagnostics(), c.diagnostics()
+    # the whole oracle is one recompression: fewer flops for M >= 2
+    for i, inst in enumerate(insts):
+        assert dc["bond_dims"][i] == da["bond_dims"][i] or precision == "mixed", i
+        if inst.M >= 3 and inst.n >= 8:
+            assert dc["flops64"][i] + dc["flops32"][i] < da["flops64"][i] + da["flops32"][i], i
