@@ -143,13 +143,13 @@ def cpu_baseline(w, iters_per_stratum: int = 100):
                       % (iters_per_stratum, len(strata), wall, est)}
 
 
-def c5_prefix(k: int, kernel: str):
+def c5_prefix(k: int, kernel: str, precontract: bool = False):
     """256 instances at n=40, M=16, cap 32 (bond 17), mixed, for a prefix of k iterations:
     the full k=205887 takes hours, so the rate and the accuracy are reported on the prefix."""
     import torch
     from paper_2601_03832_amd import gmps
     w = inputs.config_c5(k=k)
-    b = gmps.Batch(w.instances, w.precision, kernel=kernel)
+    b = gmps.Batch(w.instances, w.precision, kernel=kernel, precontract=precontract)
     b.init_uniform()
     b.iterate(k)  # warm (graph capture)
     torch.cuda.synchronize()
@@ -164,12 +164,43 @@ def c5_prefix(k: int, kernel: str):
         _, hits = b.sample(shots, w.shot_seed)
         frac[str(shots)] = float(np.mean(hits / shots))
     kms = b.last_iterate_ms()
+    d = b.diagnostics()
     b.close()
     n_inst = len(w.instances)
     return {"value": n_inst * k / (t1 - t0), "unit": "iterations/s", "instances": n_inst, "k_prefix": k,
             "seconds": t1 - t0, "kernel_ms": kms, "max_abs_err_p": err, "p_exact": exact_p(40, 16, k),
-            "mean_hit_fraction": frac,
-            "note": "256 x (n=40, M=16, cap 32) for the first %d of k=205887 iterations, mixed; not extrapolated" % k}
+            "mean_hit_fraction": frac, "flops_per_launch": float(np.sum(d["flops64"]) + np.sum(d["flops32"])),
+            "note": "256 x (n=40, M=16, cap 32) for the first %d of k=205887 iterations, mixed%s; not extrapolated"
+                    % (k, ", pre-contracted reflections" if precontract else "")}
+
+
+def precontracted_leg(w, ks, shots, kernel: str):
+    """The same workload and step through the pre-contracted reflections (psi plus product
+    terms, the whole oracle as one recompression): a recompression variant, reported next to
+    the per-projector MPO path of the headline value. One untimed step captures the graph."""
+    import torch
+    from paper_2601_03832_amd import gmps
+    out = {}
+    sum_k = int(sum(ks))
+    for prec in ("mixed", "fp64"):
+        b = gmps.Batch(w.instances, prec, kernel="team" if kernel == "auto" else kernel, precontract=True)
+        run_step(b, ks, shots, w.shot_seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p, _ = run_step(b, ks, shots, w.shot_seed)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        err = max(abs(p[i] - exact_p(inst.n, inst.M, inst.k)) for i, inst in enumerate(w.instances))
+        d = b.diagnostics()
+        out["mixed" if prec == "mixed" else "fp64"] = {
+            "value": sum_k / (t1 - t0), "unit": "iterations/s", "ms_per_step": (t1 - t0) * 1000.0,
+            "kernel_ms": b.last_iterate_ms(), "max_abs_err_p": float(err),
+            "tolerance": 1e-6 if prec == "mixed" else 1e-10,
+            "flops_per_launch": float(np.sum(d["flops64"]) + np.sum(d["flops32"]))}
+        b.close()
+    out["note"] = ("same workload and step with gmps_options.precontract = 1: each reflection applied as "
+                   "psi plus product terms (bond chi + T), the M oracle terms in one recompression")
+    return out
 
 
 def statevector_leg(n: int, k: int):
@@ -230,6 +261,7 @@ def main():
     ap.add_argument("--shots", type=int, default=None)
     ap.add_argument("--c5-k", type=int, default=48, help="iterations of the n=40, M=16 prefix leg (0: skip)")
     ap.add_argument("--sv-k", type=int, default=500, help="iterations of the statevector comparison leg (0: skip)")
+    ap.add_argument("--no-precontract", action="store_true", help="skip the pre-contracted reflections legs")
     ap.add_argument("--kernel", default="auto", choices=sorted(["auto", "group", "team"]),
                     help="iterate kernel: lane-group, team, or the library's choice")
     args = ap.parse_args()
@@ -323,9 +355,16 @@ def main():
                                 "note": "same workload and step through the FP64 path (one untimed-warmup-free step)"}
         b64.close()
         print("bench: batched fp64 leg done", file=sys.stderr, flush=True)
+    if not args.no_precontract and args.kernel != "group":
+        line["precontracted"] = precontracted_leg(w, ks, shots, args.kernel)
+        line["precontracted"]["mixed"]["speedup_over_value"] = line["precontracted"]["mixed"]["value"] / line["value"]
+        print("bench: pre-contracted legs done", file=sys.stderr, flush=True)
     if args.c5_k > 0 and args.workload == "c4":
         line["c5_prefix"] = c5_prefix(args.c5_k, args.kernel)
         print("bench: c5 prefix leg done", file=sys.stderr, flush=True)
+        if not args.no_precontract and args.kernel != "group":
+            line["c5_prefix_precontracted"] = c5_prefix(args.c5_k, args.kernel, precontract=True)
+            print("bench: c5 prefix pre-contracted leg done", file=sys.stderr, flush=True)
     if args.sv_k > 0 and args.workload == "c4":
         line["statevector"] = statevector_leg(28, args.sv_k)
         print("bench: statevector leg done", file=sys.stderr, flush=True)
