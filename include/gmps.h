@@ -113,7 +113,13 @@ typedef struct {
                            marked index is one reflection with T = 1. Same result up to
                            rounding; 0 or -1 (default): one bond-2 MPO per projector, as in
                            the paper. */
-  int32_t reserved[1];
+  int32_t pipeline;     /* 0 or 1 (default): the team classes with bond caps 5 and 8 (one
+                           instance per wave) run the per-projector reflections with
+                           alternating sweep directions on two waves, the truncation sweep of
+                           each reflection and the canonicalisation sweep of the next in lock
+                           step one site apart (no warm starts); ignored with precontract and
+                           on the lane-group kernel. -1: one wave per instance, each
+                           reflection's two sweeps in turn */
 } gmps_options;
 
 /* Bytes of device workspace gmps_create() needs for this batch with either iterate kernel

@@ -19,9 +19,9 @@ hipError_t launch_group(bool mixed, const IterParams& P, int grid, size_t lds, h
 hipError_t group_occupancy(bool mixed, size_t lds, int* blocks_per_cu);
 size_t group_lds_bytes(bool mixed, int cls);
 int team_per_bundle(int cls);
-size_t team_lds_bytes(bool mixed, bool pc, int cls);
-hipError_t launch_team(bool mixed, bool pc, int cls, const IterParams& P, int grid, size_t lds, hipStream_t st);
-hipError_t team_occupancy(bool mixed, bool pc, int cls, size_t lds, int* blocks_per_cu);
+size_t team_lds_bytes(bool mixed, bool pc, bool pipe, int cls);
+hipError_t launch_team(bool mixed, bool pc, bool pipe, int cls, const IterParams& P, int grid, size_t lds, hipStream_t st);
+hipError_t team_occupancy(bool mixed, bool pc, bool pipe, int cls, size_t lds, int* blocks_per_cu);
 hipError_t launch_queue_reset(QueueState* q, hipStream_t st);
 hipError_t launch_init(bool mixed, InstDev* inst, int B, const int64_t* site_start, int32_t* bonds, void* arena,
                        int64_t total_sites, char* warm, hipStream_t st);
@@ -142,6 +142,7 @@ struct gmps_batch {
   bool stoch_round = true;
   int jacobi_warm = 0;  // 0: library default (mixed path only), 1 on, -1 off
   bool precontract = false;  // reflections as psi + product terms (team kernel only)
+  bool pipeline = false;     // pipelined sweeps for the single-wave classes (team kernel default)
   int path = kPathGroup;
   int max_cm = 0;       // largest class bond of the batch (read-out register sizing)
   int num_cus = 0;
@@ -276,6 +277,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     b->jacobi_warm = opt->jacobi_warm;
   }
   b->precontract = precontract;
+  b->pipeline = path == kPathTeam && !(opt && opt->pipeline < 0);
   hipGetDevice(&b->device);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
@@ -402,7 +404,7 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
     // a site step of either kernel takes roughly (CM + 1) times a fixed latency
     const int refl = g.first.whole ? 2 : g.first.M + 1;  // reflections per iteration
     const double cost = (double)g.first.k * refl * std::max(1, g.first.n - 1) * (class_cm(cls) + 1.0);
-    lds[kind] = std::max(lds[kind], team ? team_lds_bytes(b->mixed, b->precontract, cls) : group_lds_bytes(b->mixed, cls) * per);
+    lds[kind] = std::max(lds[kind], team ? team_lds_bytes(b->mixed, b->precontract, b->pipeline, cls) : group_lds_bytes(b->mixed, cls) * per);
     for (size_t s = 0; s < g.second.size(); s += per) {
       Bundle bd;
       std::memset(&bd, 0, sizeof(bd));
@@ -446,7 +448,7 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
     if (count[kd] == 0) continue;
     int per_cu = 0;
     if (kd == 0) GMPS_HIP(group_occupancy(b->mixed, lds[kd], &per_cu));
-    else GMPS_HIP(team_occupancy(b->mixed, b->precontract, kWideBase + kd - 1, lds[kd], &per_cu));
+    else GMPS_HIP(team_occupancy(b->mixed, b->precontract, b->pipeline, kWideBase + kd - 1, lds[kd], &per_cu));
     if (b->waves_per_cu > 0) per_cu = std::min(per_cu, b->waves_per_cu);
     per_cu = std::max(per_cu, 1);
     cap_wg[kd] = per_cu * b->num_cus;
@@ -494,7 +496,7 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
       // it raised the largest mixed-precision error of P from 7e-7 to 1.3e-6)
       if (kd > 0 && b->precontract && b->jacobi_warm == 0 && kWide[kd - 1].CM > 2) P.warm = nullptr;
       e = kd == 0 ? launch_group(b->mixed, P, grid[kd], lds[kd], ks)
-                  : launch_team(b->mixed, b->precontract, kWideBase + kd - 1, P, grid[kd], lds[kd], ks);
+                  : launch_team(b->mixed, b->precontract, b->pipeline, kWideBase + kd - 1, P, grid[kd], lds[kd], ks);
       if (e == hipSuccess && !on_main) {
         e = hipEventRecord(b->join_ev[kd], ks);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join_ev[kd], 0);

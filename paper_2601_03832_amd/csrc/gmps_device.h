@@ -149,6 +149,14 @@ __device__ __forceinline__ void lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Orders LDS traffic between the lanes of one wave (no barrier: for code that a wave runs
+// while another wave of its workgroup runs different code).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // Round-robin (circle method) pairing of NC columns: round r pairs NC-1 with r and
 // (r+p) with (r-p) mod (NC-1); after NC-1 rounds every pair has met once.
 __host__ __device__ constexpr int circ_a(int NC, int r, int p) { return p == 0 ? NC - 1 : (r + p) % (NC - 1); }

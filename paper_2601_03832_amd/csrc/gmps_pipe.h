@@ -1,0 +1,480 @@
+// Pipelined reflections for the team classes whose instance fills one wave (bond caps 5
+// and 8), per-projector MPO form (Section III-B).
+//
+// Each reflection is a canonicalisation sweep (MPO applied, rank-stopped QR) followed by a
+// truncation sweep (one-sided Jacobi SVD) in the opposite direction. Reflections alternate
+// directions: reflection j canonicalises left to right when j is even and right to left when
+// j is odd, so the truncation sweep of reflection j and the canonicalisation sweep of
+// reflection j+1 run in the same direction, and the second can follow the first one site
+// behind. A workgroup holds one instance on two waves: wave 0 runs the truncation sweeps,
+// wave 1 the canonicalisation sweeps, in lock step ticks of one site. Every final site tensor
+// the truncation wave produces is handed to the canonicalisation wave through LDS. Both waves
+// take exactly one workgroup barrier per tick and none inside a step.
+//
+// Mirrored steps: right-to-left canonicalisation takes the LQ factorisation of the MPO-applied
+// tile as the QR of its conjugate transpose, the site keeps Q^H (right-orthonormal) and the
+// carry is R^H; left-to-right truncation runs the Jacobi on the columns of M (the bond being
+// truncated), keeps U = M J / Sigma and carries Sigma J^H to the right. After a call the chain
+// is right-canonical with the norm in site 0, as the read-out kernels expect: a call whose last
+// truncation ran left to right ends with one right-to-left canonicalisation of the identity.
+#pragma once
+#include "gmps_team.h"
+
+namespace gmps {
+
+template <class S, int CM>
+struct PipeLds {
+  using T = TeamShape<CM, 64>;
+  cx<S> W[2][CM][2][CM];         // canonicalisation: staged MPO blocks [c0 A | c1 P A]
+  cd R[T::KQ][T::D];             // canonicalisation carry: R (to the right) or R~ = L^H (left)
+  cd V[T::KQ][T::PQ * T::RQ];    // Householder vectors
+  double tau[T::KQ];
+  cx<S> Q[T::KQ][2][T::KQ];      // truncation: staged site of the canonicalised chain
+  cd Y[T::KQ][CM];               // truncation carry, [canonical bond][kept bond]
+  cx<S> H[2][CM][2][CM];         // final site tensors handed over, by tick parity
+  int32_t bond[kBondStride];     // bonds of the chain the truncation wave produces
+  int32_t rdim[2][kBondStride];  // bonds of the canonicalised chain, by reflection parity
+};
+
+template <class S, int CM>
+__device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base) {
+  constexpr int TW = 64;
+  using T = TeamShape<CM, TW>;
+  constexpr int D = T::D, KQ = T::KQ;
+  constexpr int PQ = T::PQ, RQ = T::RQ, PJ = T::PJ, RJ = T::RJ, RU = T::RU;
+  constexpr int SLOT = slot_elems(CM);
+  constexpr int NE = (CM * CM + TW - 1) / TW;  // (CM x CM) box elements per lane
+  constexpr bool kMixed = sizeof(S) == sizeof(float);
+  const int wave = threadIdx.x / 64;  // 0: truncation, 1: canonicalisation
+  const int tl = threadIdx.x % 64;
+  const int qc = tl / PQ, qh = tl % PQ;  // QR layout
+  const int jc = tl / PJ, jh = tl % PJ;  // Jacobi layout
+  const bool real = bdp->count > 0;
+  const int me = bdp->inst[0];
+  PipeLds<S, CM>& L = *reinterpret_cast<PipeLds<S, CM>*>(lds_base);
+  InstDev* I = P.inst + me;
+  const int n = I->n;
+  const int M = I->M;
+  const int cap = I->cap < CM ? I->cap : CM;
+  const int64_t k = bdp->k;
+  cx<S>* arena = reinterpret_cast<cx<S>*>(P.arena) + I->site_off;
+  const uint64_t* Wm = P.marked + I->marked_off;
+  const double tol2 = P.trunc_tol * P.trunc_tol;
+  const double rank2 = P.rank_tol * P.rank_tol;
+  const double skip2 = P.skip_tol * P.skip_tol;
+  const bool sr = P.stoch_round != 0;
+  const uint64_t k_done0 = (uint64_t)I->k_done;
+  uint64_t rs_state = mix64(((uint64_t)me << 32) ^ (k_done0 * 0x9E3779B97F4A7C15ull) ^ (uint64_t)threadIdx.x);
+
+  for (int l = threadIdx.x; l < kBondStride; l += 128) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
+  team_sync_global();
+
+  double f64 = 0.0, f32 = 0.0, drift = 0.0, truncw = 0.0;
+  int status = 0;
+  const int nrefl = M + 1;
+  const int64_t J = k * nrefl;  // reflections of this call
+
+  // ---------------------------------------------------------------- canonicalisation step
+  // Reflection jr (0..M, M = diffusion) at site i, direction lr; the site tensor comes from
+  // the handover buffer h (null: from its arena slot). rdo: the ranks it produces.
+  auto canon_step = [&](int jr, bool ident, bool lr, int i, const cx<S> (*h)[2][CM], int32_t* rdo) {
+    const bool diff = (jr == M);
+    const int xb = (diff || ident) ? 0 : (int)((Wm[jr] >> (n - 1 - i)) & 1ull);
+    const double c0 = ident ? 1.0 : (diff ? -1.0 : 1.0);
+    const double c1 = ident ? 0.0 : (diff ? 2.0 : -2.0);
+    const int chl = L.bond[i], chr = L.bond[i + 1];
+    const bool mpo_last = (i == n - 1);  // the MPO's coefficients sit on the last site
+    const bool first = lr ? (i == 0) : (i == n - 1);
+    const bool last = lr ? (i == n - 1) : (i == 0);
+    cx<S>* slot = arena + (int64_t)i * SLOT;
+    if (first && tl == 0) {
+      rdo[lr ? 0 : n] = 1;
+      L.R[0][0] = {1.0, 0.0};
+      L.R[0][1] = {1.0, 0.0};
+    }
+    // stage [c0 A | c1 P A] (coefficients on the last site only)
+    {
+      const S s0 = (S)(mpo_last ? c0 : 1.0), s1 = (S)(mpo_last ? c1 : 1.0);
+#pragma unroll
+      for (int t = 0; t < NE; ++t) {
+        const int e = tl + t * TW;
+        if (e < CM * CM) {
+          const int a = e / CM, b = e % CM;
+          const bool ok = a < chl && b < chr;
+          cx<S> a0 = czero<S>(), a1 = czero<S>();
+          if (ok) {
+            if (h) {
+              a0 = h[a][0][b];
+              a1 = h[a][1][b];
+            } else {
+              a0 = slot[a * 2 * D + b];
+              a1 = slot[a * 2 * D + D + b];
+            }
+          }
+          L.W[0][a][0][b] = s0 * a0;
+          L.W[0][a][1][b] = s0 * a1;
+          L.W[1][a][0][b] = s1 * proj_apply<S>(a0, a1, 0, diff, xb);
+          L.W[1][a][1][b] = s1 * proj_apply<S>(a0, a1, 1, diff, xb);
+        }
+      }
+    }
+    wave_sync();
+    const int r = first ? 1 : rdo[lr ? i : i + 1];
+    cd x[RQ];
+    int Dr;  // columns of the QR tile
+    if (lr) {
+      // X = R_{i-1} * MPO(A_i): rows (a, s) = 2a + s, columns (beta, b)
+      Dr = last ? 1 : 2 * chr;
+      const int beta = (!last && qc >= chr) ? 1 : 0;
+      const int bcol = qc - beta * chr;
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) {
+        const int row = qh + PQ * e;
+        const int a = row >> 1, s = row & 1;
+        cx<S> acc = czero<S>();
+        if (row < 2 * r && qc < Dr) {
+#pragma unroll
+          for (int bl = 0; bl < 2; ++bl) {
+            if (last || bl == beta) {
+#pragma unroll
+              for (int ap = 0; ap < CM; ++ap)
+                if (ap < chl) acc = cfma(acc, down<S>(L.R[a][bl * chl + ap]), L.W[bl][ap][s][bcol]);
+            }
+          }
+        }
+        x[e] = up(acc);
+      }
+    } else {
+      // X'^H, X' = MPO(A_i) * L_{i+1} with L = R~^H: rows (c, s) = 2c + s, columns
+      // (alpha, a); X'^H[(c,s)][(alpha,a)] = sum_b conj(W_alpha[a][s][b]) R~[c][alpha chr + b]
+      Dr = last ? 1 : 2 * chl;
+      const int alpha = (!last && qc >= chl) ? 1 : 0;
+      const int acol = qc - alpha * chl;
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) {
+        const int row = qh + PQ * e;
+        const int c = row >> 1, s = row & 1;
+        cx<S> acc = czero<S>();
+        if (row < 2 * r && qc < Dr) {
+#pragma unroll
+          for (int al = 0; al < 2; ++al) {
+            if (last || al == alpha) {
+#pragma unroll
+              for (int bp = 0; bp < CM; ++bp)
+                if (bp < chr) acc = cfma(acc, conj(L.W[al][last ? 0 : acol][s][bp]), down<S>(L.R[c][al * chr + bp]));
+            }
+          }
+        }
+        // the left boundary keeps X' itself (one row): conjugate back
+        x[e] = last ? conj(up(acc)) : up(acc);
+      }
+    }
+    {
+      const double macs = (double)r * (first ? 1 : 2 * (lr ? chl : chr)) * 2.0 * Dr;
+      if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+    }
+    if (last) {
+      // the boundary site stores its tile: left to right the column (a, s) of site n-1,
+      // right to left the row (s, c) of site 0
+      if (real && qc == 0) {
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) {
+          const int row = qh + PQ * e;
+          if (row < 2 * r) slot[(lr ? (row >> 1) * 2 * D : 0) + (row & 1) * D + (lr ? 0 : (row >> 1))] =
+              store_cast<S>(x[e], rs_state, sr);
+        }
+      }
+      if (tl == 0) {
+        if (lr) {
+          rdo[n - 1] = r;
+          rdo[n] = 1;
+        } else {
+          rdo[1] = r;
+          rdo[0] = 1;
+        }
+      }
+      wave_sync();
+      return;
+    }
+    const int m = 2 * r;
+    cd q[RQ];
+    double qdrop = 0.0;
+    const int npiv = lr ? chr : chl;
+    const int kr = team_qr_wave<TW, PQ, RQ, KQ, true>(x, q, 0, qc, qh, m, Dr, npiv, rank2, &qdrop, L.V, L.tau);
+    truncw = fmax(truncw, qdrop);
+    {
+      const double mm = m, cc = Dr, kk = kr;
+      f64 += 8.0 * (2.0 * mm * cc * kk - (mm + cc) * kk * kk + 2.0 * kk * kk * kk / 3.0) +
+             8.0 * (2.0 * mm * kk * kk - 2.0 * kk * kk * kk / 3.0);
+    }
+    if (real && qc < kr) {
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) {
+        const int row = qh + PQ * e;
+        if (row < m) {
+          if (lr)
+            slot[(row >> 1) * 2 * D + (row & 1) * D + qc] = store_cast<S>(q[e], rs_state, sr);
+          else  // site i keeps Q^H: [k][s][c] = conj(Q[(c, s)][k])
+            slot[qc * 2 * D + (row & 1) * D + (row >> 1)] = store_cast<S>(conj(q[e]), rs_state, sr);
+        }
+      }
+    }
+    if (qc < Dr) {
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) {
+        const int row = qh + PQ * e;
+        if (row < kr) L.R[row][qc] = x[e];
+      }
+    }
+    if (tl == 0) rdo[lr ? i + 1 : i] = kr;
+    wave_sync();
+  };
+
+  // ---------------------------------------------------------------- truncation step
+  // Reflection jr at site i, direction lr (the opposite of its canonicalisation); rdi: the
+  // canonicalised chain's bonds. Writes the final site i to its slot and to h.
+  auto trunc_step = [&](int jr, bool lr, int i, const int32_t* rdi, cx<S> (*h)[2][CM]) {
+    const bool diff = (jr == M);
+    const bool first = lr ? (i == 0) : (i == n - 1);
+    const bool edge = lr ? (i == n - 1) : (i == 0);  // absorbs the carry, holds the norm
+    cx<S>* slot = arena + (int64_t)i * SLOT;
+    const int ri = rdi[i], rn = rdi[i + 1];
+    if (first && tl == 0) L.Y[0][0] = {1.0, 0.0};
+    // stage the canonicalised site (ri, 2, rn)
+    {
+      constexpr int NQ = (KQ * 2 * KQ + TW - 1) / TW;
+#pragma unroll
+      for (int t = 0; t < NQ; ++t) {
+        const int e = tl + t * TW;
+        if (e < KQ * 2 * KQ) {
+          const int a = e / (2 * KQ), s = (e / KQ) & 1, b = e % KQ;
+          L.Q[a][s][b] = (a < ri && b < rn) ? slot[a * 2 * D + s * D + b] : czero<S>();
+        }
+      }
+    }
+    wave_sync();
+    if (edge) {
+      // right to left: site 0 = Q_0 Y, (1, 2, chn); left to right: site n-1 = Y^T Q, (chp, 2, 1)
+      const int chc = lr ? L.bond[i] : L.bond[1];  // kept bond of the carry
+      const int cr = lr ? ri : rn;                 // canonical bond of the carry
+      const bool act = tl < 2 * chc;
+      const int s = tl >= chc ? 1 : 0;
+      const int jj = tl - s * chc;
+      cx<S> acc = czero<S>();
+      if (act) {
+#pragma unroll
+        for (int b = 0; b < KQ; ++b)
+          if (b < cr) acc = lr ? cfma(acc, down<S>(L.Y[b][jj]), L.Q[b][s][0]) : cfma(acc, L.Q[0][s][b], down<S>(L.Y[b][jj]));
+      }
+      {
+        const double macs = 2.0 * cr * chc;
+        if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+      }
+      const double nn = tsum<TW>(act ? norm2(up(acc)) : 0.0);
+      if (!isfinite(nn) || !(nn > 0.0)) status |= GMPS_ST_NAN;
+      const double nr = sqrt(nn);
+      if (diff) drift = fmax(drift, fabs(nr - 1.0));
+      const cx<S> out = store_cast<S>((diff ? 1.0 / nr : 1.0) * up(acc), rs_state, sr);
+      if (act) {
+        if (real) slot[lr ? (jj * 2 * D + s * D) : (s * D + jj)] = out;
+        if (lr) h[jj][s][0] = out; else h[0][s][jj] = out;
+      }
+      if (tl == 0) L.bond[lr ? n : 0] = 1;
+      wave_sync();
+      return;
+    }
+    // tile: right to left, the columns of M^H, M = Q_i (U Sigma)_{i+1}, rows (s, jj) of the
+    // kept bond chn to the right; left to right, the columns of M = (Sigma J^H)_{i-1} Q_i,
+    // rows (s, jj) of the kept bond to the left
+    const int chn = lr ? L.bond[i] : L.bond[i + 1];
+    const int c = 2 * chn;
+    const int ncol = lr ? rn : ri;
+    const int ncj = (ncol + 1) & ~1;
+    const int cr = lr ? ri : rn;  // canonical bond summed over
+    cd a[RJ];
+#pragma unroll
+    for (int e = 0; e < RJ; ++e) {
+      const int row = jh + PJ * e;
+      const int s = row >= chn ? 1 : 0;
+      const int jj = row - s * chn;
+      cx<S> acc = czero<S>();
+      if (jc < ncol && row < c) {
+#pragma unroll
+        for (int b = 0; b < KQ; ++b)
+          if (b < cr) acc = lr ? cfma(acc, down<S>(L.Y[b][jj]), L.Q[b][s][jc]) : cfma(acc, L.Q[jc][s][b], down<S>(L.Y[b][jj]));
+      }
+      a[e] = lr ? up(acc) : conj(up(acc));
+    }
+    {
+      const double macs = (double)ncol * 2.0 * cr * chn;
+      if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+    }
+    wave_sync();  // every read of Y is done before it is rewritten below
+    cd uu[RU];
+#pragma unroll
+    for (int e = 0; e < RU; ++e) uu[e] = {(jh + PJ * e == jc && jc < ncj) ? 1.0 : 0.0, 0.0};
+    const int sweeps = team_jacobi_wave<TW, PJ, RJ, RU>(a, uu, 0, jc, jh, ncj, kJacobiTol2, skip2, P.max_sweeps);
+    f64 += (double)sweeps * ncol * (ncol - 1) / 2.0 * 56.0 * c;
+    const bool colok = jc < ncj;
+    double sg = 0.0;
+#pragma unroll
+    for (int e = 0; e < RJ; ++e) sg += norm2(a[e]);
+    sg = gsum<PJ>(sg);
+    const double mine = colok ? sg : 0.0;
+    const double smax = tmax<TW>(mine);
+    const double stot = tsum<TW>(jh == 0 ? mine : 0.0);
+    const int above = (int)tsum<TW>((jh == 0 && mine > 0.0 && mine >= tol2 * smax) ? 1.0 : 0.0);
+    int rk = 0;
+    for (int o = 0; o < ncj; ++o) {
+      const double v = shfl_f64(mine, o * PJ);
+      rk += (v > sg || (v == sg && o < jc)) ? 1 : 0;
+    }
+    int chi_new = above < cap ? above : cap;
+    if (chi_new < 1) chi_new = 1;
+    const bool keep = colok && rk < chi_new;
+    const uint64_t kept = tballot<TW>(jh == 0 && keep, 0);
+    const int pos = __popcll(kept & ((1ull << (jc * PJ)) - 1ull));
+    const double dropped = tsum<TW>((jh == 0 && colok && !keep) ? sg : 0.0);
+    if (stot > 0.0) truncw = fmax(truncw, dropped / stot);
+    if (!isfinite(stot)) status |= GMPS_ST_NAN;
+    if (keep) {
+      const double rs = rsqrt_acc(sg);  // 1/sigma
+#pragma unroll
+      for (int e = 0; e < RJ; ++e) {
+        const int row = jh + PJ * e;
+        if (row < c) {
+          const int s = row >= chn ? 1 : 0;
+          const int jp = row - s * chn;
+          // right to left: V^H[pos][s][jp] = conj(a) / sigma; left to right: U[jp][s][pos] = a / sigma
+          const cx<S> v = store_cast<S>(lr ? rs * a[e] : rs * conj(a[e]), rs_state, sr);
+          if (lr) {
+            if (real) slot[jp * 2 * D + s * D + pos] = v;
+            h[jp][s][pos] = v;
+          } else {
+            if (real) slot[pos * 2 * D + s * D + jp] = v;
+            h[pos][s][jp] = v;
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < RU; ++e) {
+        const int row = jh + PJ * e;
+        // right to left: carry J Sigma [row][pos]; left to right: (Sigma J^H)^T [row][pos]
+        if (row < ncol) L.Y[row][pos] = (sg * rs) * (lr ? conj(uu[e]) : uu[e]);
+      }
+    }
+    if (tl == 0) L.bond[lr ? i + 1 : i] = chi_new;
+    wave_sync();
+  };
+
+  // ---------------------------------------------------------------- schedule
+  // Tick t of a stage: the truncation wave takes its t-th site, the canonicalisation wave
+  // its (t-1)-th, so a site reaches the second sweep the tick after the first finished it.
+  // Stages: canonicalisation of reflection 0 alone; then truncation j with canonicalisation
+  // j+1, j = 0..J-2; then truncation J-1 alone, followed by a right-to-left canonicalisation
+  // of the identity if that truncation ran left to right. Both waves take n+1 barriers per
+  // stage.
+  const int64_t nstage = J == 0 ? 0 : J + 1;
+  const bool fix = J > 0 && ((J - 1) & 1) == 1;  // last truncation ran left to right
+  for (int64_t stg = 0; stg < nstage + (fix ? 1 : 0); ++stg) {
+    const int64_t jt = stg - 1;   // reflection whose truncation runs (-1: none)
+    const int64_t jc2 = stg;      // reflection whose canonicalisation runs
+    const bool extra = stg == nstage;
+    const bool do_t = !extra && jt >= 0;
+    const bool do_c = extra || jc2 < J;
+    // directions: canonicalisation of reflection j left to right iff j even; its truncation
+    // the other way
+    const bool lr_c = extra ? false : ((jc2 & 1) == 0);
+    const bool lr_t = (jt & 1) == 1;
+    for (int tick = 0; tick <= n; ++tick) {
+      if (wave == 0) {
+        if (do_t && tick < n) {
+          const int i = lr_t ? tick : n - 1 - tick;
+          trunc_step((int)(jt % nrefl), lr_t, i, L.rdim[jt & 1], L.H[tick & 1]);
+        }
+      } else {
+        if (do_c && tick >= 1) {
+          const int i = lr_c ? tick - 1 : n - tick;
+          // follows the truncation wave (handover of the previous tick) when it runs,
+          // else reads the arena
+          const cx<S>(*h)[2][CM] = do_t ? L.H[(tick - 1) & 1] : nullptr;
+          canon_step(extra ? 0 : (int)(jc2 % nrefl), extra, lr_c, i, h, L.rdim[extra ? 0 : (jc2 & 1)]);
+        }
+      }
+      team_sync_global();
+    }
+    if (extra) {
+      // the identity's canonicalisation only re-gauges: its ranks are the bonds
+      for (int l = threadIdx.x; l <= n; l += 128) L.bond[l] = L.rdim[0][l];
+      team_sync_global();
+    }
+  }
+
+  // ------------------------------------------------------------------ write back
+  // the two waves' counters are summed through the status slots of the instance record
+  if (real) {
+    for (int l = threadIdx.x; l < kBondStride; l += 128) P.bonds[(int64_t)me * kBondStride + l] = L.bond[l];
+  }
+  __shared__ double red[2][4];
+  __shared__ int redst[2];
+  if (tl == 0) {
+    red[wave][0] = f64;
+    red[wave][1] = f32;
+    red[wave][2] = drift;
+    red[wave][3] = truncw;
+    redst[wave] = status;
+  }
+  team_sync_global();
+  if (real && threadIdx.x == 0) {
+    const double d = fmax(red[0][2], red[1][2]);
+    const double tw = fmax(red[0][3], red[1][3]);
+    int st = redst[0] | redst[1];
+    I->k_done += k;
+    I->flops64 += red[0][0] + red[1][0];
+    I->flops32 += red[0][1] + red[1][1];
+    I->drift = fmax(I->drift, d);
+    I->trunc_w = fmax(I->trunc_w, tw);
+    if (d > 1e-3) st |= GMPS_ST_DRIFT;
+    if (tw > 1e-8) st |= GMPS_ST_TRUNC;
+    I->status |= st;
+  }
+  team_sync_global();
+}
+
+// Persistent kernel of the pipelined reflections for team class W (one instance per
+// workgroup of two waves).
+template <class S, int W>
+__global__ __launch_bounds__(128) void grover_pipe_kernel(IterParams P) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ unsigned int next_bundle;
+  for (;;) {
+    if (threadIdx.x == 0) next_bundle = atomicAdd(&P.queue->next, 1u);
+    lds_sync();
+    const unsigned int bi = next_bundle;
+    lds_sync();
+    if ((int)bi >= P.queue->nbundles) break;
+    run_pipe<S, kWide[W].CM>(P, P.bundles + bi, lds);
+  }
+}
+
+template <int W>
+hipError_t launch_pipe_w(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st);
+template <int W>
+hipError_t occupancy_pipe_w(bool mixed, size_t lds, int* blocks_per_cu);
+
+#define GMPS_PIPE_CLASS(W)                                                                           \
+  template <>                                                                                        \
+  hipError_t launch_pipe_w<W>(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st) { \
+    if (mixed)                                                                                       \
+      grover_pipe_kernel<float, W><<<grid, 128, lds, st>>>(P);                                        \
+    else                                                                                             \
+      grover_pipe_kernel<double, W><<<grid, 128, lds, st>>>(P);                                       \
+    return hipGetLastError();                                                                        \
+  }                                                                                                  \
+  template <>                                                                                        \
+  hipError_t occupancy_pipe_w<W>(bool mixed, size_t lds, int* blocks_per_cu) {                      \
+    return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_pipe_kernel<float, W>, 128, lds) \
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_pipe_kernel<double, W>, 128, lds); \
+  }
+
+}  // namespace gmps

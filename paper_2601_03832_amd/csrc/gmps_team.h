@@ -531,7 +531,7 @@ __device__ __forceinline__ void rot_apply(cd (&own)[R], const cd (&oth)[R], bool
 // vector itself), the pivot search as a team maximum plus a ballot, and column sums as
 // butterflies, so the steps need neither LDS round trips nor barriers. Only the pivot
 // slot writes its Householder vector to V, for the formation of Q at the end.
-template <int TW, int PQ, int RQ, int KQ>
+template <int TW, int PQ, int RQ, int KQ, bool WL = false>
 __device__ __forceinline__ int team_qr_wave(cd (&x)[RQ], cd (&q)[RQ], int base, int qc, int qh, int m, int c,
                                             int npiv, double rank2, double* dropped, cd (*V)[PQ * RQ],
                                             double* tau) {
@@ -616,7 +616,9 @@ __device__ __forceinline__ int team_qr_wave(cd (&x)[RQ], cd (&q)[RQ], int base, 
   }
   const double tk = tsum<TW>((colok && !used) ? tr : 0.0);
   *dropped = t0 > 0.0 ? tk / t0 : 0.0;
-  lds_sync();  // V and tau of every step, read by all slots below
+  // V and tau of every step, read by all slots below (WL: the team is the whole wave and
+  // the workgroup's other wave runs other code, so no workgroup barrier)
+  if constexpr (WL) wave_sync(); else lds_sync();
 #pragma unroll
   for (int e = 0; e < RQ; ++e) q[e] = {(qh + PQ * e == qc && qc < kr) ? 1.0 : 0.0, 0.0};
   for (int j = kr - 1; j >= 0; --j) {

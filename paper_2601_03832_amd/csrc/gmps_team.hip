@@ -1,6 +1,6 @@
 // Host-side helpers of the team iterate kernels: class geometry, LDS sizes and launches
 // (the kernels themselves are instantiated per class in gmps_team_cm*.hip).
-#include "gmps_team.h"
+#include "gmps_pipe.h"
 
 namespace gmps {
 
@@ -19,6 +19,12 @@ static_assert(sizeof(TeamLds<double, 8, 64>) + sizeof(PcLds<8>) <= 160 * 1024 - 
 static_assert(sizeof(TeamLds<double, 17, 192>) + sizeof(PcLds<17>) <= 160 * 1024 - 64, "LDS");
 static_assert(sizeof(TeamLds<double, 32, 256>) <= 160 * 1024 - 64, "LDS");
 
+static_assert(sizeof(PipeLds<double, 5>) <= 160 * 1024 - 128, "LDS");
+static_assert(sizeof(PipeLds<double, 8>) <= 160 * 1024 - 128, "LDS");
+
+// the classes with a pipelined kernel (one instance per wave: bond caps 5 and 8)
+static bool pipe_class(int w) { return w == 2 || w == 3; }
+
 template <int W>
 static size_t class_lds(bool mixed, bool pc) {
   constexpr int CM = kWide[W].CM, TW = kWide[W].TW;
@@ -28,7 +34,10 @@ static size_t class_lds(bool mixed, bool pc) {
   return per * teams;
 }
 
-size_t team_lds_bytes(bool mixed, bool pc, int cls) {
+size_t team_lds_bytes(bool mixed, bool pc, bool pipe, int cls) {
+  if (pipe && !pc && pipe_class(cls - kWideBase))
+    return cls - kWideBase == 2 ? (mixed ? sizeof(PipeLds<float, 5>) : sizeof(PipeLds<double, 5>))
+                                : (mixed ? sizeof(PipeLds<float, 8>) : sizeof(PipeLds<double, 8>));
   switch (cls - kWideBase) {
     case 0: return class_lds<0>(mixed, pc);
     case 1: return class_lds<1>(mixed, pc);
@@ -40,8 +49,10 @@ size_t team_lds_bytes(bool mixed, bool pc, int cls) {
   return 0;
 }
 
-hipError_t launch_team(bool mixed, bool pc, int cls, const IterParams& P, int grid, size_t lds, hipStream_t st) {
+hipError_t launch_team(bool mixed, bool pc, bool pipe, int cls, const IterParams& P, int grid, size_t lds,
+                       hipStream_t st) {
   const int w = cls - kWideBase;
+  if (pipe && !pc && pipe_class(w)) return w == 2 ? launch_pipe_w<2>(mixed, P, grid, lds, st) : launch_pipe_w<3>(mixed, P, grid, lds, st);
   if (pc && w >= 0 && w < kNumWide && team_pc_class(w)) {
     switch (w) {
       case 0: return launch_team_pc_w<0>(mixed, P, grid, lds, st);
@@ -63,8 +74,10 @@ hipError_t launch_team(bool mixed, bool pc, int cls, const IterParams& P, int gr
   return hipErrorInvalidValue;
 }
 
-hipError_t team_occupancy(bool mixed, bool pc, int cls, size_t lds, int* blocks_per_cu) {
+hipError_t team_occupancy(bool mixed, bool pc, bool pipe, int cls, size_t lds, int* blocks_per_cu) {
   const int w = cls - kWideBase;
+  if (pipe && !pc && pipe_class(w))
+    return w == 2 ? occupancy_pipe_w<2>(mixed, lds, blocks_per_cu) : occupancy_pipe_w<3>(mixed, lds, blocks_per_cu);
   if (pc && w >= 0 && w < kNumWide && team_pc_class(w)) {
     switch (w) {
       case 0: return occupancy_team_pc_w<0>(mixed, lds, blocks_per_cu);

@@ -43,7 +43,7 @@ class GmpsOptions(ctypes.Structure):
                 ("waves_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("round_mode", ctypes.c_int32), ("jacobi_warm", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("precontract", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("pipeline", ctypes.c_int32)]
 
 
 class GmpsError(RuntimeError):
@@ -156,7 +156,7 @@ class Batch:
     def __init__(self, instances: Sequence, precision: str = "fp64", trunc_tol: float = 0.0,
                  max_sweeps: int = 0, waves_per_cu: int = 0, use_graph: bool = True, stream=None,
                  device=None, stochastic_rounding: bool = True, jacobi_warm: Optional[bool] = None,
-                 kernel: str = "auto", precontract: bool = False):
+                 kernel: str = "auto", precontract: bool = False, pipeline: bool = True):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libgmps needs a ROCm GPU; none is visible")
@@ -182,6 +182,7 @@ class Batch:
         opt.jacobi_warm = 0 if jacobi_warm is None else (1 if jacobi_warm else -1)
         opt.kernel = KERNELS[kernel]
         opt.precontract = 1 if precontract else -1
+        opt.pipeline = 1 if pipeline else -1
         self._opt = opt
         h = ctypes.c_void_p()
         rc = self.lib.gmps_create(ctypes.byref(h), self._arr, self.B, _ptr(self._marked, ctypes.c_uint64), prec,
