@@ -32,7 +32,9 @@ FP32_VECTOR_PEAK = 157.3e12   # MI355X published FP32 vector rate, FLOP/s
 HBM_PEAK = 8.0e12             # MI355X published HBM3E bandwidth, bytes/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grover_kernel.json")
 # the iterate kernel each --kernel choice runs (the library's choice is the team kernel)
-KERNEL_NAME = {"auto": "grover_team_kernel", "team": "grover_team_kernel", "group": "grover_group_kernel"}
+# the launch's longest class kernel on the 4096-instance workload (bond cap 5: the pipelined
+# sweeps by default); the roofline's flops, bytes and time cover every class kernel of the launch
+KERNEL_NAME = {"auto": "grover_pipe_kernel", "team": "grover_pipe_kernel", "group": "grover_group_kernel"}
 CSRC = os.path.join(ROOT, "paper_2601_03832_amd", "csrc")
 
 
@@ -262,6 +264,7 @@ def main():
     ap.add_argument("--c5-k", type=int, default=48, help="iterations of the n=40, M=16 prefix leg (0: skip)")
     ap.add_argument("--sv-k", type=int, default=500, help="iterations of the statevector comparison leg (0: skip)")
     ap.add_argument("--no-precontract", action="store_true", help="skip the pre-contracted reflections legs")
+    ap.add_argument("--no-sequential", action="store_true", help="skip the sequential-sweeps leg")
     ap.add_argument("--kernel", default="auto", choices=sorted(["auto", "group", "team"]),
                     help="iterate kernel: lane-group, team, or the library's choice")
     args = ap.parse_args()
@@ -355,6 +358,21 @@ def main():
                                 "note": "same workload and step through the FP64 path (one untimed-warmup-free step)"}
         b64.close()
         print("bench: batched fp64 leg done", file=sys.stderr, flush=True)
+    if not args.no_sequential and args.kernel != "group":
+        bs = gmps.Batch(w.instances, w.precision, kernel=args.kernel, pipeline=False)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        ps, _ = run_step(bs, ks, shots, w.shot_seed)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        es = max(abs(ps[i] - exact_p(inst.n, inst.M, inst.k)) for i, inst in enumerate(w.instances))
+        line["sequential_sweeps"] = {"value": sum_k / (t5 - t4), "unit": "iterations/s", "ms_per_step": (t5 - t4) * 1000.0,
+                                     "kernel_ms": bs.last_iterate_ms(), "max_abs_err_p": es,
+                                     "note": "same workload and step with gmps_options.pipeline = -1: each reflection's "
+                                             "canonicalisation and truncation sweeps in turn on one wave per instance "
+                                             "(one step, no untimed warmup)"}
+        bs.close()
+        print("bench: sequential sweeps leg done", file=sys.stderr, flush=True)
     if not args.no_precontract and args.kernel != "group":
         line["precontracted"] = precontracted_leg(w, ks, shots, args.kernel)
         line["precontracted"]["mixed"]["speedup_over_value"] = line["precontracted"]["mixed"]["value"] / line["value"]
