@@ -230,6 +230,10 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
     wave_sync();
   };
 
+  // the truncation wave loads the next canonicalised site one tick ahead: that slot is final
+  // for the whole stage (the canonicalisation wave rewrites it two ticks later)
+  TeamQPre<S, KQ, CM, TW> qpre;
+
   // ---------------------------------------------------------------- truncation step
   // Reflection jr at site i, direction lr (the opposite of its canonicalisation); rdi: the
   // canonicalised chain's bonds. Writes the final site i to its slot and to h.
@@ -240,17 +244,12 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
     cx<S>* slot = arena + (int64_t)i * SLOT;
     const int ri = rdi[i], rn = rdi[i + 1];
     if (first && tl == 0) L.Y[0][0] = {1.0, 0.0};
-    // stage the canonicalised site (ri, 2, rn)
-    {
-      constexpr int NQ = (KQ * 2 * KQ + TW - 1) / TW;
-#pragma unroll
-      for (int t = 0; t < NQ; ++t) {
-        const int e = tl + t * TW;
-        if (e < KQ * 2 * KQ) {
-          const int a = e / (2 * KQ), s = (e / KQ) & 1, b = e % KQ;
-          L.Q[a][s][b] = (a < ri && b < rn) ? slot[a * 2 * D + s * D + b] : czero<S>();
-        }
-      }
+    // stage the canonicalised site (ri, 2, rn), then load the next one
+    if (first) qpre.load(slot, tl, ri, rn);
+    qpre.stage(&L.Q[0][0][0], tl);
+    if (!edge) {
+      const int nx = lr ? i + 1 : i - 1;
+      qpre.load(arena + (int64_t)nx * SLOT, tl, rdi[nx], rdi[nx + 1]);
     }
     wave_sync();
     if (edge) {
