@@ -141,3 +141,29 @@ def test_binding_refuses_to_run_without_a_gpu():
         pytest.skip("a GPU is visible")
     with pytest.raises(RuntimeError):
         gmps.Batch(inputs.config_c1().instances)
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """The ctypes mirrors of gmps_options and gmps_instance have the header's field offsets."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    opt_fields = [f for f, _ in gmps.GmpsOptions._fields_]
+    inst_fields = [f for f, _ in gmps.GmpsInstance._fields_]
+    body = ["#include <stdio.h>", "#include <stddef.h>", '#include "gmps.h"', "int main(void) {",
+            'printf("%zu\\n", sizeof(gmps_options));', 'printf("%zu\\n", sizeof(gmps_instance));']
+    body += ['printf("%%zu\\n", offsetof(gmps_options, %s));' % f for f in opt_fields]
+    body += ['printf("%%zu\\n", offsetof(gmps_instance, %s));' % f for f in inst_fields]
+    body += ["return 0; }"]
+    src.write_text("\n".join(body) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(gmps.GmpsOptions)
+    assert vals[1] == ctypes.sizeof(gmps.GmpsInstance)
+    offs = vals[2:]
+    got = [getattr(gmps.GmpsOptions, f).offset for f in opt_fields] + [getattr(gmps.GmpsInstance, f).offset for f in inst_fields]
+    assert offs == got
