@@ -645,8 +645,10 @@ __device__ __forceinline__ int team_qr_wave(cd (&x)[RQ], cd (&q)[RQ], int base, 
 // team_jacobi_lds for a team inside one wave: partners read each other's columns with
 // ds_bpermute, the column maximum and the continue flag are team reductions.
 template <int TW, int PJ, int RJ, int RU>
+// jstop: another sweep follows while some rotation of the sweep had a relative squared
+// off-diagonal above it.
 __device__ __forceinline__ int team_jacobi_wave(cd (&a)[RJ], cd (&u)[RU], int base, int jc, int jh, int ncj,
-                                                double tol2, double skip2, int max_sweeps) {
+                                                double tol2, double skip2, int max_sweeps, double jstop = 1e-20) {
   const bool colok = jc < ncj;
   const int lastc = ncj - 1;
   int sweeps = 0;
@@ -682,7 +684,7 @@ __device__ __forceinline__ int team_jacobi_wave(cd (&a)[RJ], cd (&u)[RU], int ba
         const double g2 = norm2(g);
         const double ab = ni * nj;
         if (g2 > tol2 * ab && fmin(ni, nj) > floor2 && g2 > 1e-300) {
-          mv |= g2 > 1e-20 * ab;
+          mv |= g2 > jstop * ab;
           double cs, tg;
           cd se;
           jacobi_rotation(g, g2, ni, nj, &cs, &se, &tg);
