@@ -117,9 +117,11 @@ typedef struct {
                            instance per wave) run the per-projector reflections with
                            alternating sweep directions on two waves, the truncation sweep of
                            each reflection and the canonicalisation sweep of the next in lock
-                           step one site apart (no warm starts); ignored with precontract and
-                           on the lane-group kernel. -1: one wave per instance, each
-                           reflection's two sweeps in turn */
+                           step one site apart (no warm starts); ignored with precontract, on
+                           the lane-group kernel, and in a batch where some bond cap is below
+                           the exact rank (a lossy truncation depends on the sweep order; such
+                           a batch keeps the sequential, right-to-left truncations). -1: one
+                           wave per instance, each reflection's two sweeps in turn */
 } gmps_options;
 
 /* Bytes of device workspace gmps_create() needs for this batch with either iterate kernel

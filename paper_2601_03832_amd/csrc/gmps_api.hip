@@ -278,6 +278,12 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   }
   b->precontract = precontract;
   b->pipeline = path == kPathTeam && !(opt && opt->pipeline < 0);
+  // A cap below the exact rank drops weight, and what a truncation drops depends on the sweep
+  // order: such a batch keeps the sequential sweeps, whose truncations run right to left as
+  // in the CPU oracle's MPS.
+  for (int i = 0; i < B && b->pipeline; ++i)
+    if (effective_cap(inst[i].n, inst[i].M, inst[i].chi_cap) < effective_cap(inst[i].n, inst[i].M, INT32_MAX))
+      b->pipeline = false;
   hipGetDevice(&b->device);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) {

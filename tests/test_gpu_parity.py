@@ -232,3 +232,17 @@ def test_pipelined_sweeps_both_end_directions(gpu, precision):
             bits, _ = b.sample(32, 99)
             check_sampling(bits[0], n, W, k, 32, 99, 0, 1e-9 if precision == "fp64" else 1e-5)
             b.close()
+
+
+def test_lossy_cap_at_bond_five_matches_the_oracle(gpu):
+    say("case: cap below the exact rank in the bond-5 class (sequential truncations kept)")
+    n, M = 12, 6
+    W = inputs.draw_marked(n, M, inputs.SplitMix64(91))
+    inst = inputs.Instance(n, W, 4, 5)  # exact rank up to 7, cap 5
+    b = run([inst], "fp64", kernel="team")
+    d = b.diagnostics()
+    assert d["status"][0] & gmps.ST_TRUNC
+    ref = omps.run(n, W, 4, chi_cap=5)
+    p = b.marked_prob(allow_numeric=True)[0]
+    assert abs(p - ref.marked_prob()) < 1e-10
+    assert d["bond_dims"][0] == ref.bond_dims()
