@@ -113,8 +113,10 @@ typedef struct {
                            marked index is one reflection with T = 1. Same result up to
                            rounding; 0 or -1 (default): one bond-2 MPO per projector, as in
                            the paper. */
-  int32_t pipeline;     /* 0 or 1 (default): the team classes with bond caps 5 and 8 (one
-                           instance per wave) run the per-projector reflections with
+  int32_t pipeline;     /* 0 or 1 (default): the team classes with bond caps 3, 5 and 8 (and 2
+                           on GMPS_FP64; on GMPS_MIXED the bond-2 class keeps its warm-started
+                           sequential sweeps, which its M = 1 instances need) run the
+                           per-projector reflections with
                            alternating sweep directions on two waves, the truncation sweep of
                            each reflection and the canonicalisation sweep of the next in lock
                            step one site apart (no warm starts); ignored with precontract, on

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmps.so")
 SOURCES = ["gmps_group.hip", "gmps_team.hip", "gmps_team_cm2.hip", "gmps_team_cm3.hip", "gmps_team_cm5.hip",
-           "gmps_team_cm8.hip", "gmps_team_cm17.hip", "gmps_team_cm32.hip", "gmps_pipe_cm5.hip", "gmps_pipe_cm8.hip",
+           "gmps_team_cm8.hip", "gmps_team_cm17.hip", "gmps_team_cm32.hip", "gmps_pipe_cm2.hip", "gmps_pipe_cm3.hip",
+           "gmps_pipe_cm5.hip", "gmps_pipe_cm8.hip",
            "gmps_readout.hip", "gmps_api.hip", "gsv.hip"]
 ARCH = os.environ.get("GMPS_OFFLOAD_ARCH", "gfx950")
 

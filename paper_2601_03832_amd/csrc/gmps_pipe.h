@@ -1,4 +1,4 @@
-// Pipelined reflections for the team classes whose instance fills one wave (bond caps 5
+// Pipelined reflections for the team classes whose teams fit one wave (bond caps 2, 3, 5
 // and 8), per-projector MPO form (Section III-B).
 //
 // Each reflection is a canonicalisation sweep (MPO applied, rank-stopped QR) followed by a
@@ -6,8 +6,9 @@
 // directions: reflection j canonicalises left to right when j is even and right to left when
 // j is odd, so the truncation sweep of reflection j and the canonicalisation sweep of
 // reflection j+1 run in the same direction, and the second can follow the first one site
-// behind. A workgroup holds one instance on two waves: wave 0 runs the truncation sweeps,
-// wave 1 the canonicalisation sweeps, in lock step ticks of one site. Every final site tensor
+// behind. A workgroup holds a bundle of 64/TW instances with equal (n, M, k) on two waves:
+// team t of wave 0 runs instance t's truncation sweeps, team t of wave 1 its canonicalisation
+// sweeps, in lock step ticks of one site. Every final site tensor
 // the truncation wave produces is handed to the canonicalisation wave through LDS. Both waves
 // take exactly one workgroup barrier per tick and none inside a step.
 //
@@ -36,22 +37,26 @@ struct PipeLds {
   int32_t rdim[2][kBondStride];  // bonds of the canonicalised chain, by reflection parity
 };
 
-template <class S, int CM>
+template <class S, int CM, int TW>
 __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base) {
-  constexpr int TW = 64;
   using T = TeamShape<CM, TW>;
+  constexpr int TEAMS = 64 / TW;
   constexpr int D = T::D, KQ = T::KQ;
   constexpr int PQ = T::PQ, RQ = T::RQ, PJ = T::PJ, RJ = T::RJ, RU = T::RU;
   constexpr int SLOT = slot_elems(CM);
   constexpr int NE = (CM * CM + TW - 1) / TW;  // (CM x CM) box elements per lane
   constexpr bool kMixed = sizeof(S) == sizeof(float);
   const int wave = threadIdx.x / 64;  // 0: truncation, 1: canonicalisation
-  const int tl = threadIdx.x % 64;
+  const int lane = threadIdx.x % 64;
+  const int team = lane / TW;
+  const int tl = lane % TW;             // lane within the team
+  const int base = lane - tl;           // the team's first lane in its wave
   const int qc = tl / PQ, qh = tl % PQ;  // QR layout
   const int jc = tl / PJ, jh = tl % PJ;  // Jacobi layout
-  const bool real = bdp->count > 0;
-  const int me = bdp->inst[0];
-  PipeLds<S, CM>& L = *reinterpret_cast<PipeLds<S, CM>*>(lds_base);
+  const bool real = team < bdp->count;
+  // inst[] is indexed per lane: read it from memory, not from a register copy
+  const int me = bdp->inst[real ? team : 0];
+  PipeLds<S, CM>& L = reinterpret_cast<PipeLds<S, CM>*>(lds_base)[team];
   InstDev* I = P.inst + me;
   const int n = I->n;
   const int M = I->M;
@@ -66,7 +71,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
   const uint64_t k_done0 = (uint64_t)I->k_done;
   uint64_t rs_state = mix64(((uint64_t)me << 32) ^ (k_done0 * 0x9E3779B97F4A7C15ull) ^ (uint64_t)threadIdx.x);
 
-  for (int l = threadIdx.x; l < kBondStride; l += 128) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
+  for (int l = wave * TW + tl; l < kBondStride; l += 2 * TW) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
   team_sync_global();
 
   double f64 = 0.0, f32 = 0.0, drift = 0.0, truncw = 0.0;
@@ -200,7 +205,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
     cd q[RQ];
     double qdrop = 0.0;
     const int npiv = lr ? chr : chl;
-    const int kr = team_qr_wave<TW, PQ, RQ, KQ, true>(x, q, 0, qc, qh, m, Dr, npiv, rank2, &qdrop, L.V, L.tau);
+    const int kr = team_qr_wave<TW, PQ, RQ, KQ, true>(x, q, base, qc, qh, m, Dr, npiv, rank2, &qdrop, L.V, L.tau);
     truncw = fmax(truncw, qdrop);
     {
       const double mm = m, cc = Dr, kk = kr;
@@ -314,7 +319,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
     for (int e = 0; e < RU; ++e) uu[e] = {(jh + PJ * e == jc && jc < ncj) ? 1.0 : 0.0, 0.0};
     // the mixed path stores every site in complex64 (relative 6e-8): a sweep whose rotations all
     // stayed below 1e-6 leaves off-diagonals of order 1e-12 and ends the Jacobi
-    const int sweeps = team_jacobi_wave<TW, PJ, RJ, RU>(a, uu, 0, jc, jh, ncj, kJacobiTol2, skip2, P.max_sweeps,
+    const int sweeps = team_jacobi_wave<TW, PJ, RJ, RU>(a, uu, base, jc, jh, ncj, kJacobiTol2, skip2, P.max_sweeps,
                                                          kMixed ? 1e-12 : 1e-20);
     f64 += (double)sweeps * ncol * (ncol - 1) / 2.0 * 56.0 * c;
     const bool colok = jc < ncj;
@@ -328,14 +333,14 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
     const int above = (int)tsum<TW>((jh == 0 && mine > 0.0 && mine >= tol2 * smax) ? 1.0 : 0.0);
     int rk = 0;
     for (int o = 0; o < ncj; ++o) {
-      const double v = shfl_f64(mine, o * PJ);
+      const double v = shfl_f64(mine, base + o * PJ);
       rk += (v > sg || (v == sg && o < jc)) ? 1 : 0;
     }
     int chi_new = above < cap ? above : cap;
     if (chi_new < 1) chi_new = 1;
     const bool keep = colok && rk < chi_new;
-    const uint64_t kept = tballot<TW>(jh == 0 && keep, 0);
-    const int pos = __popcll(kept & ((1ull << (jc * PJ)) - 1ull));
+    const uint64_t kept = tballot<TW>(jh == 0 && keep, base);
+    const int pos = __popcll(kept & ((1ull << (base + jc * PJ)) - 1ull));
     const double dropped = tsum<TW>((jh == 0 && colok && !keep) ? sg : 0.0);
     if (stot > 0.0) truncw = fmax(truncw, dropped / stot);
     if (!isfinite(stot)) status |= GMPS_ST_NAN;
@@ -407,7 +412,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
     }
     if (extra) {
       // the identity's canonicalisation only re-gauges: its ranks are the bonds
-      for (int l = threadIdx.x; l <= n; l += 128) L.bond[l] = L.rdim[0][l];
+      for (int l = wave * TW + tl; l <= n; l += 2 * TW) L.bond[l] = L.rdim[0][l];
       team_sync_global();
     }
   }
@@ -415,25 +420,25 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
   // ------------------------------------------------------------------ write back
   // the two waves' counters are summed through the status slots of the instance record
   if (real) {
-    for (int l = threadIdx.x; l < kBondStride; l += 128) P.bonds[(int64_t)me * kBondStride + l] = L.bond[l];
+    for (int l = wave * TW + tl; l < kBondStride; l += 2 * TW) P.bonds[(int64_t)me * kBondStride + l] = L.bond[l];
   }
-  __shared__ double red[2][4];
-  __shared__ int redst[2];
+  __shared__ double red[TEAMS][2][4];
+  __shared__ int redst[TEAMS][2];
   if (tl == 0) {
-    red[wave][0] = f64;
-    red[wave][1] = f32;
-    red[wave][2] = drift;
-    red[wave][3] = truncw;
-    redst[wave] = status;
+    red[team][wave][0] = f64;
+    red[team][wave][1] = f32;
+    red[team][wave][2] = drift;
+    red[team][wave][3] = truncw;
+    redst[team][wave] = status;
   }
   team_sync_global();
-  if (real && threadIdx.x == 0) {
-    const double d = fmax(red[0][2], red[1][2]);
-    const double tw = fmax(red[0][3], red[1][3]);
-    int st = redst[0] | redst[1];
+  if (real && wave == 0 && tl == 0) {
+    const double d = fmax(red[team][0][2], red[team][1][2]);
+    const double tw = fmax(red[team][0][3], red[team][1][3]);
+    int st = redst[team][0] | redst[team][1];
     I->k_done += k;
-    I->flops64 += red[0][0] + red[1][0];
-    I->flops32 += red[0][1] + red[1][1];
+    I->flops64 += red[team][0][0] + red[team][1][0];
+    I->flops32 += red[team][0][1] + red[team][1][1];
     I->drift = fmax(I->drift, d);
     I->trunc_w = fmax(I->trunc_w, tw);
     if (d > 1e-3) st |= GMPS_ST_DRIFT;
@@ -443,8 +448,8 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
   team_sync_global();
 }
 
-// Persistent kernel of the pipelined reflections for team class W (one instance per
-// workgroup of two waves).
+// Persistent kernel of the pipelined reflections for team class W (a bundle per workgroup of
+// two waves).
 template <class S, int W>
 __global__ __launch_bounds__(128) void grover_pipe_kernel(IterParams P) {
   extern __shared__ __align__(16) char lds[];
@@ -455,7 +460,7 @@ __global__ __launch_bounds__(128) void grover_pipe_kernel(IterParams P) {
     const unsigned int bi = next_bundle;
     lds_sync();
     if ((int)bi >= P.queue->nbundles) break;
-    run_pipe<S, kWide[W].CM>(P, P.bundles + bi, lds);
+    run_pipe<S, kWide[W].CM, kWide[W].TW>(P, P.bundles + bi, lds);
   }
 }
 

@@ -19,11 +19,21 @@ static_assert(sizeof(TeamLds<double, 8, 64>) + sizeof(PcLds<8>) <= 160 * 1024 - 
 static_assert(sizeof(TeamLds<double, 17, 192>) + sizeof(PcLds<17>) <= 160 * 1024 - 64, "LDS");
 static_assert(sizeof(TeamLds<double, 32, 256>) <= 160 * 1024 - 64, "LDS");
 
-static_assert(sizeof(PipeLds<double, 5>) <= 160 * 1024 - 128, "LDS");
-static_assert(sizeof(PipeLds<double, 8>) <= 160 * 1024 - 128, "LDS");
+static_assert(sizeof(PipeLds<double, 2>) * 4 <= 160 * 1024 - 256, "LDS");
+static_assert(sizeof(PipeLds<double, 3>) * 2 <= 160 * 1024 - 256, "LDS");
+static_assert(sizeof(PipeLds<double, 5>) <= 160 * 1024 - 256, "LDS");
+static_assert(sizeof(PipeLds<double, 8>) <= 160 * 1024 - 256, "LDS");
 
-// the classes with a pipelined kernel (one instance per wave: bond caps 5 and 8)
-static bool pipe_class(int w) { return w == 2 || w == 3; }
+// the classes with a pipelined kernel (teams within one wave: bond caps 2, 3, 5 and 8). The
+// bond-2 class keeps the sequential kernel on the mixed path: its M = 1 instances need the
+// warm-started Jacobi (without it they drift, |dP| up to 5e-6 on the 4096-instance workload).
+static bool pipe_class(int w, bool mixed) { return (w >= 1 && w <= 3) || (w == 0 && !mixed); }
+
+template <int W>
+static size_t pipe_lds(bool mixed) {
+  constexpr int CM = kWide[W].CM, TW = kWide[W].TW;
+  return (mixed ? sizeof(PipeLds<float, CM>) : sizeof(PipeLds<double, CM>)) * (64 / TW);
+}
 
 template <int W>
 static size_t class_lds(bool mixed, bool pc) {
@@ -35,9 +45,14 @@ static size_t class_lds(bool mixed, bool pc) {
 }
 
 size_t team_lds_bytes(bool mixed, bool pc, bool pipe, int cls) {
-  if (pipe && !pc && pipe_class(cls - kWideBase))
-    return cls - kWideBase == 2 ? (mixed ? sizeof(PipeLds<float, 5>) : sizeof(PipeLds<double, 5>))
-                                : (mixed ? sizeof(PipeLds<float, 8>) : sizeof(PipeLds<double, 8>));
+  if (pipe && !pc && pipe_class(cls - kWideBase, mixed)) {
+    switch (cls - kWideBase) {
+      case 0: return pipe_lds<0>(mixed);
+      case 1: return pipe_lds<1>(mixed);
+      case 2: return pipe_lds<2>(mixed);
+      case 3: return pipe_lds<3>(mixed);
+    }
+  }
   switch (cls - kWideBase) {
     case 0: return class_lds<0>(mixed, pc);
     case 1: return class_lds<1>(mixed, pc);
@@ -52,7 +67,14 @@ size_t team_lds_bytes(bool mixed, bool pc, bool pipe, int cls) {
 hipError_t launch_team(bool mixed, bool pc, bool pipe, int cls, const IterParams& P, int grid, size_t lds,
                        hipStream_t st) {
   const int w = cls - kWideBase;
-  if (pipe && !pc && pipe_class(w)) return w == 2 ? launch_pipe_w<2>(mixed, P, grid, lds, st) : launch_pipe_w<3>(mixed, P, grid, lds, st);
+  if (pipe && !pc && pipe_class(w, mixed)) {
+    switch (w) {
+      case 0: return launch_pipe_w<0>(mixed, P, grid, lds, st);
+      case 1: return launch_pipe_w<1>(mixed, P, grid, lds, st);
+      case 2: return launch_pipe_w<2>(mixed, P, grid, lds, st);
+      case 3: return launch_pipe_w<3>(mixed, P, grid, lds, st);
+    }
+  }
   if (pc && w >= 0 && w < kNumWide && team_pc_class(w)) {
     switch (w) {
       case 0: return launch_team_pc_w<0>(mixed, P, grid, lds, st);
@@ -76,8 +98,14 @@ hipError_t launch_team(bool mixed, bool pc, bool pipe, int cls, const IterParams
 
 hipError_t team_occupancy(bool mixed, bool pc, bool pipe, int cls, size_t lds, int* blocks_per_cu) {
   const int w = cls - kWideBase;
-  if (pipe && !pc && pipe_class(w))
-    return w == 2 ? occupancy_pipe_w<2>(mixed, lds, blocks_per_cu) : occupancy_pipe_w<3>(mixed, lds, blocks_per_cu);
+  if (pipe && !pc && pipe_class(w, mixed)) {
+    switch (w) {
+      case 0: return occupancy_pipe_w<0>(mixed, lds, blocks_per_cu);
+      case 1: return occupancy_pipe_w<1>(mixed, lds, blocks_per_cu);
+      case 2: return occupancy_pipe_w<2>(mixed, lds, blocks_per_cu);
+      case 3: return occupancy_pipe_w<3>(mixed, lds, blocks_per_cu);
+    }
+  }
   if (pc && w >= 0 && w < kNumWide && team_pc_class(w)) {
     switch (w) {
       case 0: return occupancy_team_pc_w<0>(mixed, lds, blocks_per_cu);
