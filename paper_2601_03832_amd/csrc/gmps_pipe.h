@@ -241,8 +241,11 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
 
   // ---------------------------------------------------------------- truncation step
   // Reflection jr at site i, direction lr (the opposite of its canonicalisation); rdi: the
-  // canonicalised chain's bonds. Writes the final site i to its slot and to h.
-  auto trunc_step = [&](int jr, bool lr, int i, const int32_t* rdi, cx<S> (*h)[2][CM]) {
+  // canonicalised chain's bonds. Writes the final site i to h and, when no canonicalisation
+  // follows in the stage (keep_slot), to its slot; a following canonicalisation rewrites the
+  // slot from h.
+  auto trunc_step = [&](int jr, bool lr, int i, const int32_t* rdi, cx<S> (*h)[2][CM], bool keep_slot) {
+    const bool wr = real && keep_slot;
     const bool diff = (jr == M);
     const bool first = lr ? (i == 0) : (i == n - 1);
     const bool edge = lr ? (i == n - 1) : (i == 0);  // absorbs the carry, holds the norm
@@ -280,7 +283,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
       if (diff) drift = fmax(drift, fabs(nr - 1.0));
       const cx<S> out = store_cast<S>((diff ? 1.0 / nr : 1.0) * up(acc), rs_state, sr);
       if (act) {
-        if (real) slot[lr ? (jj * 2 * D + s * D) : (s * D + jj)] = out;
+        if (wr) slot[lr ? (jj * 2 * D + s * D) : (s * D + jj)] = out;
         if (lr) h[jj][s][0] = out; else h[0][s][jj] = out;
       }
       if (tl == 0) L.bond[lr ? n : 0] = 1;
@@ -355,10 +358,10 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
           // right to left: V^H[pos][s][jp] = conj(a) / sigma; left to right: U[jp][s][pos] = a / sigma
           const cx<S> v = store_cast<S>(lr ? rs * a[e] : rs * conj(a[e]), rs_state, sr);
           if (lr) {
-            if (real) slot[jp * 2 * D + s * D + pos] = v;
+            if (wr) slot[jp * 2 * D + s * D + pos] = v;
             h[jp][s][pos] = v;
           } else {
-            if (real) slot[pos * 2 * D + s * D + jp] = v;
+            if (wr) slot[pos * 2 * D + s * D + jp] = v;
             h[pos][s][jp] = v;
           }
         }
@@ -380,7 +383,10 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
   // Stages: canonicalisation of reflection 0 alone; then truncation j with canonicalisation
   // j+1, j = 0..J-2; then truncation J-1 alone, followed by a right-to-left canonicalisation
   // of the identity if that truncation ran left to right. Both waves take n+1 barriers per
-  // stage.
+  // stage. Within a stage the waves exchange through LDS only (hand-over buffers, bonds and
+  // ranks; the truncation wave leaves the arena to the canonicalisation wave, which rewrites
+  // each slot anyway), so the intermediate barriers order LDS only; the last one of a stage
+  // also orders the arena, which the next stage reads.
   const int64_t nstage = J == 0 ? 0 : J + 1;
   const bool fix = J > 0 && ((J - 1) & 1) == 1;  // last truncation ran left to right
   for (int64_t stg = 0; stg < nstage + (fix ? 1 : 0); ++stg) {
@@ -397,7 +403,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
       if (wave == 0) {
         if (do_t && tick < n) {
           const int i = lr_t ? tick : n - 1 - tick;
-          trunc_step((int)(jt % nrefl), lr_t, i, L.rdim[jt & 1], L.H[tick & 1]);
+          trunc_step((int)(jt % nrefl), lr_t, i, L.rdim[jt & 1], L.H[tick & 1], !do_c);
         }
       } else {
         if (do_c && tick >= 1) {
@@ -408,7 +414,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
           canon_step(extra ? 0 : (int)(jc2 % nrefl), extra, lr_c, i, h, L.rdim[extra ? 0 : (jc2 & 1)]);
         }
       }
-      team_sync_global();
+      if (tick < n) lds_sync(); else team_sync_global();
     }
     if (extra) {
       // the identity's canonicalisation only re-gauges: its ranks are the bonds
