@@ -8,7 +8,9 @@ The accuracy gate requires |P_i - sin^2((2k_i+1) theta_i)| <= 1e-6 for every ins
     python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--workload c4|c2|c3] [--kernel auto|team|group]
                     [--c5-k 48] [--no-plain] [--no-cpu] [--no-fp64-batch]
 
-Prints one JSON line. See the design doc for the roofline and baseline definitions.
+Prints one JSON line. roofline: the iterate kernel's algorithmic flops per launch (FP32
+flops weighted by the FP64/FP32 peak ratio) over its HIP-event duration, against the FP64
+vector peak. cpu_baseline: the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -270,7 +272,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: instances are independent, so a multi-GPU run "
-              "would shard the batch (see DESIGN.md); --gpus %d is not supported" % args.gpus,
+              "would shard the batch, each GPU taking a share of the instances; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
