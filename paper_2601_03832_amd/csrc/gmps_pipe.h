@@ -321,9 +321,10 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
 #pragma unroll
     for (int e = 0; e < RU; ++e) uu[e] = {(jh + PJ * e == jc && jc < ncj) ? 1.0 : 0.0, 0.0};
     // the mixed path stores every site in complex64 (relative 6e-8): a sweep whose rotations all
-    // stayed below 1e-6 leaves off-diagonals of order 1e-12 and ends the Jacobi
+    // had cosines below 1e-4 of the column norms leaves, once applied, off-diagonals of order
+    // 1e-8 (the cyclic sweep converges quadratically) and ends the Jacobi
     const int sweeps = team_jacobi_wave<TW, PJ, RJ, RU>(a, uu, base, jc, jh, ncj, kJacobiTol2, skip2, P.max_sweeps,
-                                                         kMixed ? 1e-12 : 1e-20);
+                                                         kMixed ? 1e-8 : 1e-20);
     f64 += (double)sweeps * ncol * (ncol - 1) / 2.0 * 56.0 * c;
     const bool colok = jc < ncj;
     double sg = 0.0;
