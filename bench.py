@@ -241,6 +241,41 @@ def statevector_leg(n: int, k: int):
     return out
 
 
+def fp32_accuracy_leg():
+    """Marked probability after the full k = round(pi/4 sqrt(N)) iterations for M = 1 and
+    n = 12, 14, ..., 28 (one instance of each stratum of the workload), with every step in
+    FP32 (GMPS_FP32, lane-group kernel), in mixed precision and in FP64: the precision study
+    of Section IV (Fig. 3), where the paper's FP32 MPS result falls to 0.997 at n = 18 and
+    0.877 at n = 28."""
+    from paper_2601_03832_amd import gmps
+    c4 = inputs.config_c4().instances
+    insts = [[i for i in c4 if i.n == n and i.M == 1][0] for n in range(12, 29, 2)]
+    out = {"n": [i.n for i in insts], "k": [i.k for i in insts],
+           "p_exact": [exact_p(i.n, 1, i.k) for i in insts]}
+    for prec in ("fp32", "mixed", "fp64"):
+        b = gmps.Batch(insts, prec)
+        b.init_uniform()
+        b.iterate([i.k for i in insts])
+        p = b.marked_prob(allow_numeric=True)
+        ms = b.last_iterate_ms()
+        st = int(np.bitwise_or.reduce(b.diagnostics()["status"]))
+        # the marked amplitude is first order in a drift of the rotation angle, which the
+        # probability near its maximum is not: compare it with sin((2k+1) theta) (Eq. (5))
+        amp_err = []
+        for j, i in enumerate(insts):
+            a = b.amplitudes(j, np.asarray(i.marked[:1], dtype=np.uint64))[0]
+            th = math.asin(math.sqrt(2.0 ** -i.n))
+            amp_err.append(float(abs(a - math.sin((2 * i.k + 1) * th))))
+        b.close()
+        out["p_" + prec] = [float(x) for x in p]
+        out["amp_err_" + prec] = amp_err
+        out["launch_ms_" + prec] = ms
+        out["status_" + prec] = st
+    out["note"] = ("fp32: site tensors, contractions, QR, Jacobi SVD and norms in FP32, rounded to nearest; "
+                   "mixed: complex64 sites, FP64 factorisations, stochastic rounding")
+    return out
+
+
 def traffic_record():
     try:
         with open(TRAFFIC_FILE) as f:
@@ -267,6 +302,7 @@ def main():
     ap.add_argument("--sv-k", type=int, default=500, help="iterations of the statevector comparison leg (0: skip)")
     ap.add_argument("--no-precontract", action="store_true", help="skip the pre-contracted reflections legs")
     ap.add_argument("--no-sequential", action="store_true", help="skip the sequential-sweeps leg")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the all-FP32 accuracy leg")
     ap.add_argument("--kernel", default="auto", choices=sorted(["auto", "group", "team"]),
                     help="iterate kernel: lane-group, team, or the library's choice")
     args = ap.parse_args()
@@ -388,6 +424,9 @@ def main():
     if args.sv_k > 0 and args.workload == "c4":
         line["statevector"] = statevector_leg(28, args.sv_k)
         print("bench: statevector leg done", file=sys.stderr, flush=True)
+    if not args.no_fp32 and args.workload == "c4":
+        line["fp32_accuracy"] = fp32_accuracy_leg()
+        print("bench: fp32 accuracy leg done", file=sys.stderr, flush=True)
     if not args.no_plain:
         line["plain_fp64"] = plain_fp64_rate(w, args.plain_budget)
         line["plain_fp64"]["speedup_of_batched_mixed"] = line["value"] / line["plain_fp64"]["value"]

@@ -28,6 +28,12 @@
  *    GMPS_MIXED stores site tensors in complex64 and runs the MPO application and the
  *    site contractions in complex64, while QR, SVD, norms and renormalisation run in
  *    FP64 on up-converted tiles.
+ *    GMPS_FP32 (the all-single-precision simulation whose accuracy Section IV / Fig. 3
+ *    examines) runs everything in complex64 / FP32, factorisations included, with results
+ *    rounded to nearest; it exists on the lane-group kernel only (gmps_options.kernel 0 or
+ *    1; 2 returns GMPS_E_UNSUPPORTED), so effective bond caps above 6 return
+ *    GMPS_E_UNSUPPORTED; no warm starts unless jacobi_warm = 1; default trunc_tol 1e-6.
+ *    Read-outs (marked_prob, amplitudes, sampling) accumulate in FP64 on every path.
  */
 #ifndef GMPS_H
 #define GMPS_H
@@ -41,7 +47,7 @@ extern "C" {
 
 typedef struct gmps_batch gmps_batch; /* opaque, library-owned */
 
-typedef enum { GMPS_FP64 = 0, GMPS_MIXED = 1 } gmps_prec;
+typedef enum { GMPS_FP64 = 0, GMPS_MIXED = 1, GMPS_FP32 = 2 } gmps_prec;
 
 enum {
   GMPS_OK = 0,

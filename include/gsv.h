@@ -30,7 +30,8 @@ extern "C" {
 
 typedef struct gsv_state gsv_state; /* opaque, library-owned */
 
-/* Bytes of device workspace for an n-qubit state (1 <= n <= 34) in the given precision:
+/* Bytes of device workspace for an n-qubit state (1 <= n <= 34) in the given precision
+ * (GMPS_FP64 or GMPS_MIXED; GMPS_FP32 is not a statevector precision and counts as invalid):
  * the vector (8 or 4 bytes per amplitude), the marked indices and a few reduction slots.
  * 0 on invalid input. */
 size_t gsv_workspace_bytes(int32_t n, int32_t M, gmps_prec prec);

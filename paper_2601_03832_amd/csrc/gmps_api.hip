@@ -15,9 +15,9 @@
 #include "gmps_internal.h"
 
 namespace gmps {
-hipError_t launch_group(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st);
-hipError_t group_occupancy(bool mixed, size_t lds, int* blocks_per_cu);
-size_t group_lds_bytes(bool mixed, int cls);
+hipError_t launch_group(int mode, const IterParams& P, int grid, size_t lds, hipStream_t st);
+hipError_t group_occupancy(int mode, size_t lds, int* blocks_per_cu);
+size_t group_lds_bytes(int mode, int cls);
 int team_per_bundle(int cls);
 size_t team_lds_bytes(bool mixed, bool pc, bool pipe, int cls);
 hipError_t launch_team(bool mixed, bool pc, bool pipe, int cls, const IterParams& P, int grid, size_t lds, hipStream_t st);
@@ -87,7 +87,7 @@ struct Layout {
 
 bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, int path, Layout* L, std::vector<int>* cls_out,
                     std::vector<int64_t>* site_off_out, std::vector<int64_t>* warm_off_out = nullptr) {
-  const size_t elem = prec == GMPS_MIXED ? 8 : 16;
+  const size_t elem = prec == GMPS_FP64 ? 16 : 8;
   int64_t tm = 0, ts = 0;
   size_t arena_elems = 0;
   if (cls_out) cls_out->resize(B);
@@ -127,7 +127,8 @@ bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, int path, 
 
 struct gmps_batch {
   int B = 0;
-  bool mixed = false;
+  bool mixed = false;  // complex64 site tensors (GMPS_MIXED and GMPS_FP32)
+  bool fp32 = false;   // GMPS_FP32: factorisations in FP32 too (lane-group kernel)
   hipStream_t stream = nullptr;
   int device = 0;
   char* ws = nullptr;
@@ -166,6 +167,9 @@ struct gmps_batch {
 };
 
 namespace {
+
+// lane-group kernel instantiation: 0 FP64, 1 mixed, 2 all-FP32
+int group_mode(const gmps_batch* b) { return b->fp32 ? 2 : b->mixed ? 1 : 0; }
 
 int hip_fail(hipError_t e, const char* what) {
   if (e != hipSuccess) {
@@ -212,7 +216,7 @@ const char* gmps_strerror(int status) {
 }
 
 size_t gmps_workspace_bytes(const gmps_instance* inst, int32_t B, gmps_prec prec) {
-  if (!inst || B <= 0 || (prec != GMPS_FP64 && prec != GMPS_MIXED)) return 0;
+  if (!inst || B <= 0 || (prec != GMPS_FP64 && prec != GMPS_MIXED && prec != GMPS_FP32)) return 0;
   // enough for either iterate kernel, so the choice can be made at gmps_create()
   Layout Lg, Lt;
   if (!compute_layout(inst, B, prec, kPathGroup, &Lg, nullptr, nullptr)) return 0;
@@ -224,18 +228,23 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
                 const gmps_options* opt, void* dev_workspace, size_t ws_bytes, void* hip_stream) {
   if (!out) return GMPS_E_ARG;
   *out = nullptr;
-  if (!inst || B <= 0 || !marked || (prec != GMPS_FP64 && prec != GMPS_MIXED)) return GMPS_E_ARG;
+  if (!inst || B <= 0 || !marked || (prec != GMPS_FP64 && prec != GMPS_MIXED && prec != GMPS_FP32)) return GMPS_E_ARG;
   for (int i = 0; i < B; ++i)
     if (!valid_instance(inst[i])) return GMPS_E_ARG;
   if (opt && (opt->kernel < 0 || opt->kernel > kPathTeam)) return GMPS_E_ARG;
-  const int path = resolve_path(opt ? opt->kernel : kPathAuto);
+  const bool fp32 = prec == GMPS_FP32;
+  // the all-FP32 path exists on the lane-group kernel only
+  if (fp32 && opt && opt->kernel == kPathTeam) return GMPS_E_UNSUPPORTED;
+  const int path = fp32 ? kPathGroup : resolve_path(opt ? opt->kernel : kPathAuto);
   const bool precontract = opt && opt->precontract > 0;
   if (precontract && path != kPathTeam) return GMPS_E_UNSUPPORTED;
   Layout L;
   std::vector<int> cls;
   std::vector<int64_t> site_off, warm_off;
-  for (int i = 0; i < B; ++i)
-    if (pick_class(inst[i].n, inst[i].M, inst[i].chi_cap, path) < 0) return GMPS_E_UNSUPPORTED;
+  for (int i = 0; i < B; ++i) {
+    const int c = pick_class(inst[i].n, inst[i].M, inst[i].chi_cap, path);
+    if (c < 0 || (fp32 && is_wide(c))) return GMPS_E_UNSUPPORTED;
+  }
   if (!compute_layout(inst, B, prec, path, &L, &cls, &site_off, &warm_off)) return GMPS_E_ARG;
   // marked sets: in range and distinct within an instance
   int64_t tm = 0;
@@ -261,13 +270,14 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   gmps_batch* b = new (std::nothrow) gmps_batch();
   if (!b) return GMPS_E_ARG;
   b->B = B;
-  b->mixed = prec == GMPS_MIXED;
+  b->mixed = prec != GMPS_FP64;
+  b->fp32 = fp32;
   b->stream = reinterpret_cast<hipStream_t>(hip_stream);
   b->ws = reinterpret_cast<char*>(dev_workspace);
   b->lay = L;
   b->path = path;
   for (int i = 0; i < B; ++i) b->max_cm = std::max(b->max_cm, class_cm(cls[i]));
-  b->trunc_tol = b->mixed ? 5e-7 : 1e-12;
+  b->trunc_tol = fp32 ? 1e-6 : b->mixed ? 5e-7 : 1e-12;
   if (opt) {
     if (opt->trunc_tol > 0) b->trunc_tol = opt->trunc_tol;
     if (opt->max_sweeps > 0) b->max_sweeps = opt->max_sweeps;
@@ -355,8 +365,9 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   P.skip_tol = std::min(b->trunc_tol, b->mixed ? 1e-7 : 1e-15);
   P.rank_tol = b->trunc_tol;
   P.max_sweeps = b->max_sweeps;
-  P.stoch_round = (b->mixed && b->stoch_round) ? 1 : 0;
-  const bool warm_on = b->jacobi_warm > 0 || (b->jacobi_warm == 0 && b->mixed);
+  // stochastic rounding applies to FP64 results stored as complex64 (none on the all-FP32 path)
+  P.stoch_round = (b->mixed && !b->fp32 && b->stoch_round) ? 1 : 0;
+  const bool warm_on = b->jacobi_warm > 0 || (b->jacobi_warm == 0 && b->mixed && !b->fp32);
   P.warm = warm_on ? reinterpret_cast<void*>(b->ws + L.warm) : nullptr;
   *out = b;
   return GMPS_OK;
@@ -410,7 +421,7 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
     // a site step of either kernel takes roughly (CM + 1) times a fixed latency
     const int refl = g.first.whole ? 2 : g.first.M + 1;  // reflections per iteration
     const double cost = (double)g.first.k * refl * std::max(1, g.first.n - 1) * (class_cm(cls) + 1.0);
-    lds[kind] = std::max(lds[kind], team ? team_lds_bytes(b->mixed, b->precontract, b->pipeline, cls) : group_lds_bytes(b->mixed, cls) * per);
+    lds[kind] = std::max(lds[kind], team ? team_lds_bytes(b->mixed, b->precontract, b->pipeline, cls) : group_lds_bytes(group_mode(b), cls) * per);
     for (size_t s = 0; s < g.second.size(); s += per) {
       Bundle bd;
       std::memset(&bd, 0, sizeof(bd));
@@ -453,7 +464,7 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
     grid[kd] = 0;
     if (count[kd] == 0) continue;
     int per_cu = 0;
-    if (kd == 0) GMPS_HIP(group_occupancy(b->mixed, lds[kd], &per_cu));
+    if (kd == 0) GMPS_HIP(group_occupancy(group_mode(b), lds[kd], &per_cu));
     else GMPS_HIP(team_occupancy(b->mixed, b->precontract, b->pipeline, kWideBase + kd - 1, lds[kd], &per_cu));
     if (b->waves_per_cu > 0) per_cu = std::min(per_cu, b->waves_per_cu);
     per_cu = std::max(per_cu, 1);
@@ -501,7 +512,7 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
       // the previous unitary does not shorten the Jacobi, and on the 4096-instance workload
       // it raised the largest mixed-precision error of P from 7e-7 to 1.3e-6)
       if (kd > 0 && b->precontract && b->jacobi_warm == 0 && kWide[kd - 1].CM > 2) P.warm = nullptr;
-      e = kd == 0 ? launch_group(b->mixed, P, grid[kd], lds[kd], ks)
+      e = kd == 0 ? launch_group(group_mode(b), P, grid[kd], lds[kd], ks)
                   : launch_team(b->mixed, b->precontract, b->pipeline, kWideBase + kd - 1, P, grid[kd], lds[kd], ks);
       if (e == hipSuccess && !on_main) {
         e = hipEventRecord(b->join_ev[kd], ks);

@@ -50,6 +50,9 @@ template <class S>
 __device__ __forceinline__ cd up(cx<S> a) { return {(double)a.re, (double)a.im}; }
 template <class S>
 __device__ __forceinline__ cx<S> czero() { return {(S)0, (S)0}; }
+// conversion between complex types (the identity when T == U)
+template <class T, class U>
+__device__ __forceinline__ cx<T> cvt(cx<U> a) { return {(T)a.re, (T)a.im}; }
 
 // ---------------------------------------------------------------------- stochastic rounding
 // Unbiased (stochastic) rounding of a double to float: 29 random bits are added to the low
@@ -68,6 +71,9 @@ __device__ __forceinline__ float sround_f32(double x, uint32_t r29) {
   mag &= ~((1ull << 29) - 1ull);
   return (float)__longlong_as_double((long long)(sign | mag));
 }
+// An FP32 result (all-FP32 path) is stored as it is.
+template <class S>
+__device__ __forceinline__ cx<S> store_cast(cx<float> a, uint64_t&, bool) { return {(S)a.re, (S)a.im}; }
 // Conversion of an FP64 result to the storage type S.
 template <class S>
 __device__ __forceinline__ cx<S> store_cast(cd a, uint64_t& st, bool sr) {
@@ -118,10 +124,31 @@ __device__ __forceinline__ double gsum(double v) {
 }
 template <int G>
 __device__ __forceinline__ cd gsum(cd v) { return {gsum<G>(v.re), gsum<G>(v.im)}; }
+// the same butterfly on FP32 values (all-FP32 path)
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int G>
+__device__ __forceinline__ float gsum(float v) {
+  static_assert(G == 2 || G == 4 || G == 8 || G == 16 || G == 32, "group size");
+  v += dpp_f32<0xB1>(v);
+  if (G > 2) v += dpp_f32<0x4E>(v);
+  if (G > 4) v += dpp_f32<0x141>(v);
+  if (G > 8) v += dpp_f32<0x140>(v);
+  if (G > 16) v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ cx<float> gsum(cx<float> v) { return {gsum<G>(v.re), gsum<G>(v.im)}; }
 // value held by group lane src, delivered to every lane of the group
 template <int G>
 __device__ __forceinline__ cd gbcast(cd v, int gl, int src) {
   return gsum<G>(gl == src ? v : cd{0.0, 0.0});
+}
+template <int G>
+__device__ __forceinline__ cx<float> gbcast(cx<float> v, int gl, int src) {
+  return gsum<G>(gl == src ? v : cx<float>{0.0f, 0.0f});
 }
 
 // Raw v_rsq_f64 / v_rcp_f64 are accurate to about 2^-23; two Newton steps bring them to
@@ -140,6 +167,21 @@ __device__ __forceinline__ double rcp_acc(double x) {
   r = fma(-x, y, 1.0);
   return fma(y, r, y);
 }
+// FP32 (all-FP32 path): v_rsq_f32 / v_rcp_f32 are within about 1 ulp; one Newton step
+// each brings them to rounding of the working precision.
+__device__ __forceinline__ float rsqrt_acc(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  return fmaf(0.5f * y, fmaf(-x * y, y, 1.0f), y);
+}
+__device__ __forceinline__ float rcp_acc(float x) {
+  const float y = __builtin_amdgcn_rcpf(x);
+  return fmaf(y, fmaf(-x, y, 1.0f), y);
+}
+// raw hardware estimates, for quantities that need only angle accuracy
+__device__ __forceinline__ double rsq_raw(double x) { return __builtin_amdgcn_rsq(x); }
+__device__ __forceinline__ float rsq_raw(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rcp_raw(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ float rcp_raw(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Orders LDS traffic between the lanes of the (single-wave) workgroup without waiting
 // for outstanding global memory operations.
@@ -167,8 +209,9 @@ __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a < b ? b : a; }
 
 // (x, y) <- (c x - conj(se) y, se x + c y) for real c and complex se = s e^{i phi}.
-__device__ __forceinline__ void rot2(cd& x, cd& y, double c, cd se) {
-  const cd x0 = x, y0 = y;
+template <class T>
+__device__ __forceinline__ void rot2(cx<T>& x, cx<T>& y, T c, cx<T> se) {
+  const cx<T> x0 = x, y0 = y;
   x.re = fma(c, x0.re, fma(-se.re, y0.re, -se.im * y0.im));
   x.im = fma(c, x0.im, fma(-se.re, y0.im, se.im * y0.re));
   y.re = fma(c, y0.re, fma(se.re, x0.re, -se.im * x0.im));

@@ -17,8 +17,9 @@
 //                          Jacobi SVD, keep sigma >= tol * sigma_max (at most the cap),
 //                          V^dagger stays, U Sigma moves left.
 //   site 0               : Q_0 * (U Sigma)_1, renormalised after the diffusion.
-// QR, SVD and norms are FP64. The storage / contraction type S is double (FP64 path) or
-// float (mixed path: complex64 site tensors and contractions).
+// The storage / contraction type S is double (FP64 path) or float (complex64 site tensors
+// and contractions). The factorisation type C (QR, SVD, norms) is double on the FP64 and
+// mixed paths and float on the all-FP32 path.
 #include <hip/hip_runtime.h>
 
 #include "gmps_device.h"
@@ -37,15 +38,16 @@ namespace gmps {
 // A block has full rank and is eliminated in its own order; the projector block adds one
 // direction (rank chi + 1 in all), which need not lie in the block's first column, so from
 // step npiv on the remaining column with the largest residual norm is pivoted in first.
-template <int G, int NC, int KMAX>
-__device__ __forceinline__ int householder_qr_rank(cd (&x)[NC], cd (&q)[KMAX], int (&perm)[NC], int gl, int m,
-                                                   int c, int npiv, double rank2, double* dropped) {
+template <class C, int G, int NC, int KMAX>
+__device__ __forceinline__ int householder_qr_rank(cx<C> (&x)[NC], cx<C> (&q)[KMAX], int (&perm)[NC], int gl, int m,
+                                                   int c, int npiv, C rank2, double* dropped) {
+  using T = cx<C>;
   const int kmax = min(min(m, c), KMAX);
-  cd hv[KMAX];
-  double tau[KMAX];
+  T hv[KMAX];
+  C tau[KMAX];
 #pragma unroll
   for (int k = 0; k < NC; ++k) perm[k] = k;
-  double t0 = 0.0;
+  C t0 = 0;
 #pragma unroll
   for (int k = 0; k < NC; ++k) t0 += norm2(x[k]);
   t0 = gsum<G>(gl < m ? t0 : 0.0);
@@ -53,13 +55,13 @@ __device__ __forceinline__ int householder_qr_rank(cd (&x)[NC], cd (&q)[KMAX], i
   bool done = false;
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
-    hv[j] = {0.0, 0.0};
-    tau[j] = 0.0;
+    hv[j] = czero<C>();
+    tau[j] = 0;
     if (j > 0 && !done && j < kmax) {
-      double tj = 0.0;
+      C tj = 0;
 #pragma unroll
       for (int k = j; k < NC; ++k) tj += norm2(x[k]);
-      tj = gsum<G>((gl >= j && gl < m) ? tj : 0.0);
+      tj = gsum<G>((gl >= j && gl < m) ? tj : C(0));
       if (tj <= rank2 * t0) {
         done = true;
         kr = j;
@@ -67,12 +69,12 @@ __device__ __forceinline__ int householder_qr_rank(cd (&x)[NC], cd (&q)[KMAX], i
     }
     if (!done && j < kmax && j >= npiv) {
       // pivot: the remaining column with the largest norm below row j
-      double best = -1.0;
+      C best = -1;
       int p = j;
 #pragma unroll
       for (int k = j; k < NC; ++k) {
         if (k < c) {
-          const double nk = gsum<G>((gl >= j && gl < m) ? norm2(x[k]) : 0.0);
+          const C nk = gsum<G>((gl >= j && gl < m) ? norm2(x[k]) : C(0));
           if (nk > best) {
             best = nk;
             p = k;
@@ -82,7 +84,7 @@ __device__ __forceinline__ int householder_qr_rank(cd (&x)[NC], cd (&q)[KMAX], i
 #pragma unroll
       for (int k = j + 1; k < NC; ++k) {
         if (k == p) {
-          const cd t = x[j];
+          const T t = x[j];
           x[j] = x[k];
           x[k] = t;
           const int pt = perm[j];
@@ -92,54 +94,54 @@ __device__ __forceinline__ int householder_qr_rank(cd (&x)[NC], cd (&q)[KMAX], i
       }
     }
     if (!done && j < kmax) {
-      const cd xj = x[j];
-      const double sub = gsum<G>((gl > j && gl < m) ? norm2(xj) : 0.0);
-      const cd alpha = gbcast<G>(xj, gl, j);
-      const double a2 = norm2(alpha);
-      const bool refl = sub > 0.0;
-      const double ra = a2 > 0.0 ? rsqrt_acc(a2) : 0.0;
-      const double aa = a2 * ra;                          // |alpha|
-      const double n2 = a2 + sub;
-      const double nrm = refl ? n2 * rsqrt_acc(n2) : aa;  // norm of column j from the diagonal down
-      const cd ph = a2 > 0.0 ? cd{alpha.re * ra, alpha.im * ra} : cd{1.0, 0.0};
-      const cd beta = {-ph.re * nrm, -ph.im * nrm};
-      const double t = refl ? rcp_acc(nrm * (nrm + aa)) : 0.0;
-      cd v = (gl == j) ? alpha - beta : ((gl > j && gl < m) ? xj : cd{0.0, 0.0});
-      if (!refl) v = {0.0, 0.0};
-      cd w[NC];
+      const T xj = x[j];
+      const C sub = gsum<G>((gl > j && gl < m) ? norm2(xj) : C(0));
+      const T alpha = gbcast<G>(xj, gl, j);
+      const C a2 = norm2(alpha);
+      const bool refl = sub > 0;
+      const C ra = a2 > 0 ? rsqrt_acc(a2) : C(0);
+      const C aa = a2 * ra;                               // |alpha|
+      const C n2 = a2 + sub;
+      const C nrm = refl ? n2 * rsqrt_acc(n2) : aa;       // norm of column j from the diagonal down
+      const T ph = a2 > 0 ? T{alpha.re * ra, alpha.im * ra} : T{C(1), C(0)};
+      const T beta = {-ph.re * nrm, -ph.im * nrm};
+      const C t = refl ? rcp_acc(nrm * (nrm + aa)) : C(0);
+      T v = (gl == j) ? alpha - beta : ((gl > j && gl < m) ? xj : czero<C>());
+      if (!refl) v = czero<C>();
+      T w[NC];
 #pragma unroll
       for (int k = j + 1; k < NC; ++k)
         if (k < c) w[k] = gsum<G>(cmulc(v, x[k]));
 #pragma unroll
       for (int k = j + 1; k < NC; ++k)
         if (k < c) {
-          const cd tw = t * w[k];
+          const T tw = t * w[k];
           x[k] = x[k] - v * tw;
         }
-      if (refl) x[j] = (gl == j) ? beta : ((gl > j) ? cd{0.0, 0.0} : xj);
+      if (refl) x[j] = (gl == j) ? beta : ((gl > j) ? czero<C>() : xj);
       hv[j] = v;
       tau[j] = t;
     }
   }
-  double tk = 0.0;
+  C tk = 0;
 #pragma unroll
-  for (int k = 0; k < NC; ++k) tk += (k >= kr) ? norm2(x[k]) : 0.0;
-  tk = gsum<G>((gl >= kr && gl < m) ? tk : 0.0);
-  *dropped = t0 > 0.0 ? tk / t0 : 0.0;
+  for (int k = 0; k < NC; ++k) tk += (k >= kr) ? norm2(x[k]) : C(0);
+  tk = gsum<G>((gl >= kr && gl < m) ? tk : C(0));
+  *dropped = t0 > 0 ? (double)(tk / t0) : 0.0;
   // thin Q = H_0 ... H_{kr-1} [I; 0], applied right to left
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) q[k] = {(gl == k && k < kr) ? 1.0 : 0.0, 0.0};
+  for (int k = 0; k < KMAX; ++k) q[k] = {(gl == k && k < kr) ? C(1) : C(0), C(0)};
 #pragma unroll
   for (int j = KMAX - 1; j >= 0; --j) {
-    if (j < kr && tau[j] != 0.0) {
-      cd w[KMAX];
+    if (j < kr && tau[j] != 0) {
+      T w[KMAX];
 #pragma unroll
       for (int k = j; k < KMAX; ++k)
         if (k < kr) w[k] = gsum<G>(cmulc(hv[j], q[k]));
 #pragma unroll
       for (int k = j; k < KMAX; ++k)
         if (k < kr) {
-          const cd tw = tau[j] * w[k];
+          const T tw = tau[j] * w[k];
           q[k] = q[k] - hv[j] * tw;
         }
     }
@@ -160,25 +162,40 @@ __device__ __forceinline__ int householder_qr_rank(cd (&x)[NC], cd (&q)[KMAX], i
 // norm): such a column is dropped by the truncation, and leaving it unrotated changes the
 // kept part by no more than its own norm. Convergence is quadratic, so a sweep whose
 // largest relative off-diagonal was below 1e-10 leaves ~1e-20 behind and ends the iteration.
-template <int W, int NC, int NCM>
-__device__ __forceinline__ int jacobi_fixed(cd (&a)[NCM], cd (&v)[NCM], double tol2, double skip2,
+// The all-FP32 instantiation stops at a relative off-diagonal of 1e-5 instead (its rounding
+// floor is near 1e-7), and its guards against underflow and overflow are FP32 ones.
+template <class C>
+struct JacobiLimits;
+template <>
+struct JacobiLimits<double> {
+  static constexpr double stop = 1e-20, tiny = 1e-300, huge = 1e300;
+};
+template <>
+struct JacobiLimits<float> {
+  static constexpr float stop = 1e-10f, tiny = 1e-36f, huge = 1e30f;
+};
+
+template <class C, int W, int NC, int NCM>
+__device__ __forceinline__ int jacobi_fixed(cx<C> (&a)[NCM], cx<C> (&v)[NCM], C tol2, C skip2,
                                             int max_sweeps) {
+  using T = cx<C>;
+  using Lim = JacobiLimits<C>;
   int sweeps = 0;
   bool more = true;
   while (more && sweeps < max_sweeps) {
     ++sweeps;
-    double nrm[NC];
-    double amax = 0.0;
+    C nrm[NC];
+    C amax = 0;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       nrm[k] = gsum<W>(norm2(a[k]));
       amax = fmax(amax, nrm[k]);
     }
-    const double floor2 = skip2 * amax;
+    const C floor2 = skip2 * amax;
     more = false;
 #pragma unroll
     for (int r = 0; r < NC - 1; ++r) {
-      cd ga[NC / 2];
+      T ga[NC / 2];
 #pragma unroll
       for (int p = 0; p < NC / 2; ++p) {
         const int i = cmin(circ_a(NC, r, p), circ_b(NC, r, p));
@@ -189,24 +206,24 @@ __device__ __forceinline__ int jacobi_fixed(cd (&a)[NCM], cd (&v)[NCM], double t
       for (int p = 0; p < NC / 2; ++p) {
         const int i = cmin(circ_a(NC, r, p), circ_b(NC, r, p));
         const int j = cmax(circ_a(NC, r, p), circ_b(NC, r, p));
-        const double g2 = norm2(ga[p]);
-        const double ab = nrm[i] * nrm[j];
-        if (g2 > tol2 * ab && fmin(nrm[i], nrm[j]) > floor2 && g2 > 1e-300) {
-          more |= g2 > 1e-20 * ab;
-          const double rg = rsqrt_acc(g2);                       // 1/|gamma|
-          const double zeta = (nrm[j] - nrm[i]) * (0.5 * rg);
-          const double az = fabs(zeta);
-          const double u = fmin(fma(zeta, zeta, 1.0), 1e300);
-          const double den = az + u * __builtin_amdgcn_rsq(u);  // |zeta| + sqrt(1 + zeta^2)
-          double t = __builtin_amdgcn_rcp(den);
-          t = fma(t, fma(-den, t, 1.0), t);
+        const C g2 = norm2(ga[p]);
+        const C ab = nrm[i] * nrm[j];
+        if (g2 > tol2 * ab && fmin(nrm[i], nrm[j]) > floor2 && g2 > Lim::tiny) {
+          more |= g2 > Lim::stop * ab;
+          const C rg = rsqrt_acc(g2);                          // 1/|gamma|
+          const C zeta = (nrm[j] - nrm[i]) * (C(0.5) * rg);
+          const C az = fabs(zeta);
+          const C u = fmin(fma(zeta, zeta, C(1)), Lim::huge);
+          const C den = az + u * rsq_raw(u);                   // |zeta| + sqrt(1 + zeta^2)
+          C t = rcp_raw(den);
+          t = fma(t, fma(-den, t, C(1)), t);
           t = copysign(t, zeta);
-          const double cs = rsqrt_acc(fma(t, t, 1.0));
-          const double sn = cs * t;
-          const cd se = {sn * ga[p].re * rg, sn * ga[p].im * rg};  // s e^{i phi}
+          const C cs = rsqrt_acc(fma(t, t, C(1)));
+          const C sn = cs * t;
+          const T se = {sn * ga[p].re * rg, sn * ga[p].im * rg};  // s e^{i phi}
           rot2(a[i], a[j], cs, se);
           rot2(v[i], v[j], cs, se);
-          const double tg = t * (g2 * rg);
+          const C tg = t * (g2 * rg);
           nrm[i] -= tg;
           nrm[j] += tg;
         }
@@ -220,31 +237,31 @@ __device__ __forceinline__ int jacobi_fixed(cd (&a)[NCM], cd (&v)[NCM], double t
 // round-robin schedule is full.
 // v[] must hold row gl of the starting unitary (the identity, or a warm start whose
 // product with the tile is already in a[]).
-template <int W, int NCM>
-__device__ __forceinline__ int jacobi_svd(cd (&a)[NCM], cd (&v)[NCM], int gl, int c, double tol2,
-                                          double skip2, int max_sweeps) {
+template <class C, int W, int NCM>
+__device__ __forceinline__ int jacobi_svd(cx<C> (&a)[NCM], cx<C> (&v)[NCM], int gl, int c, C tol2,
+                                          C skip2, int max_sweeps) {
   switch (c) {
-    case 2: return jacobi_fixed<W, 2, NCM>(a, v, tol2, skip2, max_sweeps);
-    case 4: if constexpr (NCM >= 4) return jacobi_fixed<W, 4, NCM>(a, v, tol2, skip2, max_sweeps); break;
-    case 6: if constexpr (NCM >= 6) return jacobi_fixed<W, 6, NCM>(a, v, tol2, skip2, max_sweeps); break;
-    case 8: if constexpr (NCM >= 8) return jacobi_fixed<W, 8, NCM>(a, v, tol2, skip2, max_sweeps); break;
-    case 10: if constexpr (NCM >= 10) return jacobi_fixed<W, 10, NCM>(a, v, tol2, skip2, max_sweeps); break;
-    case 12: if constexpr (NCM >= 12) return jacobi_fixed<W, 12, NCM>(a, v, tol2, skip2, max_sweeps); break;
+    case 2: return jacobi_fixed<C, W, 2, NCM>(a, v, tol2, skip2, max_sweeps);
+    case 4: if constexpr (NCM >= 4) return jacobi_fixed<C, W, 4, NCM>(a, v, tol2, skip2, max_sweeps); break;
+    case 6: if constexpr (NCM >= 6) return jacobi_fixed<C, W, 6, NCM>(a, v, tol2, skip2, max_sweeps); break;
+    case 8: if constexpr (NCM >= 8) return jacobi_fixed<C, W, 8, NCM>(a, v, tol2, skip2, max_sweeps); break;
+    case 10: if constexpr (NCM >= 10) return jacobi_fixed<C, W, 10, NCM>(a, v, tol2, skip2, max_sweeps); break;
+    case 12: if constexpr (NCM >= 12) return jacobi_fixed<C, W, 12, NCM>(a, v, tol2, skip2, max_sweeps); break;
     default: break;
   }
   return 0;
 }
 
 // ---------------------------------------------------------------------------- per-group LDS
-template <class S, int CM>
+template <class S, class C, int CM>
 struct GroupLds {
   static constexpr int D = 2 * CM;
-  cd X[2 * D][D];           // staged QR tile (rows (a, s)) or SVD tile (rows a)
-  cd R[D][D];               // R of the previous QR step
-  cd Y[D][CM];              // U Sigma of the previous SVD step
+  cx<C> X[2 * D][D];        // staged QR tile (rows (a, s)) or SVD tile (rows a)
+  cx<C> R[D][D];            // R of the previous QR step
+  cx<C> Y[D][CM];           // U Sigma of the previous SVD step
   cx<S> A[CM][2][CM];       // compressed site tensor, zero padded
-  cd U[CM + 2][CM + 2];     // warm-start unitary
-  cd UG[CM + 2][CM + 2];    // U^H U of the warm start
+  cx<C> U[CM + 2][CM + 2];  // warm-start unitary
+  cx<C> UG[CM + 2][CM + 2]; // U^H U of the warm start
   int32_t bond[kBondStride];
   int32_t rdim[kBondStride];
 };
@@ -291,11 +308,13 @@ struct WPrefetch {
 };
 
 // ------------------------------------------------------------------------------ one bundle
-template <class S, int CM, int G, int WS>
+template <class S, class C, int CM, int G, int WS>
 __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_base) {
+  using T = cx<C>;
   constexpr int D = 2 * CM;
   constexpr int SLOT = slot_elems(CM);
   constexpr bool kMixed = sizeof(S) == sizeof(float);
+  constexpr bool kF32 = sizeof(C) == sizeof(float);  // factorisations in FP32
   constexpr int KQ = CM + 1;                 // rank of a tile after the bond-2 MPO, at most
   constexpr int KJ = (KQ + 1) & ~1;          // Jacobi columns (even)
   static_assert(G >= 2 * KQ, "a lane group must hold a QR tile's rows");
@@ -306,7 +325,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
   const bool real = grp < bdp->count;
   // inst[] is indexed per lane: read it from memory, not from a register copy
   const int me = bdp->inst[real ? grp : 0];
-  GroupLds<S, CM>& L = reinterpret_cast<GroupLds<S, CM>*>(lds_base)[grp];
+  GroupLds<S, C, CM>& L = reinterpret_cast<GroupLds<S, C, CM>*>(lds_base)[grp];
   InstDev* I = P.inst + me;
   const int n = I->n;
   const int M = I->M;
@@ -314,8 +333,8 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
   const int64_t k = bdp->k;
   cx<S>* arena = reinterpret_cast<cx<S>*>(P.arena) + I->site_off;
   const uint64_t* W = P.marked + I->marked_off;
-  const double tol2 = P.trunc_tol * P.trunc_tol;
-  const double rank2 = P.rank_tol * P.rank_tol;
+  const C tol2 = (C)(P.trunc_tol * P.trunc_tol);
+  const C rank2 = (C)(P.rank_tol * P.rank_tol);
   const bool sr = P.stoch_round != 0;
   WarmRec* warm = P.warm ? reinterpret_cast<WarmRec*>(reinterpret_cast<char*>(P.warm) + I->warm_off) : nullptr;
   // read once: a global load inside the sweeps would be waited for at its use
@@ -342,12 +361,12 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
           const cx<S> as = sel(a0, a1, gl);
           o = {(S)c0 * as.re + (S)c1 * pa.re, (S)c0 * as.im + (S)c1 * pa.im};
         }
-        double nn = gsum<G>(gl < 2 ? norm2(up(o)) : 0.0);
+        const C nn = gsum<G>(gl < 2 ? norm2(cvt<C>(o)) : C(0));
         if (diff) {
-          const double nr = sqrt(nn);
-          drift = fmax(drift, fabs(nr - 1.0));
-          if (!(nn > 0.0) || !isfinite(nn)) status |= GMPS_ST_NAN;
-          o = down<S>((1.0 / nr) * up(o));
+          const C nr = sqrt(nn);
+          drift = fmax(drift, fabs((double)nr - 1.0));
+          if (!(nn > 0) || !isfinite(nn)) status |= GMPS_ST_NAN;
+          o = cvt<S>((C(1) / nr) * cvt<C>(o));
         }
         lds_sync();
         if (real && gl < 2) arena[gl * D] = o;
@@ -364,7 +383,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
         // ---------------------------------------------- QR sweep with the MPO fused
         int r = 1;
         if (gl == 0) {
-          L.R[0][0] = {1.0, 0.0};
+          L.R[0][0] = {C(1), C(0)};
           L.rdim[0] = 1;
         }
         APrefetch<S, CM, G> apre;
@@ -400,15 +419,15 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
                           if (ap < chl) {
                             const cx<S> a0 = L.A[ap][0][b], a1 = L.A[ap][1][b];
                             const cx<S> wa = beta == 0 ? sel(a0, a1, s) : proj_apply<S>(a0, a1, s, diff, xb);
-                            acc = cfma(acc, down<S>(L.R[a][beta * chl + ap]), wa);
+                            acc = cfma(acc, cvt<S>(L.R[a][beta * chl + ap]), wa);
                           }
                       }
                     }
-                    L.X[gl][beta * chr + b] = up(acc);
+                    L.X[gl][beta * chr + b] = cvt<C>(acc);
                   }
                 }
               }
-              for (int col = Dr; col < D; ++col) L.X[gl][col] = {0.0, 0.0};
+              for (int col = Dr; col < D; ++col) L.X[gl][col] = czero<C>();
             } else {
               cx<S> acc = czero<S>();
               if (rowok) {
@@ -420,11 +439,11 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
                     if (ap < chl) {
                       const cx<S> a0 = L.A[ap][0][0], a1 = L.A[ap][1][0];
                       const cx<S> wa = al == 0 ? sel(a0, a1, s) : proj_apply<S>(a0, a1, s, diff, xb);
-                      acc = cfma(acc, down<S>(L.R[a][al * chl + ap]), cal * wa);
+                      acc = cfma(acc, cvt<S>(L.R[a][al * chl + ap]), cal * wa);
                     }
                 }
               }
-              L.X[gl][0] = up(acc);
+              L.X[gl][0] = cvt<C>(acc);
             }
           }
           const double macs = (double)r * Dl * 2.0 * Dr;
@@ -442,18 +461,19 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
             lds_sync();
             break;
           }
-          cd xr[D], q[KQ];
+          T xr[D], q[KQ];
 #pragma unroll
-          for (int col = 0; col < D; ++col) xr[col] = (gl < 2 * D) ? L.X[gl][col] : cd{0.0, 0.0};
+          for (int col = 0; col < D; ++col) xr[col] = (gl < 2 * D) ? L.X[gl][col] : czero<C>();
           const int m = 2 * r;
           double qdrop = 0.0;
           int perm[D];
-          const int kr = householder_qr_rank<G, D, KQ>(xr, q, perm, gl, m, Dr, last ? Dr : chr, rank2, &qdrop);
+          const int kr = householder_qr_rank<C, G, D, KQ>(xr, q, perm, gl, m, Dr, last ? Dr : chr, rank2, &qdrop);
           truncw = fmax(truncw, qdrop);
           {
             const double mm = m, cc = Dr, kk = kr;
-            f64 += 8.0 * (2.0 * mm * cc * kk - (mm + cc) * kk * kk + 2.0 * kk * kk * kk / 3.0) +
-                   8.0 * (2.0 * mm * kk * kk - 2.0 * kk * kk * kk / 3.0);
+            const double fl = 8.0 * (2.0 * mm * cc * kk - (mm + cc) * kk * kk + 2.0 * kk * kk * kk / 3.0) +
+                              8.0 * (2.0 * mm * kk * kk - 2.0 * kk * kk * kk / 3.0);
+            if (kF32) f32 += fl; else f64 += fl;
           }
           if (real && gl < m) {
             const int a = gl >> 1, s = gl & 1;
@@ -464,7 +484,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
           if (gl < kr) {
             // R P^T: column t of the pivoted R belongs to column perm[t] of the tile
 #pragma unroll
-            for (int col = 0; col < D; ++col) L.R[gl][perm[col]] = col < gl ? cd{0.0, 0.0} : xr[col];
+            for (int col = 0; col < D; ++col) L.R[gl][perm[col]] = col < gl ? czero<C>() : xr[col];
           }
           if (gl == 0) L.rdim[i + 1] = kr;
           r = kr;
@@ -475,7 +495,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
         // At site i the tile is M = Q_i (U Sigma)_{i+1} reshaped (r_i, 2 chi'). Jacobi runs on
         // the r_i columns of M^H (rows (s, j) on lanes): M^H J = V Sigma with J = U, so
         // V^H = Sigma^{-1} (M^H J)^H stays in site i and U Sigma = J Sigma moves left.
-        if (gl == 0) L.Y[0][0] = {1.0, 0.0};
+        if (gl == 0) L.Y[0][0] = {C(1), C(0)};
         QPrefetch<S, CM, KQ> qpre;
         WPrefetch<KJ, G> wpre;
         qpre.load(arena + (int64_t)(n - 1) * SLOT, gl, L.rdim[n - 1], L.rdim[n]);
@@ -504,8 +524,8 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
                   cx<S> acc = czero<S>();
 #pragma unroll
                   for (int b = 0; b < KQ; ++b)
-                    if (b < rn) acc = cfma(acc, qrow[b], down<S>(L.Y[b][jj]));
-                  L.X[gl][s * chn + jj] = up(acc);
+                    if (b < rn) acc = cfma(acc, qrow[b], cvt<S>(L.Y[b][jj]));
+                  L.X[gl][s * chn + jj] = cvt<C>(acc);
                 }
             }
           }
@@ -514,9 +534,9 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
             if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
           }
           lds_sync();
-          cd mh[KJ], u[KJ];
+          T mh[KJ], u[KJ];
 #pragma unroll
-          for (int a = 0; a < KJ; ++a) mh[a] = (gl < c && a < ri) ? conj(L.X[a][gl]) : cd{0.0, 0.0};
+          for (int a = 0; a < KJ; ++a) mh[a] = (gl < c && a < ri) ? conj(L.X[a][gl]) : czero<C>();
           const int ncj = (ri + 1) & ~1;
           // warm start: the unitary from this (reflection, site) in the previous iteration
           WarmRec* wrec = warm ? warm + ((int64_t)j * n + i) : nullptr;
@@ -529,7 +549,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
             for (int t = 0; t < WPrefetch<KJ, G>::NE; ++t) {
               const int e = gl + t * G;
               const int ra = e / KJ, ca = e % KJ;
-              if (e < KJ * KJ && ra < ncj && ca < ncj) L.U[ra][ca] = wcur.v[t];
+              if (e < KJ * KJ && ra < ncj && ca < ncj) L.U[ra][ca] = cvt<C>(wcur.v[t]);
             }
           }
           lds_sync();
@@ -540,7 +560,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
 #pragma unroll
               for (int cc = 0; cc < KJ; ++cc)
                 if (cc < ncj) {
-                  cd g = {0.0, 0.0};
+                  T g = czero<C>();
 #pragma unroll
                   for (int a = 0; a < KJ; ++a)
                     if (a < ncj) g = g + cmulc(L.U[a][gl], L.U[a][cc]);
@@ -550,15 +570,15 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
           }
           lds_sync();
           if (renorm_warm) {
-            cd un[KJ];
+            T un[KJ];
             if (gl < ncj) {
 #pragma unroll
               for (int cc = 0; cc < KJ; ++cc) {
-                cd acc = {0.0, 0.0};
+                T acc = czero<C>();
 #pragma unroll
                 for (int b = 0; b < KJ; ++b)
                   if (b < ncj && cc < ncj) acc = cfma(acc, L.U[gl][b], L.UG[b][cc]);
-                un[cc] = cc < ncj ? 1.5 * L.U[gl][cc] - 0.5 * acc : cd{0.0, 0.0};
+                un[cc] = cc < ncj ? C(1.5) * L.U[gl][cc] - C(0.5) * acc : czero<C>();
               }
             }
             lds_sync();
@@ -572,10 +592,10 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
           }
           lds_sync();
           if (use_warm) {
-            cd t[KJ];
+            T t[KJ];
 #pragma unroll
             for (int b = 0; b < KJ; ++b) {
-              cd acc = {0.0, 0.0};
+              T acc = czero<C>();
 #pragma unroll
               for (int a = 0; a < KJ; ++a)
                 if (a < ncj && b < ncj) acc = cfma(acc, mh[a], L.U[a][b]);
@@ -584,26 +604,30 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
 #pragma unroll
             for (int b = 0; b < KJ; ++b) {
               mh[b] = t[b];
-              u[b] = (gl < ncj && b < ncj) ? L.U[gl][b] : cd{(gl == b && b < ncj) ? 1.0 : 0.0, 0.0};
+              u[b] = (gl < ncj && b < ncj) ? L.U[gl][b] : T{(gl == b && b < ncj) ? C(1) : C(0), C(0)};
             }
           } else {
 #pragma unroll
-            for (int b = 0; b < KJ; ++b) u[b] = {(gl == b && b < ncj) ? 1.0 : 0.0, 0.0};
+            for (int b = 0; b < KJ; ++b) u[b] = {(gl == b && b < ncj) ? C(1) : C(0), C(0)};
           }
           int sweeps = 0;
-          if (gl < WS) sweeps = jacobi_svd<WS, KJ>(mh, u, gl, ncj, kJacobiTol2, P.skip_tol * P.skip_tol, P.max_sweeps);
+          if (gl < WS)
+            sweeps = jacobi_svd<C, WS, KJ>(mh, u, gl, ncj, (C)kJacobiTol2, (C)(P.skip_tol * P.skip_tol), P.max_sweeps);
           else {
 #pragma unroll
-            for (int a = 0; a < KJ; ++a) u[a] = {0.0, 0.0};
+            for (int a = 0; a < KJ; ++a) u[a] = czero<C>();
           }
           sweeps = (int)gsum<G>(gl == 0 ? (double)sweeps : 0.0);
-          f64 += (double)sweeps * ri * (ri - 1) / 2.0 * 56.0 * c;
-          double sg[KJ];
-          double smax = 0.0, stot = 0.0;
+          {
+            const double fl = (double)sweeps * ri * (ri - 1) / 2.0 * 56.0 * c;
+            if (kF32) f32 += fl; else f64 += fl;
+          }
+          C sg[KJ];
+          C smax = 0, stot = 0;
           // every column below ncj can carry weight (a warm start mixes the pad column in)
 #pragma unroll
           for (int col = 0; col < KJ; ++col) {
-            sg[col] = col < ncj ? gsum<G>(gl < c ? norm2(mh[col]) : 0.0) : 0.0;
+            sg[col] = col < ncj ? gsum<G>(gl < c ? norm2(mh[col]) : C(0)) : C(0);
             smax = fmax(smax, sg[col]);
             stot += sg[col];
           }
@@ -615,7 +639,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
           // keep the chi_new largest columns; kept columns stay in their index order (so the
           // bond basis, and the next warm start, does not jump when Schmidt values are
           // degenerate), dropped ones follow
-          double dropped = 0.0;
+          C dropped = 0;
           int rank[KJ];
           bool keep[KJ];
 #pragma unroll
@@ -635,7 +659,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
               nd += keep[col] ? 0 : 1;
             }
           }
-          if (stot > 0.0) truncw = fmax(truncw, dropped / stot);
+          if (stot > 0) truncw = fmax(truncw, (double)(dropped / stot));
           if (!isfinite(stot)) status |= GMPS_ST_NAN;
           if (wrec && real) {
             // keep J with its columns in singular-value order for the next iteration
@@ -655,8 +679,8 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
           for (int col = 0; col < KJ; ++col) {
             if (rank[col] < chi_new) {
               const int rk = rank[col];
-              const double sig2 = sg[col];
-              const double rs = rsqrt_acc(sig2);  // 1/sigma
+              const C sig2 = sg[col];
+              const C rs = rsqrt_acc(sig2);  // 1/sigma
               if (real && gl < c) {
                 const int s = gl >= chn ? 1 : 0;
                 const int jp = gl - s * chn;
@@ -679,15 +703,15 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
           if (act) {
 #pragma unroll
             for (int b = 0; b < KQ; ++b)
-              if (b < rn) acc = cfma(acc, slot[s * D + b], down<S>(L.Y[b][jj]));
+              if (b < rn) acc = cfma(acc, slot[s * D + b], cvt<S>(L.Y[b][jj]));
           }
           const double macs = 2.0 * rn * chn;
           if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
-          const double nn = gsum<G>(act ? norm2(up(acc)) : 0.0);
-          if (!isfinite(nn) || !(nn > 0.0)) status |= GMPS_ST_NAN;
-          const double nr = sqrt(nn);
-          if (diff) drift = fmax(drift, fabs(nr - 1.0));
-          const cx<S> out = store_cast<S>((diff ? 1.0 / nr : 1.0) * up(acc), rs_state, sr);
+          const C nn = gsum<G>(act ? norm2(cvt<C>(acc)) : C(0));
+          if (!isfinite(nn) || !(nn > 0)) status |= GMPS_ST_NAN;
+          const C nr = sqrt(nn);
+          if (diff) drift = fmax(drift, fabs((double)nr - 1.0));
+          const cx<S> out = store_cast<S>((diff ? C(1) / nr : C(1)) * cvt<C>(acc), rs_state, sr);
           lds_sync();
           if (real && act) slot[s * D + jj] = out;
           if (gl == 0) L.bond[0] = 1;
@@ -714,7 +738,7 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
   lds_sync();
 }
 
-template <class S>
+template <class S, class C>
 __global__ __launch_bounds__(64) void grover_group_kernel(IterParams P) {
   extern __shared__ __align__(16) char lds[];
   for (;;) {
@@ -724,37 +748,50 @@ __global__ __launch_bounds__(64) void grover_group_kernel(IterParams P) {
     if ((int)bi >= P.queue->nbundles) break;
     const Bundle* bd = P.bundles + bi;
     switch (bd->cls) {
-      case 0: run_bundle<S, 2, 8, 4>(P, bd, lds); break;
-      case 1: run_bundle<S, 3, 8, 8>(P, bd, lds); break;
-      case 2: run_bundle<S, 4, 16, 8>(P, bd, lds); break;
-      case 3: run_bundle<S, 5, 16, 16>(P, bd, lds); break;
-      case 4: run_bundle<S, 6, 16, 16>(P, bd, lds); break;
+      case 0: run_bundle<S, C, 2, 8, 4>(P, bd, lds); break;
+      case 1: run_bundle<S, C, 3, 8, 8>(P, bd, lds); break;
+      case 2: run_bundle<S, C, 4, 16, 8>(P, bd, lds); break;
+      case 3: run_bundle<S, C, 5, 16, 16>(P, bd, lds); break;
+      case 4: run_bundle<S, C, 6, 16, 16>(P, bd, lds); break;
       default: break;
     }
   }
 }
 
 // ------------------------------------------------------------------------- launch wrappers
-hipError_t launch_group(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st) {
-  if (mixed)
-    grover_group_kernel<float><<<grid, 64, lds, st>>>(P);
+// mode: 0 FP64, 1 mixed (complex64 storage, FP64 factorisations), 2 all-FP32
+hipError_t launch_group(int mode, const IterParams& P, int grid, size_t lds, hipStream_t st) {
+  if (mode == 2)
+    grover_group_kernel<float, float><<<grid, 64, lds, st>>>(P);
+  else if (mode == 1)
+    grover_group_kernel<float, double><<<grid, 64, lds, st>>>(P);
   else
-    grover_group_kernel<double><<<grid, 64, lds, st>>>(P);
+    grover_group_kernel<double, double><<<grid, 64, lds, st>>>(P);
   return hipGetLastError();
 }
 
-hipError_t group_occupancy(bool mixed, size_t lds, int* blocks_per_cu) {
-  return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_group_kernel<float>, 64, lds)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_group_kernel<double>, 64, lds);
+hipError_t group_occupancy(int mode, size_t lds, int* blocks_per_cu) {
+  if (mode == 2)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_group_kernel<float, float>, 64, lds);
+  if (mode == 1)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_group_kernel<float, double>, 64, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_group_kernel<double, double>, 64, lds);
 }
 
-size_t group_lds_bytes(bool mixed, int cls) {
+template <int CM>
+size_t group_lds_cls(int mode) {
+  if (mode == 2) return sizeof(GroupLds<float, float, CM>);
+  if (mode == 1) return sizeof(GroupLds<float, double, CM>);
+  return sizeof(GroupLds<double, double, CM>);
+}
+
+size_t group_lds_bytes(int mode, int cls) {
   switch (cls) {
-    case 0: return mixed ? sizeof(GroupLds<float, 2>) : sizeof(GroupLds<double, 2>);
-    case 1: return mixed ? sizeof(GroupLds<float, 3>) : sizeof(GroupLds<double, 3>);
-    case 2: return mixed ? sizeof(GroupLds<float, 4>) : sizeof(GroupLds<double, 4>);
-    case 3: return mixed ? sizeof(GroupLds<float, 5>) : sizeof(GroupLds<double, 5>);
-    case 4: return mixed ? sizeof(GroupLds<float, 6>) : sizeof(GroupLds<double, 6>);
+    case 0: return group_lds_cls<2>(mode);
+    case 1: return group_lds_cls<3>(mode);
+    case 2: return group_lds_cls<4>(mode);
+    case 3: return group_lds_cls<5>(mode);
+    case 4: return group_lds_cls<6>(mode);
   }
   return 0;
 }

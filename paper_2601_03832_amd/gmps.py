@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgmps.so")
 
 GMPS_FP64 = 0
 GMPS_MIXED = 1
+GMPS_FP32 = 2
 GMPS_OK = 0
 GMPS_E_ARG = -1
 GMPS_E_WORKSPACE = -2
@@ -144,7 +145,9 @@ def _prec(precision: str) -> int:
         return GMPS_FP64
     if precision in ("mixed", GMPS_MIXED):
         return GMPS_MIXED
-    raise ValueError("precision must be 'fp64' or 'mixed'")
+    if precision in ("fp32", GMPS_FP32):
+        return GMPS_FP32
+    raise ValueError("precision must be 'fp64', 'mixed' or 'fp32'")
 
 
 class Batch:

@@ -167,3 +167,30 @@ def test_struct_layouts_match_the_binding(tmp_path):
     offs = vals[2:]
     got = [getattr(gmps.GmpsOptions, f).offset for f in opt_fields] + [getattr(gmps.GmpsInstance, f).offset for f in inst_fields]
     assert offs == got
+
+
+def test_precision_codes_match_the_header():
+    text = open(HEADER).read()
+    codes = dict((k, int(v)) for k, v in re.findall(r"\b(GMPS_(?:FP64|MIXED|FP32))\s*=\s*(\d+)", text))
+    assert codes == {"GMPS_FP64": gmps.GMPS_FP64, "GMPS_MIXED": gmps.GMPS_MIXED, "GMPS_FP32": gmps.GMPS_FP32}
+
+
+def test_fp32_workspace_and_rejections_before_touching_a_device(lib):
+    """GMPS_FP32 stores complex64 sites like the mixed path; it runs on the lane-group kernel
+    only, so the team kernel and bond caps above that kernel's classes are refused."""
+    c1 = inputs.config_c1().instances
+    arr, _ = gmps.pack_instances(c1)
+    assert lib.gmps_workspace_bytes(arr, 1, gmps.GMPS_FP32) == lib.gmps_workspace_bytes(arr, 1, gmps.GMPS_MIXED) > 0
+    assert lib.gsv_workspace_bytes(10, 1, gmps.GMPS_FP32) == 0
+    wide = (gmps.GmpsInstance * 1)()
+    wide[0].n, wide[0].M, wide[0].chi_cap = 14, 8, 9    # effective cap 9 > 6
+    assert _create(lib, wide, np.arange(8, dtype=np.uint64), prec=gmps.GMPS_FP32) == gmps.GMPS_E_UNSUPPORTED
+    narrow = (gmps.GmpsInstance * 1)()
+    narrow[0].n, narrow[0].M, narrow[0].chi_cap = 10, 1, 2
+    opt = gmps.GmpsOptions()
+    opt.kernel = gmps.KERNELS["team"]
+    h = ctypes.c_void_p()
+    m = np.array([3], dtype=np.uint64)
+    rc = lib.gmps_create(ctypes.byref(h), narrow, 1, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                         gmps.GMPS_FP32, ctypes.byref(opt), ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == gmps.GMPS_E_UNSUPPORTED
