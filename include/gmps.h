@@ -54,7 +54,8 @@ enum {
   GMPS_E_ARG = -1,         /* invalid argument; nothing was enqueued               */
   GMPS_E_WORKSPACE = -2,   /* workspace NULL, misaligned (<256 B) or too small      */
   GMPS_E_HIP = -3,         /* a HIP runtime call failed                             */
-  GMPS_E_UNSUPPORTED = -4, /* effective bond cap above 32, or no device            */
+  GMPS_E_UNSUPPORTED = -4, /* no tile class holds the bond cap, an option the chosen *
+                            * kernel or precision lacks, or no device               */
   GMPS_E_NUMERIC = -5      /* some instance reports NaN/Inf or norm drift (see      *
                             * gmps_diagnostics); results were still written         */
 };
@@ -94,7 +95,7 @@ typedef struct {
   int32_t jacobi_warm;  /* 1: each Jacobi SVD starts from the unitary it produced at the
                            same (reflection, site) one iteration earlier, which keeps the
                            bond bases continuous across iterations; -1: start from the
-                           identity; 0: default: off for GMPS_FP64, on for GMPS_MIXED (it
+                           identity; 0: default: off for GMPS_FP64 and GMPS_FP32, on for GMPS_MIXED (it
                            removes a systematic drift at M = 1 and keeps single marked
                            amplitudes together), except with precontract, where it is on
                            for bond caps of 2 only: there the bond basis of a (reflection,
@@ -104,7 +105,7 @@ typedef struct {
                            instances per wave; bond caps up to 6, larger caps go to the team
                            kernel), 2 = team kernel (a tile column per lane slot, one instance per
                            team of 16-256 threads; bond caps up to 32), 0 = library choice
-                           (the team kernel) */
+                           (the team kernel; the lane-group kernel for GMPS_FP32) */
   int32_t precontract;  /* 1: projector pre-contraction, a recompression variant of Section III-B
                            (team kernel only; with kernel = 1: GMPS_E_UNSUPPORTED; instances
                            whose effective bond cap exceeds 17 keep the bond-2 MPOs). A reflection
@@ -141,8 +142,9 @@ size_t gmps_workspace_bytes(const gmps_instance* inst, int32_t B, gmps_prec prec
  * least gmps_workspace_bytes() bytes, 256-byte aligned. hip_stream: hipStream_t or NULL.
  * The chain is left uninitialised: call mps_init_uniform() next.
  * Errors: GMPS_E_ARG (bad instance, duplicate or out-of-range marked index, unknown
- * kernel), GMPS_E_WORKSPACE, GMPS_E_UNSUPPORTED (no tile class holds the bond cap),
- * GMPS_E_HIP. */
+ * kernel or precision), GMPS_E_WORKSPACE, GMPS_E_UNSUPPORTED (no tile class holds the bond
+ * cap; precontract without the team kernel; GMPS_FP32 with kernel = 2 or an effective bond
+ * cap above 6), GMPS_E_HIP. */
 int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const uint64_t* marked,
                 gmps_prec prec, const gmps_options* opt, void* dev_workspace, size_t ws_bytes,
                 void* hip_stream);
