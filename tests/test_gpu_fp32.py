@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 from oracle import closed_form as cf
+from oracle import sampling as osamp
 from oracle import statevector as sv
 from paper_2601_03832_amd import gmps, inputs
 
@@ -128,3 +129,25 @@ def test_fp32_full_k_within_bound(gpu):
     for i, x in enumerate(insts):
         assert errs["fp32"][i] < 2 * amp_bound(x.n, 1, x.k)
         assert errs["mixed"][i] < 1e-6
+
+
+def test_fp32_sampling_matches_oracle(gpu):
+    """Perfect sampling from FP32 states replays the oracle's exact site-by-site draw with the
+    same Philox uniforms; a shot may differ only where its uniform lies within the marginal's
+    error (twice the amplitude bound) of the decision threshold."""
+    say("case: fp32 sampling replay, 12 instances x 64 shots")
+    insts = inputs.random_batch(12, 5, 12, (1, 2, 4), seed=99)
+    b = run(insts)
+    bits, hits = b.sample(64, 4242)
+    nbad = 0
+    for i, inst in enumerate(insts):
+        tie = 2 * amp_bound(inst.n, inst.M, inst.k)
+        exp, p0s, us = osamp.sample(inst.n, inst.marked, inst.k, 64, 4242, i)
+        for sh in np.nonzero(bits[i] != exp)[0]:
+            x, y = int(bits[i][sh]), int(exp[sh])
+            first = next(t for t in range(inst.n) if ((x ^ y) >> (inst.n - 1 - t)) & 1)
+            assert abs(us[sh, first] - p0s[sh, first]) < tie, (i, sh, first)
+            nbad += 1
+        assert hits[i] == sum(1 for x in bits[i] if int(x) in set(int(v) for v in inst.marked))
+    say("  %d of %d shots differ at near-ties" % (nbad, 64 * len(insts)))
+    b.close()
