@@ -27,7 +27,9 @@
  *  - Precision: GMPS_FP64 keeps site tensors and all arithmetic in complex128.
  *    GMPS_MIXED stores site tensors in complex64 and runs the MPO application and the
  *    site contractions in complex64, while QR, SVD, norms and renormalisation run in
- *    FP64 on up-converted tiles.
+ *    FP64 on up-converted tiles. It resolves Schmidt components down to its rounding
+ *    floor, about 1e-7 of the largest: in the first iterations at n above about 40 the
+ *    marked component lies below it (amplitude ~2^(-n/2)), so such runs need GMPS_FP64.
  *    GMPS_FP32 (the all-single-precision simulation whose accuracy Section IV / Fig. 3
  *    examines) runs everything in complex64 / FP32, factorisations included, with results
  *    rounded to nearest; it exists on the lane-group kernel only (gmps_options.kernel 0 or

@@ -164,6 +164,41 @@ def test_c2_with_sampling(gpu, kernel):
     assert hits[0] >= 4090
 
 
+def test_maximum_n(gpu, kernel):
+    """n = 62 and 63 (the largest the ABI takes), marked indices with their top bits set: bit
+    extraction, the bond profile and read-outs at 64-bit indices, FP64. After k <= 3
+    iterations the amplitudes are ~1e-9 and P ~1e-18, while the chain carries absolute
+    rounding errors near 1e-16, so the bar is relative, 1e-3: a wrong bit gives an O(1)
+    relative error. (The mixed path cannot resolve such states: their marked component's
+    Schmidt weight, ~1e-9 of the largest, lies below complex64 rounding of the bulk.)"""
+    say("case: n=62/63, high marked bits, fp64 %s" % kernel)
+    insts = [inputs.Instance(63, np.array([2 ** 62 + 12345], np.uint64), 2, 2),
+             inputs.Instance(63, np.array([2 ** 63 - 1, 5], np.uint64), 1, 3),
+             inputs.Instance(62, np.array([2 ** 61 + 7, 2 ** 60, 3], np.uint64), 3, 4)]
+    rel = 1e-3
+    b = run(insts, "fp64", kernel=kernel)
+    p = b.marked_prob()
+    d = b.diagnostics()
+    rng = np.random.default_rng(5)
+    for i, inst in enumerate(insts):
+        exp = cf.p_marked(inst.n, inst.M, inst.k)
+        assert abs(p[i] - exp) <= rel * exp, (i, p[i], exp)
+        am, au = cf.amplitudes_wr(inst.n, inst.M, inst.k)
+        a = b.amplitudes(i, inst.marked)
+        assert np.all(np.abs(a - am) <= rel * abs(am)), (i, a, am)
+        others = (rng.integers(0, 2 ** 62, 6, dtype=np.uint64) << np.uint64(inst.n - 62)) | np.uint64(1)
+        others = np.array([x for x in others if int(x) not in set(int(v) for v in inst.marked)], np.uint64)
+        a = b.amplitudes(i, others)
+        assert np.all(np.abs(a - au) <= rel * abs(au)), (i, a, au)
+        ref = omps.run(inst.n, inst.marked, inst.k, inst.chi_cap)
+        assert d["bond_dims"][i] == ref.bond_dims(), (i, d["bond_dims"][i], ref.bond_dims())
+    assert d["status"].tolist() == [0, 0, 0]
+    bits, hits = b.sample(16, 77)
+    for i, inst in enumerate(insts):
+        check_sampling(bits[i], inst.n, inst.marked, inst.k, 16, 77, i, 1e-9)
+    b.close()
+
+
 def test_sampling_many_instances_matches_oracle(gpu, kernel):
     say("case: sampling replay, 12 instances x 64 shots, fp64 and mixed, %s" % kernel)
     insts = inputs.random_batch(12, 5, 12, (1, 2, 4), seed=99)
