@@ -276,6 +276,27 @@ def fp32_accuracy_leg():
     return out
 
 
+def fp32_c4_leg(w, ks, shots):
+    """The whole workload on the lane-group kernel (its tile classes hold every C4 bond cap)
+    in all-FP32, mixed and FP64: the same kernel code with FP32 or FP64 factorisations, one
+    step each after an untimed one."""
+    from paper_2601_03832_amd import gmps
+    out = {}
+    for prec in ("fp32", "mixed", "fp64"):
+        b = gmps.Batch(w.instances, prec, kernel="group")
+        run_step(b, ks, shots, w.shot_seed)
+        t0 = time.perf_counter()
+        p, _ = run_step(b, ks, shots, w.shot_seed)
+        t1 = time.perf_counter()
+        errs = np.array([abs(p[i] - exact_p(x.n, x.M, x.k)) for i, x in enumerate(w.instances)])
+        out[prec] = {"value": sum(ks) / (t1 - t0), "unit": "iterations/s", "ms_per_step": (t1 - t0) * 1e3,
+                     "kernel_ms": b.last_iterate_ms(), "max_abs_err_p": float(errs.max())}
+        b.close()
+        print("bench: lane-group %s step %.1f s" % (prec, t1 - t0), file=sys.stderr, flush=True)
+    out["note"] = "same workload and step on the lane-group kernel (gmps_options.kernel = 1)"
+    return out
+
+
 def traffic_record():
     try:
         with open(TRAFFIC_FILE) as f:
@@ -303,6 +324,8 @@ def main():
     ap.add_argument("--no-precontract", action="store_true", help="skip the pre-contracted reflections legs")
     ap.add_argument("--no-sequential", action="store_true", help="skip the sequential-sweeps leg")
     ap.add_argument("--no-fp32", action="store_true", help="skip the all-FP32 accuracy leg")
+    ap.add_argument("--fp32-c4", action="store_true",
+                    help="also time the whole workload on the lane-group kernel in FP32, mixed and FP64")
     ap.add_argument("--kernel", default="auto", choices=sorted(["auto", "group", "team"]),
                     help="iterate kernel: lane-group, team, or the library's choice")
     args = ap.parse_args()
@@ -427,6 +450,9 @@ def main():
     if not args.no_fp32 and args.workload == "c4":
         line["fp32_accuracy"] = fp32_accuracy_leg()
         print("bench: fp32 accuracy leg done", file=sys.stderr, flush=True)
+    if args.fp32_c4 and args.workload == "c4":
+        line["fp32_c4_lane_group"] = fp32_c4_leg(w, ks, shots)
+        print("bench: lane-group fp32/mixed/fp64 leg done", file=sys.stderr, flush=True)
     if not args.no_plain:
         line["plain_fp64"] = plain_fp64_rate(w, args.plain_budget)
         line["plain_fp64"]["speedup_of_batched_mixed"] = line["value"] / line["plain_fp64"]["value"]

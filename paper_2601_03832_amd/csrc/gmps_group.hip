@@ -38,6 +38,20 @@ namespace gmps {
 // A block has full rank and is eliminated in its own order; the projector block adds one
 // direction (rank chi + 1 in all), which need not lie in the block's first column, so from
 // step npiv on the remaining column with the largest residual norm is pivoted in first.
+// Below `zero` a squared norm counts as zero. In FP32 the squares of entries near 1e-20 are
+// denormals, which v_rsq_f32 / v_rcp_f32 flush to zero (an infinite estimate, and NaN after
+// the Newton step), so the FP32 instantiation treats squared norms below 1e-30 as zero.
+template <class C>
+struct QrLimits;
+template <>
+struct QrLimits<double> {
+  static constexpr double zero = 0.0;
+};
+template <>
+struct QrLimits<float> {
+  static constexpr float zero = 1e-30f;
+};
+
 template <class C, int G, int NC, int KMAX>
 __device__ __forceinline__ int householder_qr_rank(cx<C> (&x)[NC], cx<C> (&q)[KMAX], int (&perm)[NC], int gl, int m,
                                                    int c, int npiv, C rank2, double* dropped) {
@@ -98,12 +112,13 @@ __device__ __forceinline__ int householder_qr_rank(cx<C> (&x)[NC], cx<C> (&q)[KM
       const C sub = gsum<G>((gl > j && gl < m) ? norm2(xj) : C(0));
       const T alpha = gbcast<G>(xj, gl, j);
       const C a2 = norm2(alpha);
-      const bool refl = sub > 0;
-      const C ra = a2 > 0 ? rsqrt_acc(a2) : C(0);
+      const bool refl = sub > QrLimits<C>::zero;
+      const bool anz = a2 > QrLimits<C>::zero;
+      const C ra = anz ? rsqrt_acc(a2) : C(0);
       const C aa = a2 * ra;                               // |alpha|
       const C n2 = a2 + sub;
       const C nrm = refl ? n2 * rsqrt_acc(n2) : aa;       // norm of column j from the diagonal down
-      const T ph = a2 > 0 ? T{alpha.re * ra, alpha.im * ra} : T{C(1), C(0)};
+      const T ph = anz ? T{alpha.re * ra, alpha.im * ra} : T{C(1), C(0)};
       const T beta = {-ph.re * nrm, -ph.im * nrm};
       const C t = refl ? rcp_acc(nrm * (nrm + aa)) : C(0);
       T v = (gl == j) ? alpha - beta : ((gl > j && gl < m) ? xj : czero<C>());
@@ -633,7 +648,8 @@ __device__ void run_bundle(const IterParams& P, const Bundle* bdp, char* lds_bas
           }
           int above = 0;
 #pragma unroll
-          for (int col = 0; col < KJ; ++col) above += (col < ncj && sg[col] > 0.0 && sg[col] >= tol2 * smax) ? 1 : 0;
+          for (int col = 0; col < KJ; ++col)
+            above += (col < ncj && sg[col] > QrLimits<C>::zero && sg[col] >= tol2 * smax) ? 1 : 0;
           int chi_new = above < cap ? above : cap;
           if (chi_new < 1) chi_new = 1;
           // keep the chi_new largest columns; kept columns stay in their index order (so the

@@ -151,3 +151,21 @@ def test_fp32_sampling_matches_oracle(gpu):
         assert hits[i] == sum(1 for x in bits[i] if int(x) in set(int(v) for v in inst.marked))
     say("  %d of %d shots differ at near-ties" % (nbad, 64 * len(insts)))
     b.close()
+
+
+def test_fp32_no_underflow_in_the_qr(gpu):
+    """Regression: in FP32 the squared norm of a QR column entry near 1e-20 is a denormal, which
+    v_rsq_f32 flushes (an infinite estimate, NaN after the Newton step); it hit M = 2 instances
+    of the 4096-instance workload with n >= 25 in their first iteration. The QR treats squared
+    norms below 1e-30 as zero on the FP32 path."""
+    say("case: fp32, every M=2, n>=25 instance of the 4096-instance workload, 2 iterations")
+    insts = [inputs.Instance(i.n, i.marked, 2, i.chi_cap) for i in inputs.config_c4().instances
+             if i.M == 2 and i.n >= 25]
+    b = run(insts)
+    p = b.marked_prob()
+    d = b.diagnostics()
+    assert np.all(np.isfinite(p)) and not np.any(d["status"] & gmps.ST_NAN)
+    for i, inst in enumerate(insts):
+        assert abs(p[i] - cf.p_marked(inst.n, 2, 2)) < 2 * amp_bound(inst.n, 2, 2), (i, inst.n)
+    say("  %d instances finite" % len(insts))
+    b.close()
