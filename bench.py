@@ -6,7 +6,14 @@ launch), read out (marked_prob) and sampled (sample_shots). value = sum_i k_i / 
 The accuracy gate requires |P_i - sin^2((2k_i+1) theta_i)| <= 1e-6 for every instance.
 
     python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--workload c4|c2|c3] [--kernel auto|team|group]
-                    [--c5-k 48] [--no-plain] [--no-cpu] [--no-fp64-batch]
+                    [--c5-k 48] [--sv-k 500] [--no-plain] [--no-cpu] [--no-fp64-batch]
+                    [--no-sequential] [--no-precontract] [--no-fp32] [--fp32-c4]
+
+Besides the headline line, the default run adds legs on the same hardware: the workload
+through the FP64 path, with sequential sweeps and with pre-contracted reflections; a prefix of
+the n=40, M=16 workload; the dense statevector backend; the all-FP32 precision study (M=1,
+n=12..28); B=1 FP64 handles; and the CPU oracle. --fp32-c4 also times the whole workload on
+the lane-group kernel in FP32, mixed and FP64.
 
 Prints one JSON line. roofline: the iterate kernel's algorithmic flops per launch (FP32
 flops weighted by the FP64/FP32 peak ratio) over its HIP-event duration, against the FP64
