@@ -278,8 +278,20 @@ def fp32_accuracy_leg():
         out["amp_err_" + prec] = amp_err
         out["launch_ms_" + prec] = ms
         out["status_" + prec] = st
+    # the paper sets the FP32 statevector beside the FP32 MPS: the FP32 vector (FP64 sums)
+    sv_p = []
+    for i in insts:
+        if i.n < 24:
+            continue
+        s = gmps.StateVector(i.n, i.marked, "mixed")
+        s.init_uniform()
+        s.iterate(i.k)
+        sv_p.append([i.n, float(s.marked_prob())])
+        s.close()
+    out["sv_fp32_vector"] = sv_p
     out["note"] = ("fp32: site tensors, contractions, QR, Jacobi SVD and norms in FP32, rounded to nearest; "
-                   "mixed: complex64 sites, FP64 factorisations, stochastic rounding")
+                   "mixed: complex64 sites, FP64 factorisations, stochastic rounding; sv_fp32_vector: [n, P] "
+                   "of the dense statevector with an FP32 vector and FP64 sums")
     return out
 
 
