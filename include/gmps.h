@@ -25,11 +25,22 @@
  *    that stream first.
  *  - Threads: a handle is not thread-safe; distinct handles are independent.
  *  - Precision: GMPS_FP64 keeps site tensors and all arithmetic in complex128.
- *    GMPS_MIXED stores site tensors in complex64 and runs the MPO application and the
- *    site contractions in complex64, while QR, SVD, norms and renormalisation run in
- *    FP64 on up-converted tiles. It resolves Schmidt components down to its rounding
- *    floor, about 1e-7 of the largest: in the first iterations at n above about 40 the
- *    marked component lies below it (amplitude ~2^(-n/2)), so such runs need GMPS_FP64.
+ *    GMPS_MIXED on the team kernel (the default) runs every arithmetic step in FP64 and
+ *    stores the bulk of the chain in complex64. The rounding error of a stored isometry is
+ *    split in two: the part inside the span of the stored vectors is folded into the FP64
+ *    carry that moves on along the sweep (compensated rounding), and the rest is orthogonal
+ *    to every state whose support at that bond lies in that span, as the Grover states'
+ *    supports do. The sites within ceil(log2(M+1)) of either end, where a bond can be
+ *    smaller than that support, and the norm-carrying end site are kept in complex128 in
+ *    edge slots of the workspace. On the lane-group kernel GMPS_MIXED instead runs the MPO
+ *    application and the site contractions in complex64 and the factorisations in FP64 on
+ *    up-converted tiles. Either way Schmidt components below trunc_tol (5e-7) of the
+ *    largest are dropped: in the first iterations at n above about 40 the marked component
+ *    lies near that floor (amplitude ~2^(-n/2)), so such runs need GMPS_FP64. Near the
+ *    peak of P, in the one iteration where the unmarked component passes through a few
+ *    1e-6, the mixed path's rotation angle (2k+1) theta can shift by up to about 2e-6 rad;
+ *    P, flat there, moves by ~1e-12, but the shift stays with the state if it is iterated
+ *    on past the peak.
  *    GMPS_FP32 (the all-single-precision simulation whose accuracy Section IV / Fig. 3
  *    examines) runs everything in complex64 / FP32, factorisations included, with results
  *    rounded to nearest; it exists on the lane-group kernel only (gmps_options.kernel 0 or
@@ -90,19 +101,17 @@ typedef struct {
   int32_t waves_per_cu; /* persistent-grid occupancy; <= 0: library plan              */
   int32_t use_graph;    /* 1 (default when 0): replay grover_iterate from a hipGraph;
                            -1: plain launches                                         */
-  int32_t round_mode;   /* GMPS_MIXED only. 0 or 1 (default): every FP64 result stored as
-                           complex64 is rounded stochastically (unbiased), so rounding
-                           errors of successive iterations do not add up coherently;
-                           -1: round to nearest                                         */
+  int32_t round_mode;   /* GMPS_MIXED only: how an FP64 result stored as complex64 is rounded.
+                           0 (default): to nearest on the team kernel, stochastically on the
+                           lane-group kernel; 1: stochastically (unbiased, so the rounding
+                           errors of successive iterations do not add up coherently);
+                           -1: to nearest                                                */
   int32_t jacobi_warm;  /* 1: each Jacobi SVD starts from the unitary it produced at the
                            same (reflection, site) one iteration earlier, which keeps the
                            bond bases continuous across iterations; -1: start from the
-                           identity; 0: default: off for GMPS_FP64 and GMPS_FP32, on for GMPS_MIXED (it
-                           removes a systematic drift at M = 1 and keeps single marked
-                           amplitudes together), except with precontract, where it is on
-                           for bond caps of 2 only: there the bond basis of a (reflection,
-                           site) is not continuous across iterations at larger caps, and
-                           the warm start costs time and accuracy                         */
+                           identity; 0 (default): on for GMPS_MIXED on the lane-group kernel
+                           (complex64 contractions; it removes a systematic drift at M = 1
+                           there), off everywhere else. Ignored by the pipelined sweeps.    */
   int32_t kernel;       /* iterate kernel: 1 = lane-group kernel (a tile row per lane, up to 8
                            instances per wave; bond caps up to 6, larger caps go to the team
                            kernel), 2 = team kernel (a tile column per lane slot, one instance per
@@ -122,21 +131,21 @@ typedef struct {
                            marked index is one reflection with T = 1. Same result up to
                            rounding; 0 or -1 (default): one bond-2 MPO per projector, as in
                            the paper. */
-  int32_t pipeline;     /* 0 or 1 (default): the team classes with bond caps 3, 5 and 8 (and 2
-                           on GMPS_FP64; on GMPS_MIXED the bond-2 class keeps its warm-started
-                           sequential sweeps, which its M = 1 instances need) run the
-                           per-projector reflections with
-                           alternating sweep directions on two waves, the truncation sweep of
-                           each reflection and the canonicalisation sweep of the next in lock
-                           step one site apart (no warm starts); ignored with precontract, on
-                           the lane-group kernel, and in a batch where some bond cap is below
-                           the exact rank (a lossy truncation depends on the sweep order; such
-                           a batch keeps the sequential, right-to-left truncations). -1: one
-                           wave per instance, each reflection's two sweeps in turn */
+  int32_t pipeline;     /* 0 or 1 (default): the team classes with bond caps 2, 3, 5 and 8 run
+                           the per-projector reflections with alternating sweep directions on
+                           two waves, the truncation sweep of each reflection and the
+                           canonicalisation sweep of the next in lock step one site apart;
+                           ignored with precontract, on the lane-group kernel, and in a batch
+                           where some bond cap is below the exact rank (a lossy truncation
+                           depends on the sweep order; such a batch keeps the sequential,
+                           right-to-left truncations). -1: one wave per instance, each
+                           reflection's two sweeps in turn                                */
 } gmps_options;
 
 /* Bytes of device workspace gmps_create() needs for this batch with either iterate kernel
- * (0 on invalid input). inst: host [B]; marked offsets are not read. */
+ * (0 on invalid input): the site arena, the complex128 edge slots, per-instance tables, and
+ * a 16 MiB staging region that read-outs and sampling pass through in chunks, so no call
+ * after gmps_create() allocates device memory. inst: host [B]; marked offsets are not read. */
 size_t gmps_workspace_bytes(const gmps_instance* inst, int32_t B, gmps_prec prec);
 
 /* Creates a handle over B instances. inst: host [B]; marked: host, every instance's
@@ -173,10 +182,18 @@ int marked_prob(gmps_batch* b, double* out_p);
 int sample_shots(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_t seed,
                  uint64_t* out_bits, int64_t* out_hits);
 
-/* <x|psi_inst> for cnt basis indices. xs: host [cnt]; out_reim: host [2*cnt] (re, im).
- * Synchronises. */
+/* Eq. (5): amplitudes <x|psi_inst> / ||psi_inst|| of the normalised state for cnt basis
+ * indices (the stored chain's norm differs from 1 by the rounding of its tensors). xs: host
+ * [cnt]; out_reim: host [2*cnt] (re, im). Queries pass through the workspace's staging region in
+ * chunks. Synchronises. GMPS_E_NUMERIC if the norm is not finite and positive. */
 int gmps_amplitudes(gmps_batch* b, int32_t inst, const uint64_t* xs, int64_t cnt,
                     double* out_reim);
+
+/* <s|psi_inst> / ||psi_inst|| with |s> = |+>^n the uniform superposition (Eq. (2)). With the
+ * marked amplitudes it fixes the state's components along the two directions of Eq. (5), the
+ * normalised uniform superpositions over the marked and the unmarked indices, and so its
+ * rotation angle. out_reim: host [2]. Synchronises. */
+int gmps_overlap_uniform(gmps_batch* b, int32_t inst, double* out_reim);
 
 /* Per-instance diagnostics; any pointer may be NULL. Synchronises.
  *  norm_drift:   host [B], largest |norm - 1| seen before a renormalisation
@@ -193,7 +210,7 @@ int gmps_diagnostics(gmps_batch* b, double* norm_drift, double* trunc_weight, in
  * with HIP events recorded around that launch. Synchronises. */
 int gmps_last_iterate_ms(gmps_batch* b, double* ms);
 
-/* Frees the handle and its library-owned staging memory (not the workspace). NULL is OK. */
+/* Frees the handle (not the workspace). NULL is OK. */
 int gmps_destroy(gmps_batch* b);
 
 /* Static string for a GMPS_* status code. */

@@ -24,14 +24,17 @@ hipError_t launch_team(bool mixed, bool pc, bool pipe, int cls, const IterParams
 hipError_t team_occupancy(bool mixed, bool pc, bool pipe, int cls, size_t lds, int* blocks_per_cu);
 hipError_t launch_queue_reset(QueueState* q, hipStream_t st);
 hipError_t launch_init(bool mixed, InstDev* inst, int B, const int64_t* site_start, int32_t* bonds, void* arena,
-                       int64_t total_sites, char* warm, hipStream_t st);
+                       int64_t total_sites, char* warm, void* edge, hipStream_t st);
 hipError_t launch_prob(bool mixed, InstDev* inst, const uint64_t* marked, const int32_t* bonds, const void* arena,
-                       int B, double* out, hipStream_t st);
+                       const void* edge, int B, double* out, hipStream_t st);
+hipError_t launch_overlap_uniform(bool mixed, const InstDev* inst, int which, const int32_t* bonds,
+                                  const void* arena, const void* edge, double* out, hipStream_t st);
 hipError_t launch_amplitudes(bool mixed, int maxc, const InstDev* inst, int which, const int32_t* bonds,
-                             const void* arena, const uint64_t* xs, int64_t cnt, double* out, hipStream_t st);
+                             const void* arena, const void* edge, const uint64_t* xs, int64_t cnt, double* out,
+                             double* norm2, hipStream_t st);
 hipError_t launch_sample(bool mixed, int maxc, const InstDev* inst, const uint64_t* marked, const int32_t* bonds,
-                         const void* arena, int B, const int64_t* shot_off, int64_t total, uint64_t seed,
-                         uint64_t* bits, unsigned long long* hits, hipStream_t st);
+                         const void* arena, const void* edge, int B, int inst_base, const int64_t* shot_off,
+                         int64_t total, uint64_t seed, uint64_t* bits, unsigned long long* hits, hipStream_t st);
 }  // namespace gmps
 
 using namespace gmps;
@@ -40,6 +43,9 @@ namespace {
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+// Staging region of the read-out calls in the workspace: amplitude queries and sampled bitstrings
+// pass through it in chunks, so the library allocates no device memory after gmps_create.
+constexpr size_t kStageBytes = size_t(16) << 20;
 
 // Effective bond cap: the exact Schmidt rank of every intermediate state is at most M+1
 // (the state stays a combination of the uniform superposition and M marked basis states),
@@ -81,19 +87,22 @@ bool valid_instance(const gmps_instance& in) {
 }
 
 struct Layout {
-  size_t inst, marked, bonds, bundles, queue, prob, hits, site_start, warm, arena, total;
+  size_t inst, marked, bonds, bundles, queue, prob, hits, site_start, warm, edge, stage, arena, total;
   int64_t total_marked, total_sites;
 };
 
 bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, int path, Layout* L, std::vector<int>* cls_out,
-                    std::vector<int64_t>* site_off_out, std::vector<int64_t>* warm_off_out = nullptr) {
+                    std::vector<int64_t>* site_off_out, std::vector<int64_t>* warm_off_out = nullptr,
+                    std::vector<int64_t>* edge_off_out = nullptr) {
   const size_t elem = prec == GMPS_FP64 ? 16 : 8;
   int64_t tm = 0, ts = 0;
   size_t arena_elems = 0;
   if (cls_out) cls_out->resize(B);
   if (site_off_out) site_off_out->resize(B);
   if (warm_off_out) warm_off_out->resize(B);
+  if (edge_off_out) edge_off_out->resize(B);
   size_t warm_bytes = 0;
+  int64_t edge_cd = 0;
   for (int i = 0; i < B; ++i) {
     if (!valid_instance(inst[i])) return false;
     const int c = pick_class(inst[i].n, inst[i].M, inst[i].chi_cap, path);
@@ -103,6 +112,8 @@ bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, int path, 
     arena_elems += (size_t)inst[i].n * slot_elems(class_cm(c));
     if (warm_off_out) (*warm_off_out)[i] = (int64_t)warm_bytes;
     warm_bytes += (size_t)(inst[i].M + 1) * inst[i].n * warm_rec_bytes(c);
+    if (edge_off_out) (*edge_off_out)[i] = edge_cd;
+    edge_cd += (int64_t)edge_count(inst[i].n, edge_width(inst[i].M)) * slot_elems(class_cm(c));
     tm += inst[i].M;
     ts += inst[i].n;
   }
@@ -116,6 +127,8 @@ bool compute_layout(const gmps_instance* inst, int B, gmps_prec prec, int path, 
   L->hits = off;       off = align_up(off + sizeof(uint64_t) * B);
   L->site_start = off; off = align_up(off + sizeof(int64_t) * (B + 1));
   L->warm = off;       off = align_up(off + warm_bytes);
+  L->edge = off;       off = align_up(off + 16 * (size_t)edge_cd);
+  L->stage = off;      off = align_up(off + kStageBytes);
   L->arena = off;      off = align_up(off + elem * arena_elems);
   L->total = off;
   L->total_marked = tm;
@@ -140,7 +153,7 @@ struct gmps_batch {
   int max_sweeps = 16;
   int waves_per_cu = 0;
   bool use_graph = true;
-  bool stoch_round = true;
+  int round_mode = 0;  // 0: library default, 1: stochastic, -1: nearest
   int jacobi_warm = 0;  // 0: library default (mixed path only), 1 on, -1 off
   bool precontract = false;  // reflections as psi + product terms (team kernel only)
   bool pipeline = false;     // pipelined sweeps for the single-wave classes (team kernel default)
@@ -161,15 +174,17 @@ struct gmps_batch {
   hipStream_t side[kLaunchKinds] = {};
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kLaunchKinds] = {};
-  // lazily grown device staging for read-out calls
-  void* stage = nullptr;
-  size_t stage_bytes = 0;
 };
 
 namespace {
 
 // lane-group kernel instantiation: 0 FP64, 1 mixed, 2 all-FP32
 int group_mode(const gmps_batch* b) { return b->fp32 ? 2 : b->mixed ? 1 : 0; }
+
+// The team kernels keep the edge sites (the norm-carrying end site among them) in complex FP64 edge
+// slots, which the read-out kernels then use in place of their site slots; the lane-group kernel
+// does not maintain them.
+const void* readout_edge(const gmps_batch* b) { return b->path == kPathTeam ? b->params.edge : nullptr; }
 
 int hip_fail(hipError_t e, const char* what) {
   if (e != hipSuccess) {
@@ -184,20 +199,6 @@ int hip_fail(hipError_t e, const char* what) {
     int _rc = hip_fail((call), #call);                 \
     if (_rc != GMPS_OK) return _rc;                    \
   } while (0)
-
-int ensure_stage(gmps_batch* b, size_t bytes) {
-  if (bytes <= b->stage_bytes) return GMPS_OK;
-  if (b->stage) {
-    GMPS_HIP(hipStreamSynchronize(b->stream));
-    GMPS_HIP(hipFree(b->stage));
-    b->stage = nullptr;
-    b->stage_bytes = 0;
-  }
-  size_t sz = std::max<size_t>(bytes, 1 << 20);
-  GMPS_HIP(hipMalloc(&b->stage, sz));
-  b->stage_bytes = sz;
-  return GMPS_OK;
-}
 
 }  // namespace
 
@@ -240,12 +241,12 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   if (precontract && path != kPathTeam) return GMPS_E_UNSUPPORTED;
   Layout L;
   std::vector<int> cls;
-  std::vector<int64_t> site_off, warm_off;
+  std::vector<int64_t> site_off, warm_off, edge_off;
   for (int i = 0; i < B; ++i) {
     const int c = pick_class(inst[i].n, inst[i].M, inst[i].chi_cap, path);
     if (c < 0 || (fp32 && is_wide(c))) return GMPS_E_UNSUPPORTED;
   }
-  if (!compute_layout(inst, B, prec, path, &L, &cls, &site_off, &warm_off)) return GMPS_E_ARG;
+  if (!compute_layout(inst, B, prec, path, &L, &cls, &site_off, &warm_off, &edge_off)) return GMPS_E_ARG;
   // marked sets: in range and distinct within an instance
   int64_t tm = 0;
   for (int i = 0; i < B; ++i) tm = std::max<int64_t>(tm, inst[i].marked_off + inst[i].M);
@@ -283,7 +284,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     if (opt->max_sweeps > 0) b->max_sweeps = opt->max_sweeps;
     if (opt->waves_per_cu > 0) b->waves_per_cu = opt->waves_per_cu;
     if (opt->use_graph < 0) b->use_graph = false;
-    if (opt->round_mode < 0) b->stoch_round = false;
+    b->round_mode = opt->round_mode > 0 ? 1 : opt->round_mode < 0 ? -1 : 0;
     b->jacobi_warm = opt->jacobi_warm;
   }
   b->precontract = precontract;
@@ -319,6 +320,8 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     d.marked_off = moff;
     d.site_off = site_off[i];
     d.warm_off = warm_off[i];
+    d.edge_off = edge_off[i];
+    d.ew = edge_width(inst[i].M);
     moff += inst[i].M;
     site_start[i + 1] = site_start[i] + inst[i].n;
   }
@@ -366,9 +369,12 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   P.rank_tol = b->trunc_tol;
   P.max_sweeps = b->max_sweeps;
   // stochastic rounding applies to FP64 results stored as complex64 (none on the all-FP32 path)
-  P.stoch_round = (b->mixed && !b->fp32 && b->stoch_round) ? 1 : 0;
-  const bool warm_on = b->jacobi_warm > 0 || (b->jacobi_warm == 0 && b->mixed && !b->fp32);
+  // stochastic rounding of stored complex64 values: set per class kernel at launch
+  P.stoch_round = 0;
+  // warm starts by default only on the lane-group kernel's mixed path (complex64 arithmetic)
+  const bool warm_on = b->jacobi_warm > 0 || (b->jacobi_warm == 0 && b->mixed && !b->fp32 && path == kPathGroup);
   P.warm = warm_on ? reinterpret_cast<void*>(b->ws + L.warm) : nullptr;
+  P.edge = reinterpret_cast<void*>(b->ws + L.edge);
   *out = b;
   return GMPS_OK;
 }
@@ -376,7 +382,8 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
 int mps_init_uniform(gmps_batch* b) {
   if (!b) return GMPS_E_ARG;
   GMPS_HIP(launch_init(b->mixed, b->params.inst, b->B, reinterpret_cast<const int64_t*>(b->ws + b->lay.site_start),
-                       b->params.bonds, b->params.arena, b->lay.total_sites, b->ws + b->lay.warm, b->stream));
+                       b->params.bonds, b->params.arena, b->lay.total_sites, b->ws + b->lay.warm, b->params.edge,
+                       b->stream));
   std::fill(b->k_done_h.begin(), b->k_done_h.end(), 0);
   return GMPS_OK;
 }
@@ -507,11 +514,14 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
       IterParams P = b->params;
       P.bundles = dev_bundles + first[kd];
       P.queue = dev_queue + kd;
-      // library default for pre-contracted reflections: warm starts for the bond-2 class
-      // only (above it the bond basis of a (reflection, site) changes between iterations,
-      // the previous unitary does not shorten the Jacobi, and on the 4096-instance workload
-      // it raised the largest mixed-precision error of P from 7e-7 to 1.3e-6)
-      if (kd > 0 && b->precontract && b->jacobi_warm == 0 && kWide[kd - 1].CM > 2) P.warm = nullptr;
+      // The team kernels compute in FP64 and compensate their complex64 stores: they round to
+      // nearest unless stochastic rounding is asked for, and their Jacobi rotates every column
+      // above the FP64 floor. The lane-group kernel computes in the storage type on the mixed
+      // path: it rounds stochastically unless nearest is asked for, and leaves columns at the
+      // complex64 floor unrotated.
+      const bool comp = kd > 0;
+      P.stoch_round = (b->mixed && !b->fp32 && (comp ? b->round_mode == 1 : b->round_mode != -1)) ? 1 : 0;
+      if (comp) P.skip_tol = std::min(b->trunc_tol, 1e-15);
       e = kd == 0 ? launch_group(group_mode(b), P, grid[kd], lds[kd], ks)
                   : launch_team(b->mixed, b->precontract, b->pipeline, kWideBase + kd - 1, P, grid[kd], lds[kd], ks);
       if (e == hipSuccess && !on_main) {
@@ -579,8 +589,8 @@ static int any_bad_status(gmps_batch* b, bool* bad) {
 int marked_prob(gmps_batch* b, double* out_p) {
   if (!b || !out_p) return GMPS_E_ARG;
   double* dprob = reinterpret_cast<double*>(b->ws + b->lay.prob);
-  GMPS_HIP(launch_prob(b->mixed, b->params.inst, b->params.marked, b->params.bonds, b->params.arena, b->B, dprob,
-                       b->stream));
+  GMPS_HIP(launch_prob(b->mixed, b->params.inst, b->params.marked, b->params.bonds, b->params.arena, readout_edge(b),
+                       b->B, dprob, b->stream));
   GMPS_HIP(hipMemcpyAsync(out_p, dprob, sizeof(double) * b->B, hipMemcpyDeviceToHost, b->stream));
   bool bad = false;
   int rc = any_bad_status(b, &bad);
@@ -591,26 +601,39 @@ int marked_prob(gmps_batch* b, double* out_p) {
 int sample_shots(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_t seed, uint64_t* out_bits,
                  int64_t* out_hits) {
   if (!b || !shots || (shots_len != 1 && shots_len != b->B)) return GMPS_E_ARG;
-  std::vector<int64_t> off(b->B + 1, 0);
-  for (int i = 0; i < b->B; ++i) {
-    const int64_t s = shots[shots_len == 1 ? 0 : i];
-    if (s < 0) return GMPS_E_ARG;
-    off[i + 1] = off[i] + s;
-  }
-  const int64_t total = off[b->B];
-  const size_t need = align_up(sizeof(int64_t) * (b->B + 1)) + align_up(sizeof(uint64_t) * std::max<int64_t>(total, 1));
-  int rc = ensure_stage(b, need);
-  if (rc != GMPS_OK) return rc;
-  char* st = reinterpret_cast<char*>(b->stage);
-  int64_t* doff = reinterpret_cast<int64_t*>(st);
-  uint64_t* dbits = reinterpret_cast<uint64_t*>(st + align_up(sizeof(int64_t) * (b->B + 1)));
+  for (int i = 0; i < shots_len; ++i)
+    if (shots[i] < 0) return GMPS_E_ARG;
+  // The instances are sampled in chunks whose offset table and bitstrings fit the staging
+  // region of the workspace; a chunk's bits are copied out before the next chunk runs.
+  char* st = b->ws + b->lay.stage;
   unsigned long long* dhits = reinterpret_cast<unsigned long long*>(b->ws + b->lay.hits);
-  GMPS_HIP(hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (b->B + 1), hipMemcpyHostToDevice, b->stream));
   GMPS_HIP(hipMemsetAsync(dhits, 0, sizeof(uint64_t) * b->B, b->stream));
-  GMPS_HIP(launch_sample(b->mixed, b->max_cm, b->params.inst, b->params.marked, b->params.bonds, b->params.arena,
-                         b->B, doff, total, seed, dbits, dhits, b->stream));
-  if (out_bits && total > 0)
-    GMPS_HIP(hipMemcpyAsync(out_bits, dbits, sizeof(uint64_t) * total, hipMemcpyDeviceToHost, b->stream));
+  std::vector<int64_t> off;
+  int64_t done = 0;  // shots of the instances before the current chunk
+  for (int i0 = 0; i0 < b->B;) {
+    off.assign(1, 0);
+    int i1 = i0;
+    for (; i1 < b->B; ++i1) {
+      const int64_t s = shots[shots_len == 1 ? 0 : i1];
+      const size_t need = align_up(sizeof(int64_t) * (off.size() + 1)) + sizeof(uint64_t) * (size_t)(off.back() + s);
+      if (need > kStageBytes) break;
+      off.push_back(off.back() + s);
+    }
+    if (i1 == i0) return GMPS_E_WORKSPACE;  // one instance's shots exceed the staging region
+    const int nb = i1 - i0;
+    const int64_t total = off.back();
+    int64_t* doff = reinterpret_cast<int64_t*>(st);
+    uint64_t* dbits = reinterpret_cast<uint64_t*>(st + align_up(sizeof(int64_t) * (nb + 1)));
+    GMPS_HIP(hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, b->stream));
+    GMPS_HIP(launch_sample(b->mixed, b->max_cm, b->params.inst + i0, b->params.marked, b->params.bonds + (int64_t)i0 * kBondStride,
+                           b->params.arena, readout_edge(b), nb, i0, doff, total, seed, dbits, dhits + i0, b->stream));
+    if (out_bits && total > 0)
+      GMPS_HIP(hipMemcpyAsync(out_bits + done, dbits, sizeof(uint64_t) * total, hipMemcpyDeviceToHost, b->stream));
+    // the staging region is reused by the next chunk
+    GMPS_HIP(hipStreamSynchronize(b->stream));
+    done += total;
+    i0 = i1;
+  }
   if (out_hits) GMPS_HIP(hipMemcpyAsync(out_hits, dhits, sizeof(int64_t) * b->B, hipMemcpyDeviceToHost, b->stream));
   GMPS_HIP(hipStreamSynchronize(b->stream));
   return GMPS_OK;
@@ -622,17 +645,51 @@ int gmps_amplitudes(gmps_batch* b, int32_t inst, const uint64_t* xs, int64_t cnt
   const int n = b->inst_h[inst].n;
   for (int64_t t = 0; t < cnt; ++t)
     if (n < 64 && (xs[t] >> n) != 0) return GMPS_E_ARG;
-  const size_t need = align_up(sizeof(uint64_t) * cnt) + align_up(sizeof(double) * 2 * cnt);
-  int rc = ensure_stage(b, need);
-  if (rc != GMPS_OK) return rc;
-  char* st = reinterpret_cast<char*>(b->stage);
-  uint64_t* dxs = reinterpret_cast<uint64_t*>(st);
-  double* dout = reinterpret_cast<double*>(st + align_up(sizeof(uint64_t) * cnt));
-  GMPS_HIP(hipMemcpyAsync(dxs, xs, sizeof(uint64_t) * cnt, hipMemcpyHostToDevice, b->stream));
-  GMPS_HIP(launch_amplitudes(b->mixed, b->max_cm, b->params.inst, inst, b->params.bonds, b->params.arena, dxs, cnt,
-                             dout, b->stream));
-  GMPS_HIP(hipMemcpyAsync(out_reim, dout, sizeof(double) * 2 * cnt, hipMemcpyDeviceToHost, b->stream));
+  // queries pass through the staging region in chunks; each amplitude is divided by the norm
+  // of the state (the chain's norm differs from 1 by the rounding of its stored tensors)
+  char* st = b->ws + b->lay.stage;
+  double* dnorm = reinterpret_cast<double*>(st);
+  const int64_t chunk = (int64_t)((kStageBytes - kAlign) / (sizeof(uint64_t) + 2 * sizeof(double)));
+  double norm2 = 0.0;
+  for (int64_t t0 = 0; t0 < cnt; t0 += chunk) {
+    const int64_t c = std::min(chunk, cnt - t0);
+    uint64_t* dxs = reinterpret_cast<uint64_t*>(st + kAlign);
+    double* dout = reinterpret_cast<double*>(st + kAlign + align_up(sizeof(uint64_t) * c));
+    GMPS_HIP(hipMemcpyAsync(dxs, xs + t0, sizeof(uint64_t) * c, hipMemcpyHostToDevice, b->stream));
+    GMPS_HIP(launch_amplitudes(b->mixed, b->max_cm, b->params.inst, inst, b->params.bonds, b->params.arena,
+                               readout_edge(b), dxs, c, dout, dnorm, b->stream));
+    GMPS_HIP(hipMemcpyAsync(out_reim + 2 * t0, dout, sizeof(double) * 2 * c, hipMemcpyDeviceToHost, b->stream));
+    if (t0 == 0) GMPS_HIP(hipMemcpyAsync(&norm2, dnorm, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    GMPS_HIP(hipStreamSynchronize(b->stream));
+  }
+  if (!(norm2 > 0.0) || !std::isfinite(norm2)) return GMPS_E_NUMERIC;
+  const double inv = 1.0 / std::sqrt(norm2);
+  for (int64_t t = 0; t < 2 * cnt; ++t) out_reim[t] *= inv;
+  return GMPS_OK;
+}
+
+int gmps_overlap_uniform(gmps_batch* b, int32_t inst, double* out_reim) {
+  if (!b || inst < 0 || inst >= b->B || !out_reim) return GMPS_E_ARG;
+  char* st = b->ws + b->lay.stage;
+  double* dnorm = reinterpret_cast<double*>(st);
+  double* dov = reinterpret_cast<double*>(st + kAlign);
+  const uint64_t x0 = 0;
+  uint64_t* dxs = reinterpret_cast<uint64_t*>(st + 2 * kAlign);
+  double* damp = reinterpret_cast<double*>(st + 3 * kAlign);
+  // the norm comes with an amplitude query (any index) through the same launch
+  GMPS_HIP(hipMemcpyAsync(dxs, &x0, sizeof(uint64_t), hipMemcpyHostToDevice, b->stream));
+  GMPS_HIP(launch_amplitudes(b->mixed, b->max_cm, b->params.inst, inst, b->params.bonds, b->params.arena,
+                             readout_edge(b), dxs, 1, damp, dnorm, b->stream));
+  GMPS_HIP(launch_overlap_uniform(b->mixed, b->params.inst, inst, b->params.bonds, b->params.arena, readout_edge(b),
+                                  dov, b->stream));
+  double h[3];
+  GMPS_HIP(hipMemcpyAsync(h, dov, sizeof(double) * 2, hipMemcpyDeviceToHost, b->stream));
+  GMPS_HIP(hipMemcpyAsync(h + 2, dnorm, sizeof(double), hipMemcpyDeviceToHost, b->stream));
   GMPS_HIP(hipStreamSynchronize(b->stream));
+  if (!(h[2] > 0.0) || !std::isfinite(h[2])) return GMPS_E_NUMERIC;
+  const double inv = 1.0 / std::sqrt(h[2]);
+  out_reim[0] = h[0] * inv;
+  out_reim[1] = h[1] * inv;
   return GMPS_OK;
 }
 
@@ -667,7 +724,6 @@ int gmps_destroy(gmps_batch* b) {
   if (b->staging_done) hipEventDestroy(b->staging_done);
   if (b->ev_start) hipEventDestroy(b->ev_start);
   if (b->ev_stop) hipEventDestroy(b->ev_stop);
-  if (b->stage) hipFree(b->stage);
   for (int kd = 0; kd < kLaunchKinds; ++kd) {
     if (b->side[kd]) hipStreamDestroy(b->side[kd]);
     if (b->join_ev[kd]) hipEventDestroy(b->join_ev[kd]);

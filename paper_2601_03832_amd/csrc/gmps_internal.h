@@ -16,7 +16,31 @@ struct InstDev {
   double trunc_w;          // largest dropped-weight fraction of one truncation
   double flops64, flops32; // algorithmic flops spent so far
   int64_t warm_off;        // byte offset of this instance's first warm-start record
+  int64_t edge_off;        // complex-FP64 offset of this instance's first edge slot
+  int32_t ew;              // edge width: sites i < ew and i >= n - ew are edge sites
+  int32_t pad_;
 };
+
+// Edge sites. A stored isometry changes the state by its rounding error d times the rest of
+// the chain; the kernels fold the part of d inside the span of the stored vectors into the FP64
+// carry, and the rest is orthogonal to every state whose support at that bond lies in that span.
+// The Grover states (combinations of |s> and the M marked basis states) have supports of
+// dimension up to M+1 at a bond, and the bond of site i is at most 2^min(i, n-i): within
+// ew = ceil(log2(M+1)) sites of either end the stored span can be smaller than theirs, and a
+// rounding error there would rotate the state at first order. Those sites (and always the
+// norm-carrying end site) are therefore kept in complex FP64 in edge slots of their own, laid
+// out like a site slot (D, 2, D); their site slots hold storage-type copies. Every other site
+// (the bulk of the chain) is stored as complex64 on the mixed path.
+__host__ __device__ constexpr int edge_width(int M) {
+  int e = 1;
+  while ((1 << e) < M + 1 && e < 31) ++e;
+  return e;
+}
+__host__ __device__ constexpr int edge_count(int n, int ew) { return n <= 2 * ew ? n : 2 * ew; }
+// edge slot of site i, or -1 for a bulk site
+__host__ __device__ constexpr int edge_index(int i, int n, int ew) {
+  return n <= 2 * ew ? i : (i < ew ? i : (i >= n - ew ? ew + (n - 1 - i) : -1));
+}
 
 // The Jacobi SVD at (reflection j, site i) starts from the unitary it produced at the same
 // place in the previous iteration: the tile changes by O(theta) per iteration, so the
@@ -91,8 +115,9 @@ struct IterParams {
   double skip_tol;   // relative column norm below which Jacobi leaves a column unrotated
   double rank_tol;   // relative trailing norm at which the QR sweep stops (numerical rank)
   int32_t max_sweeps;
-  int32_t stoch_round;  // mixed path: stochastic rounding of FP64 results stored as complex64
+  int32_t stoch_round;  // stochastic (1) or nearest (0) rounding of FP64 results stored as complex64
   void* warm;           // warm-start records (null: every Jacobi starts from the identity)
+  void* edge;           // edge slots (complex FP64)
 };
 
 }  // namespace gmps

@@ -18,6 +18,19 @@
 // truncated), keeps U = M J / Sigma and carries Sigma J^H to the right. After a call the chain
 // is right-canonical with the norm in site 0, as the read-out kernels expect: a call whose last
 // truncation ran left to right ends with one right-to-left canonicalisation of the identity.
+//
+// Storage precision (S = float: GMPS_MIXED). All arithmetic is FP64. The bulk sites are stored
+// as complex64 and each rounding is compensated: a stored isometry Q~ = Q + d changes the state
+// by d times the rest of the chain, and the part of d inside the span of Q's columns (rows, for
+// a right-orthonormal site) is undone to first order by the carry that moves on,
+// R' = R - (Q^H d) R (for kept rows v_q of a truncation, Y' = Y - Y Z with Z[p][q] = <v_q | d_p>).
+// The part outside that span is orthogonal to every state whose support at this bond lies in
+// it, as the Grover states' supports do away from the chain's ends: it cannot rotate the state
+// within their span, and it reaches the marked probability only at second order. The edge
+// sites (within ceil(log2(M+1)) of either end, where a bond of 2^i cannot hold that support,
+// and the norm-carrying end site) stay in complex FP64 in edge slots, and the hand-over between
+// the waves is FP64 too. With plain rounding every stored tile moves the rotation angle by
+// O(2^-24), and the moves add up over the k (M+1) 2n stores of a run.
 #pragma once
 #include "gmps_team.h"
 
@@ -26,13 +39,16 @@ namespace gmps {
 template <class S, int CM>
 struct PipeLds {
   using T = TeamShape<CM, 64>;
-  cx<S> W[2][CM][2][CM];         // canonicalisation: staged MPO blocks [c0 A | c1 P A]
+  cd W[2][CM][2][CM];            // canonicalisation: staged MPO blocks [c0 A | c1 P A]
   cd R[T::KQ][T::D];             // canonicalisation carry: R (to the right) or R~ = L^H (left)
-  cd V[T::KQ][T::PQ * T::RQ];    // Householder vectors
+  cd V[T::KQ][T::PQ * T::RQ];    // Householder vectors, then the columns of Q
   double tau[T::KQ];
-  cx<S> Q[T::KQ][2][T::KQ];      // truncation: staged site of the canonicalised chain
+  cd ZQ[T::KQ][T::KQ];           // canonicalisation: Q^H d of the stored Q~ = Q + d
+  cd Q[T::KQ][2][T::KQ];         // truncation: staged site of the canonicalised chain
   cd Y[T::KQ][CM];               // truncation carry, [canonical bond][kept bond]
-  cx<S> H[2][CM][2][CM];         // final site tensors handed over, by tick parity
+  cd WB[CM][2 * CM];             // truncation: the kept vectors, by position
+  cd ZT[CM][CM];                 // truncation: Z[p][q] = <v_q | d_p>
+  cd H[2][CM][2][CM];            // final site tensors handed over (as stored), by tick parity
   int32_t bond[kBondStride];     // bonds of the chain the truncation wave produces
   int32_t rdim[2][kBondStride];  // bonds of the canonicalised chain, by reflection parity
 };
@@ -63,13 +79,19 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
   const int cap = I->cap < CM ? I->cap : CM;
   const int64_t k = bdp->k;
   cx<S>* arena = reinterpret_cast<cx<S>*>(P.arena) + I->site_off;
+  cd* edges = reinterpret_cast<cd*>(P.edge) + I->edge_off;
+  const int ew = I->ew;
+  // the complex-FP64 slot of an edge site, or null for a bulk site
+  auto eslot = [&](int i) -> cd* {
+    const int ei = edge_index(i, n, ew);
+    return ei >= 0 ? edges + (int64_t)ei * SLOT : nullptr;
+  };
   const uint64_t* Wm = P.marked + I->marked_off;
+  const bool sr = P.stoch_round != 0;
+  uint64_t rs_state = mix64(((uint64_t)me << 32) ^ ((uint64_t)I->k_done * 0x9E3779B97F4A7C15ull) ^ (uint64_t)threadIdx.x);
   const double tol2 = P.trunc_tol * P.trunc_tol;
   const double rank2 = P.rank_tol * P.rank_tol;
   const double skip2 = P.skip_tol * P.skip_tol;
-  const bool sr = P.stoch_round != 0;
-  const uint64_t k_done0 = (uint64_t)I->k_done;
-  uint64_t rs_state = mix64(((uint64_t)me << 32) ^ (k_done0 * 0x9E3779B97F4A7C15ull) ^ (uint64_t)threadIdx.x);
 
   for (int l = wave * TW + tl; l < kBondStride; l += 2 * TW) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
   team_sync_global();
@@ -82,7 +104,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
   // ---------------------------------------------------------------- canonicalisation step
   // Reflection jr (0..M, M = diffusion) at site i, direction lr; the site tensor comes from
   // the handover buffer h (null: from its arena slot). rdo: the ranks it produces.
-  auto canon_step = [&](int jr, bool ident, bool lr, int i, const cx<S> (*h)[2][CM], int32_t* rdo) {
+  auto canon_step = [&](int jr, bool ident, bool lr, int i, const cd (*h)[2][CM], int32_t* rdo) {
     const bool diff = (jr == M);
     const int xb = (diff || ident) ? 0 : (int)((Wm[jr] >> (n - 1 - i)) & 1ull);
     const double c0 = ident ? 1.0 : (diff ? -1.0 : 1.0);
@@ -92,34 +114,39 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
     const bool first = lr ? (i == 0) : (i == n - 1);
     const bool last = lr ? (i == n - 1) : (i == 0);
     cx<S>* slot = arena + (int64_t)i * SLOT;
+    cd* es = eslot(i);
     if (first && tl == 0) {
       rdo[lr ? 0 : n] = 1;
       L.R[0][0] = {1.0, 0.0};
       L.R[0][1] = {1.0, 0.0};
     }
-    // stage [c0 A | c1 P A] (coefficients on the last site only)
+    // stage [c0 A | c1 P A] (coefficients on the last site only): the site as the truncation
+    // wave handed it over, else from its edge slot (complex FP64) or its site slot
     {
-      const S s0 = (S)(mpo_last ? c0 : 1.0), s1 = (S)(mpo_last ? c1 : 1.0);
+      const double s0 = mpo_last ? c0 : 1.0, s1 = mpo_last ? c1 : 1.0;
 #pragma unroll
       for (int t = 0; t < NE; ++t) {
         const int e = tl + t * TW;
         if (e < CM * CM) {
           const int a = e / CM, b = e % CM;
           const bool ok = a < chl && b < chr;
-          cx<S> a0 = czero<S>(), a1 = czero<S>();
+          cd a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
           if (ok) {
             if (h) {
               a0 = h[a][0][b];
               a1 = h[a][1][b];
+            } else if (es) {
+              a0 = es[a * 2 * D + b];
+              a1 = es[a * 2 * D + D + b];
             } else {
-              a0 = slot[a * 2 * D + b];
-              a1 = slot[a * 2 * D + D + b];
+              a0 = up(slot[a * 2 * D + b]);
+              a1 = up(slot[a * 2 * D + D + b]);
             }
           }
           L.W[0][a][0][b] = s0 * a0;
           L.W[0][a][1][b] = s0 * a1;
-          L.W[1][a][0][b] = s1 * proj_apply<S>(a0, a1, 0, diff, xb);
-          L.W[1][a][1][b] = s1 * proj_apply<S>(a0, a1, 1, diff, xb);
+          L.W[1][a][0][b] = s1 * proj_apply<double>(a0, a1, 0, diff, xb);
+          L.W[1][a][1][b] = s1 * proj_apply<double>(a0, a1, 1, diff, xb);
         }
       }
     }
@@ -136,18 +163,18 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
       for (int e = 0; e < RQ; ++e) {
         const int row = qh + PQ * e;
         const int a = row >> 1, s = row & 1;
-        cx<S> acc = czero<S>();
+        cd acc = {0.0, 0.0};
         if (row < 2 * r && qc < Dr) {
 #pragma unroll
           for (int bl = 0; bl < 2; ++bl) {
             if (last || bl == beta) {
 #pragma unroll
               for (int ap = 0; ap < CM; ++ap)
-                if (ap < chl) acc = cfma(acc, down<S>(L.R[a][bl * chl + ap]), L.W[bl][ap][s][bcol]);
+                if (ap < chl) acc = cfma(acc, L.R[a][bl * chl + ap], L.W[bl][ap][s][bcol]);
             }
           }
         }
-        x[e] = up(acc);
+        x[e] = acc;
       }
     } else {
       // X'^H, X' = MPO(A_i) * L_{i+1} with L = R~^H: rows (c, s) = 2c + s, columns
@@ -159,34 +186,35 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
       for (int e = 0; e < RQ; ++e) {
         const int row = qh + PQ * e;
         const int c = row >> 1, s = row & 1;
-        cx<S> acc = czero<S>();
+        cd acc = {0.0, 0.0};
         if (row < 2 * r && qc < Dr) {
 #pragma unroll
           for (int al = 0; al < 2; ++al) {
             if (last || al == alpha) {
 #pragma unroll
               for (int bp = 0; bp < CM; ++bp)
-                if (bp < chr) acc = cfma(acc, conj(L.W[al][last ? 0 : acol][s][bp]), down<S>(L.R[c][al * chr + bp]));
+                if (bp < chr) acc = cfma(acc, conj(L.W[al][last ? 0 : acol][s][bp]), L.R[c][al * chr + bp]);
             }
           }
         }
         // the left boundary keeps X' itself (one row): conjugate back
-        x[e] = last ? conj(up(acc)) : up(acc);
+        x[e] = last ? conj(acc) : acc;
       }
     }
-    {
-      const double macs = (double)r * (first ? 1 : 2 * (lr ? chl : chr)) * 2.0 * Dr;
-      if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
-    }
+    f64 += 8.0 * (double)r * (first ? 1 : 2 * (lr ? chl : chr)) * 2.0 * Dr;
     if (last) {
-      // the boundary site stores its tile: left to right the column (a, s) of site n-1,
-      // right to left the row (s, c) of site 0
+      // the boundary site holds the norm: its tile goes to its edge slot and, as stored, to its
+      // site slot (left to right the column (a, s) of site n-1, right to left the row (s, c) of
+      // site 0)
       if (real && qc == 0) {
 #pragma unroll
         for (int e = 0; e < RQ; ++e) {
           const int row = qh + PQ * e;
-          if (row < 2 * r) slot[(lr ? (row >> 1) * 2 * D : 0) + (row & 1) * D + (lr ? 0 : (row >> 1))] =
-              store_cast<S>(x[e], rs_state, sr);
+          if (row < 2 * r) {
+            const int off = (lr ? (row >> 1) * 2 * D : 0) + (row & 1) * D + (lr ? 0 : (row >> 1));
+            slot[off] = store_cast<S>(x[e], rs_state, sr);
+            es[off] = x[e];
+          }
         }
       }
       if (tl == 0) {
@@ -212,15 +240,19 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
       f64 += 8.0 * (2.0 * mm * cc * kk - (mm + cc) * kk * kk + 2.0 * kk * kk * kk / 3.0) +
              8.0 * (2.0 * mm * kk * kk - 2.0 * kk * kk * kk / 3.0);
     }
+    // the stored Q~ (stochastic rounding on the mixed path unless round_mode asks for nearest)
+    cx<S> qs[RQ];
+#pragma unroll
+    for (int e = 0; e < RQ; ++e) qs[e] = store_cast<S>(q[e], rs_state, sr);
     if (real && qc < kr) {
 #pragma unroll
       for (int e = 0; e < RQ; ++e) {
         const int row = qh + PQ * e;
         if (row < m) {
-          if (lr)
-            slot[(row >> 1) * 2 * D + (row & 1) * D + qc] = store_cast<S>(q[e], rs_state, sr);
-          else  // site i keeps Q^H: [k][s][c] = conj(Q[(c, s)][k])
-            slot[qc * 2 * D + (row & 1) * D + (row >> 1)] = store_cast<S>(conj(q[e]), rs_state, sr);
+          // right to left site i keeps Q^H: [k][s][c] = conj(Q[(c, s)][k])
+          const int off = lr ? (row >> 1) * 2 * D + (row & 1) * D + qc : qc * 2 * D + (row & 1) * D + (row >> 1);
+          slot[off] = lr ? qs[e] : conj(qs[e]);
+          if (es) es[off] = lr ? q[e] : conj(q[e]);
         }
       }
     }
@@ -230,6 +262,46 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
         const int row = qh + PQ * e;
         if (row < kr) L.R[row][qc] = x[e];
       }
+    }
+    if (kMixed && !es) {
+      // compensation of the stored Q~ = Q + d: R <- R - (Q^H d) R. Column b of Z = Q^H d is
+      // formed in slot b from the columns of Q (through V, free once Q is formed); row a of
+      // the correction then reads Z and R from LDS.
+      cd dq[RQ];
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) dq[e] = up(qs[e]) - q[e];
+      wave_sync();
+      if (qc < kr) {
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) L.V[qc][qh + PQ * e] = q[e];
+      }
+      wave_sync();
+      for (int a = 0; a < kr; ++a) {
+        cd z = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) z = z + cmulc(L.V[a][qh + PQ * e], dq[e]);
+        z = gsum<PQ>(z);
+        if (qh == 0 && qc < kr) L.ZQ[a][qc] = z;
+      }
+      wave_sync();
+      cd corr[RQ];
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) {
+        const int row = qh + PQ * e;
+        cd cz = {0.0, 0.0};
+        if (qc < Dr && row < kr)
+          for (int b = 0; b < kr; ++b) cz = cfma(cz, L.ZQ[row][b], L.R[b][qc]);
+        corr[e] = cz;
+      }
+      wave_sync();
+      if (qc < Dr) {
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) {
+          const int row = qh + PQ * e;
+          if (row < kr) L.R[row][qc] = x[e] - corr[e];
+        }
+      }
+      f64 += 8.0 * ((double)kr * kr * m + (double)kr * kr * Dr);
     }
     if (tl == 0) rdo[lr ? i + 1 : i] = kr;
     wave_sync();
@@ -244,20 +316,28 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
   // canonicalised chain's bonds. Writes the final site i to h and, when no canonicalisation
   // follows in the stage (keep_slot), to its slot; a following canonicalisation rewrites the
   // slot from h.
-  auto trunc_step = [&](int jr, bool lr, int i, const int32_t* rdi, cx<S> (*h)[2][CM], bool keep_slot) {
+  auto trunc_step = [&](int jr, bool lr, int i, const int32_t* rdi, cd (*h)[2][CM], bool keep_slot) {
     const bool wr = real && keep_slot;
     const bool diff = (jr == M);
     const bool first = lr ? (i == 0) : (i == n - 1);
     const bool edge = lr ? (i == n - 1) : (i == 0);  // absorbs the carry, holds the norm
     cx<S>* slot = arena + (int64_t)i * SLOT;
+    cd* es = eslot(i);
     const int ri = rdi[i], rn = rdi[i + 1];
     if (first && tl == 0) L.Y[0][0] = {1.0, 0.0};
-    // stage the canonicalised site (ri, 2, rn), then load the next one
-    if (first) qpre.load(slot, tl, ri, rn);
-    qpre.stage(&L.Q[0][0][0], tl);
+    // stage the canonicalised site (ri, 2, rn), then load the next one: an edge site (the first
+    // one holds the norm) from its edge slot, a bulk site from the prefetch of its site slot
+    if (es) {
+      for (int e = tl; e < KQ * 2 * KQ; e += TW) {
+        const int a = e / (2 * KQ), s = (e / KQ) & 1, b = e % KQ;
+        (&L.Q[0][0][0])[e] = (a < ri && b < rn) ? es[a * 2 * D + s * D + b] : cd{0.0, 0.0};
+      }
+    } else {
+      qpre.stage(&L.Q[0][0][0], tl);
+    }
     if (!edge) {
       const int nx = lr ? i + 1 : i - 1;
-      qpre.load(arena + (int64_t)nx * SLOT, tl, rdi[nx], rdi[nx + 1]);
+      if (!eslot(nx)) qpre.load(arena + (int64_t)nx * SLOT, tl, rdi[nx], rdi[nx + 1]);
     }
     wave_sync();
     if (edge) {
@@ -267,24 +347,27 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
       const bool act = tl < 2 * chc;
       const int s = tl >= chc ? 1 : 0;
       const int jj = tl - s * chc;
-      cx<S> acc = czero<S>();
+      cd acc = {0.0, 0.0};
       if (act) {
 #pragma unroll
         for (int b = 0; b < KQ; ++b)
-          if (b < cr) acc = lr ? cfma(acc, down<S>(L.Y[b][jj]), L.Q[b][s][0]) : cfma(acc, L.Q[0][s][b], down<S>(L.Y[b][jj]));
+          if (b < cr) acc = lr ? cfma(acc, L.Y[b][jj], L.Q[b][s][0]) : cfma(acc, L.Q[0][s][b], L.Y[b][jj]);
       }
-      {
-        const double macs = 2.0 * cr * chc;
-        if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
-      }
-      const double nn = tsum<TW>(act ? norm2(up(acc)) : 0.0);
+      f64 += 8.0 * 2.0 * cr * chc;
+      const double nn = tsum<TW>(act ? norm2(acc) : 0.0);
       if (!isfinite(nn) || !(nn > 0.0)) status |= GMPS_ST_NAN;
       const double nr = sqrt(nn);
       if (diff) drift = fmax(drift, fabs(nr - 1.0));
-      const cx<S> out = store_cast<S>((diff ? 1.0 / nr : 1.0) * up(acc), rs_state, sr);
+      // the new norm-carrying end site: in FP64 to the canonicalisation wave and, when no
+      // canonicalisation follows in this stage, to its edge slot (and as stored to its site slot)
+      const cd out = (diff ? 1.0 / nr : 1.0) * acc;
       if (act) {
-        if (wr) slot[lr ? (jj * 2 * D + s * D) : (s * D + jj)] = out;
+        const int off = lr ? (jj * 2 * D + s * D) : (s * D + jj);
         if (lr) h[jj][s][0] = out; else h[0][s][jj] = out;
+        if (wr) {
+          slot[off] = store_cast<S>(out, rs_state, sr);
+          es[off] = out;
+        }
       }
       if (tl == 0) L.bond[lr ? n : 0] = 1;
       wave_sync();
@@ -304,18 +387,15 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
       const int row = jh + PJ * e;
       const int s = row >= chn ? 1 : 0;
       const int jj = row - s * chn;
-      cx<S> acc = czero<S>();
+      cd acc = {0.0, 0.0};
       if (jc < ncol && row < c) {
 #pragma unroll
         for (int b = 0; b < KQ; ++b)
-          if (b < cr) acc = lr ? cfma(acc, down<S>(L.Y[b][jj]), L.Q[b][s][jc]) : cfma(acc, L.Q[jc][s][b], down<S>(L.Y[b][jj]));
+          if (b < cr) acc = lr ? cfma(acc, L.Y[b][jj], L.Q[b][s][jc]) : cfma(acc, L.Q[jc][s][b], L.Y[b][jj]);
       }
-      a[e] = lr ? up(acc) : conj(up(acc));
+      a[e] = lr ? acc : conj(acc);
     }
-    {
-      const double macs = (double)ncol * 2.0 * cr * chn;
-      if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
-    }
+    f64 += 8.0 * (double)ncol * 2.0 * cr * chn;
     wave_sync();  // every read of Y is done before it is rewritten below
     cd uu[RU];
 #pragma unroll
@@ -348,30 +428,80 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
     const double dropped = tsum<TW>((jh == 0 && colok && !keep) ? sg : 0.0);
     if (stot > 0.0) truncw = fmax(truncw, dropped / stot);
     if (!isfinite(stot)) status |= GMPS_ST_NAN;
+    const double rs = keep ? rsqrt_acc(sg) : 0.0;  // 1/sigma
+    cd wv[RJ];  // this slot's kept vector: right to left a row of V^H, left to right a column of U
+    cx<S> vs[RJ];  // ... as stored
+#pragma unroll
+    for (int e = 0; e < RJ; ++e) {
+      wv[e] = lr ? rs * a[e] : rs * conj(a[e]);
+      vs[e] = store_cast<S>(wv[e], rs_state, sr);
+    }
     if (keep) {
-      const double rs = rsqrt_acc(sg);  // 1/sigma
 #pragma unroll
       for (int e = 0; e < RJ; ++e) {
         const int row = jh + PJ * e;
         if (row < c) {
           const int s = row >= chn ? 1 : 0;
           const int jp = row - s * chn;
-          // right to left: V^H[pos][s][jp] = conj(a) / sigma; left to right: U[jp][s][pos] = a / sigma
-          const cx<S> v = store_cast<S>(lr ? rs * a[e] : rs * conj(a[e]), rs_state, sr);
-          if (lr) {
-            if (wr) slot[jp * 2 * D + s * D + pos] = v;
-            h[jp][s][pos] = v;
-          } else {
-            if (wr) slot[pos * 2 * D + s * D + jp] = v;
-            h[pos][s][jp] = v;
+          // right to left: V^H[pos][s][jp] = conj(a) / sigma; left to right: U[jp][s][pos] = a / sigma;
+          // an edge site keeps it in FP64, a bulk site as stored
+          const int off = lr ? jp * 2 * D + s * D + pos : pos * 2 * D + s * D + jp;
+          const cd hv = es ? wv[e] : up(vs[e]);
+          if (wr) {
+            slot[off] = vs[e];
+            if (es) es[off] = wv[e];
           }
+          if (lr) h[jp][s][pos] = hv; else h[pos][s][jp] = hv;
         }
       }
+    }
+    // right to left: carry J Sigma [row][pos]; left to right: (Sigma J^H)^T [row][pos]
+    cd yv[RU];
+#pragma unroll
+    for (int e = 0; e < RU; ++e) yv[e] = (sg * rs) * (lr ? conj(uu[e]) : uu[e]);
+    if (kMixed && !es) {
+      // compensation of the stored vectors v~_p = v_p + d_p: Y <- Y - Y Z, Z[p][q] = <v_q | d_p>;
+      // the kept vectors go through LDS, row p of Z is formed in the slot of position p
+      if (keep) {
+#pragma unroll
+        for (int e = 0; e < RJ; ++e) {
+          const int row = jh + PJ * e;
+          if (row < c) L.WB[pos][row] = wv[e];
+        }
+#pragma unroll
+        for (int e = 0; e < RU; ++e) {
+          const int row = jh + PJ * e;
+          if (row < ncol) L.Y[row][pos] = yv[e];
+        }
+      }
+      wave_sync();
+      for (int q = 0; q < chi_new; ++q) {
+        cd z = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < RJ; ++e) {
+          const int row = jh + PJ * e;
+          if (row < c) z = z + cmulc(L.WB[q][row], up(vs[e]) - wv[e]);
+        }
+        z = gsum<PJ>(z);
+        if (keep && jh == 0) L.ZT[pos][q] = z;
+      }
+      wave_sync();
 #pragma unroll
       for (int e = 0; e < RU; ++e) {
         const int row = jh + PJ * e;
-        // right to left: carry J Sigma [row][pos]; left to right: (Sigma J^H)^T [row][pos]
-        if (row < ncol) L.Y[row][pos] = (sg * rs) * (lr ? conj(uu[e]) : uu[e]);
+        cd cz = {0.0, 0.0};
+        if (keep && row < ncol)
+          for (int p = 0; p < chi_new; ++p) cz = cfma(cz, L.Y[row][p], L.ZT[p][pos]);
+        yv[e] = yv[e] - cz;
+      }
+      wave_sync();
+      f64 += 8.0 * ((double)chi_new * chi_new * c + (double)chi_new * chi_new * ncol);
+    }
+    if (keep) {
+#pragma unroll
+      for (int e = 0; e < RU; ++e) {
+        const int row = jh + PJ * e;
+        if (row < ncol) L.Y[row][pos] = yv[e];
       }
     }
     if (tl == 0) L.bond[lr ? i + 1 : i] = chi_new;
@@ -411,7 +541,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
           const int i = lr_c ? tick - 1 : n - tick;
           // follows the truncation wave (handover of the previous tick) when it runs,
           // else reads the arena
-          const cx<S>(*h)[2][CM] = do_t ? L.H[(tick - 1) & 1] : nullptr;
+          const cd(*h)[2][CM] = do_t ? L.H[(tick - 1) & 1] : nullptr;
           canon_step(extra ? 0 : (int)(jc2 % nrefl), extra, lr_c, i, h, L.rdim[extra ? 0 : (jc2 & 1)]);
         }
       }

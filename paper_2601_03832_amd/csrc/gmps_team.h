@@ -50,13 +50,13 @@ struct TeamLds {
   using T = TeamShape<CM, TW>;
   union {
     struct {                                  // QR sweep
-      cx<S> W[2][CM][2][CM];                  // staged MPO blocks [c0 A | c1 P A] of the site
+      cd W[2][CM][2][CM];                     // staged MPO blocks [c0 A | c1 P A] of the site
       cd R[T::KQ][T::D];                      // R of the previous step, original column order
       cd V[T::KQ][T::PQ * T::RQ];             // Householder vectors of this step
       double tau[T::KQ];
     } q;
     struct {                                  // SVD sweep
-      cx<S> Q[T::KQ][2][T::KQ];               // staged left-orthonormal site tensor
+      cd Q[T::KQ][2][T::KQ];                  // staged left-orthonormal site tensor
       cd Y[T::KQ][CM];                        // U Sigma of the previous step
       cd XA[T::NBUF][T::KJ][T::PJ * T::RJ];   // Jacobi partner exchange
       cd XU[T::NBUF][T::KJ][T::PJ * T::RU];   // (its first buffer also holds the Gram matrix
@@ -69,6 +69,14 @@ struct TeamLds {
   int32_t colr[TW];
   int32_t bond[kBondStride];
   int32_t rdim[kBondStride];
+  // Q^H d of a compensated store: in the staging block when it holds KQ x KQ complex doubles,
+  // else here
+  static constexpr bool kZInW = sizeof(cd) * 4 * CM * CM >= sizeof(cd) * (CM + 1) * (CM + 1);
+  cd zq[kZInW ? 1 : (CM + 1) * (CM + 1)];
+  __device__ cd* zbuf() { return kZInW ? reinterpret_cast<cd*>(&u.q.W[0][0][0][0]) : zq; }
+  // the kept rows and Z of a compensated truncation go into the (free) Jacobi exchange buffers
+  static_assert(sizeof(u.s.XA) >= sizeof(cd) * 2 * CM * CM, "kept rows fit XA");
+  static_assert(sizeof(u.s.XU) >= sizeof(cd) * CM * CM, "Z fits XU");
 };
 
 // LDS of a team's pre-contracted reflections, placed after the TeamLds of every team of the
@@ -199,6 +207,47 @@ struct TeamAPre {
       }
     }
   }
+  // staged in complex FP64: from the prefetched values or, for an edge site (es non-null), from
+  // its complex-FP64 edge slot
+  __device__ __forceinline__ void stage64(cd (*W)[CM][2][CM], const cd* es, int tl, bool diff, int xb, double c0,
+                                          double c1) const {
+    constexpr int D = 2 * CM;
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tl + t * TW;
+      if (e < CM * CM) {
+        const int a = e / CM, b = e % CM;
+        const bool ok = a < chl_ && b < chr_;
+        cd a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+        if (ok) {
+          a0 = es ? es[a * 2 * D + b] : up(v0[t]);
+          a1 = es ? es[a * 2 * D + D + b] : up(v1[t]);
+        }
+        W[0][a][0][b] = c0 * a0;
+        W[0][a][1][b] = c0 * a1;
+        W[1][a][0][b] = c1 * proj_apply<double>(a0, a1, 0, diff, xb);
+        W[1][a][1][b] = c1 * proj_apply<double>(a0, a1, 1, diff, xb);
+      }
+    }
+  }
+  __device__ __forceinline__ void stage_a64(cd (*W)[CM][2][CM], const cd* es, int tl, double c0) const {
+    constexpr int D = 2 * CM;
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tl + t * TW;
+      if (e < CM * CM) {
+        const int a = e / CM, b = e % CM;
+        const bool ok = a < chl_ && b < chr_;
+        cd a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+        if (ok) {
+          a0 = es ? es[a * 2 * D + b] : up(v0[t]);
+          a1 = es ? es[a * 2 * D + D + b] : up(v1[t]);
+        }
+        W[0][a][0][b] = c0 * a0;
+        W[0][a][1][b] = c0 * a1;
+      }
+    }
+  }
   // the site tensor alone, scaled by c0 (pre-contracted reflections)
   __device__ __forceinline__ void stage_a(cx<S> (*W)[CM][2][CM], int tl, S c0) const {
 #pragma unroll
@@ -233,12 +282,14 @@ struct TeamQPre {
       v[t] = slot[a * 2 * D + s * D + b];
     }
   }
-  __device__ __forceinline__ void stage(cx<S>* lds_q, int tl) const {
+  // staged in the storage type, or up-converted to complex FP64 (T = double)
+  template <class T>
+  __device__ __forceinline__ void stage(cx<T>* lds_q, int tl) const {
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = tl + t * TW;
       const int a = e / (2 * KQ), b = e % KQ;
-      if (e < KQ * 2 * KQ) lds_q[e] = (a < ri_ && b < rn_) ? v[t] : czero<S>();
+      if (e < KQ * 2 * KQ) lds_q[e] = (a < ri_ && b < rn_) ? cvt<T>(v[t]) : czero<T>();
     }
   }
 };
@@ -699,6 +750,103 @@ __device__ __forceinline__ int team_jacobi_wave(cd (&a)[RJ], cd (&u)[RU], int ba
   return sweeps;
 }
 
+
+// ------------------------------------------------------------- compensated complex64 stores
+// On the mixed path every arithmetic step is FP64 and only the isometries (all sites but the
+// norm-carrying end site, which the centre record keeps in FP64) are stored as complex64. A
+// stored isometry changes the state by its rounding error d times the rest of the chain. The
+// part of d inside the span of the stored vectors is folded into the FP64 carry that moves on;
+// the part outside that span is orthogonal to every state whose support at this bond lies in it,
+// as the Grover states' supports do, so it does not rotate the state within their span and
+// reaches the marked probability only at second order. Both helpers take workgroup barriers:
+// every thread of the workgroup calls them.
+
+// Thin Q of a QR step (QR layout: slot qc holds column qc, q[] in FP64, qs[] as stored): the
+// carry R (RB, rows < kr, columns < Dr) becomes R - (Q^H d) R. QB [KQ][PQ*RQ] and ZB [KQ*KQ]
+// are LDS scratch.
+template <int PQ, int RQ, int KQ, int DR, class S>
+__device__ __forceinline__ void comp_store_cols(const cd (&q)[RQ], const cx<S> (&qs)[RQ], int qc, int qh, int kr,
+                                                int Dr, cd (*QB)[PQ * RQ], cd* ZB, cd (*RB)[DR]) {
+  cd dq[RQ];
+#pragma unroll
+  for (int e = 0; e < RQ; ++e) dq[e] = up(qs[e]) - q[e];
+  lds_sync();
+  if (qc < kr) {
+#pragma unroll
+    for (int e = 0; e < RQ; ++e) QB[qc][qh + PQ * e] = q[e];
+  }
+  lds_sync();
+  for (int a = 0; a < kr; ++a) {
+    cd z = {0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < RQ; ++e) z = z + cmulc(QB[a][qh + PQ * e], dq[e]);
+    z = gsum<PQ>(z);
+    if (qh == 0 && qc < kr) ZB[a * KQ + qc] = z;
+  }
+  lds_sync();
+  cd corr[RQ];
+#pragma unroll
+  for (int e = 0; e < RQ; ++e) {
+    const int row = qh + PQ * e;
+    cd cz = {0.0, 0.0};
+    if (qc < Dr && row < kr)
+      for (int b = 0; b < kr; ++b) cz = cfma(cz, ZB[row * KQ + b], RB[b][qc]);
+    corr[e] = cz;
+  }
+  lds_sync();
+  if (qc < Dr) {
+#pragma unroll
+    for (int e = 0; e < RQ; ++e) {
+      const int row = qh + PQ * e;
+      if (row < kr) RB[row][qc] = RB[row][qc] - corr[e];
+    }
+  }
+}
+
+// Kept vectors of a truncation (Jacobi layout: the slot kept at position pos holds v_pos in wv[],
+// its stored value in vs[], and its column of the carry Y (rows jh + PJ e < ny) in yv[]): the
+// carry becomes Y - Y Z with Z[p][q] = <v_q | d_p>. WB [CM*2CM] and ZT [CM*CM] are LDS scratch;
+// Y holds the carry and is rewritten by the caller from yv[].
+template <int PJ, int RJ, int RU, int CM, int KY, class S>
+__device__ __forceinline__ void comp_store_rows(const cd (&wv)[RJ], const cx<S> (&vs)[RJ], cd (&yv)[RU], bool keep,
+                                                int pos, int jh, int c, int ny, int chi, cd* WB, cd* ZT,
+                                                cd (*Y)[KY]) {
+  lds_sync();
+  if (keep) {
+#pragma unroll
+    for (int e = 0; e < RJ; ++e) {
+      const int row = jh + PJ * e;
+      if (row < c) WB[pos * 2 * CM + row] = wv[e];
+    }
+#pragma unroll
+    for (int e = 0; e < RU; ++e) {
+      const int row = jh + PJ * e;
+      if (row < ny) Y[row][pos] = yv[e];
+    }
+  }
+  lds_sync();
+  for (int q = 0; q < chi; ++q) {
+    cd z = {0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < RJ; ++e) {
+      const int row = jh + PJ * e;
+      if (row < c) z = z + cmulc(WB[q * 2 * CM + row], up(vs[e]) - wv[e]);
+    }
+    z = gsum<PJ>(z);
+    if (keep && jh == 0) ZT[pos * CM + q] = z;
+  }
+  lds_sync();
+#pragma unroll
+  for (int e = 0; e < RU; ++e) {
+    const int row = jh + PJ * e;
+    cd cz = {0.0, 0.0};
+    if (keep && row < ny)
+      for (int p = 0; p < chi; ++p) cz = cfma(cz, Y[row][p], ZT[p * CM + pos]);
+    yv[e] = yv[e] - cz;
+  }
+  lds_sync();
+}
+
 // ------------------------------------------------------------------------------- one team
 template <class S, int CM, int TW>
 __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base) {
@@ -724,6 +872,13 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
   const int cap = I->cap < CM ? I->cap : CM;
   const int64_t k = bdp->k;
   cx<S>* arena = reinterpret_cast<cx<S>*>(P.arena) + I->site_off;
+  cd* edges = reinterpret_cast<cd*>(P.edge) + I->edge_off;
+  const int ew = I->ew;
+  // the complex-FP64 slot of an edge site, or null for a bulk site
+  auto eslot = [&](int i) -> cd* {
+    const int ei = edge_index(i, n, ew);
+    return ei >= 0 ? edges + (int64_t)ei * SLOT : nullptr;
+  };
   const uint64_t* W = P.marked + I->marked_off;
   const double tol2 = P.trunc_tol * P.trunc_tol;
   const double rank2 = P.rank_tol * P.rank_tol;
@@ -750,22 +905,26 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
         const bool diff = (j == M);
         const int xb = diff ? 0 : (int)(W[j] & 1);
         const double c0 = diff ? -1.0 : 1.0, c1 = diff ? 2.0 : -2.0;
-        const cx<S> a0 = arena[0], a1 = arena[D];
-        cx<S> o = czero<S>();
+        // the one site holds the norm: from and to its edge slot in FP64
+        const cd a0 = edges[0], a1 = edges[D];
+        cd o = {0.0, 0.0};
         if (tl < 2) {
-          const cx<S> pa = proj_apply<S>(a0, a1, tl, diff, xb);
-          const cx<S> as = sel(a0, a1, tl);
-          o = {(S)c0 * as.re + (S)c1 * pa.re, (S)c0 * as.im + (S)c1 * pa.im};
+          const cd pa = proj_apply<double>(a0, a1, tl, diff, xb);
+          const cd as = sel(a0, a1, tl);
+          o = {c0 * as.re + c1 * pa.re, c0 * as.im + c1 * pa.im};
         }
-        const double nn = gsum<PQ>(tl < 2 ? norm2(up(o)) : 0.0);
+        const double nn = gsum<PQ>(tl < 2 ? norm2(o) : 0.0);
         if (diff) {
           const double nr = sqrt(nn);
           drift = fmax(drift, fabs(nr - 1.0));
           if (!(nn > 0.0) || !isfinite(nn)) status |= GMPS_ST_NAN;
-          o = down<S>((1.0 / nr) * up(o));
+          o = (1.0 / nr) * o;
         }
         team_sync_global();
-        if (real && tl < 2) arena[tl * D] = o;
+        if (real && tl < 2) {
+          arena[tl * D] = store_cast<S>(o, rs_state, sr);
+          edges[tl * D] = o;
+        }
         team_sync_global();
       }
     }
@@ -794,7 +953,8 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
           const int Dl = first ? 1 : 2 * chl;
           const int Dr = last ? 1 : 2 * chr;
           cx<S>* slot = arena + (int64_t)i * SLOT;
-          apre.stage(L.u.q.W, tl, diff, xb, (S)(last ? c0 : 1.0), (S)(last ? c1 : 1.0));
+          cd* es = eslot(i);
+          apre.stage64(L.u.q.W, es, tl, diff, xb, last ? c0 : 1.0, last ? c1 : 1.0);
           if (i + 1 < n) apre.load(arena + (int64_t)(i + 1) * SLOT, tl, L.bond[i + 1], L.bond[i + 2]);
           lds_sync();
           // X = R_{i-1} * MPO(A_i): this slot's column, rows (a, s) = part + PQ*e
@@ -806,7 +966,7 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
             for (int e = 0; e < RQ; ++e) {
               const int row = qh + PQ * e;
               const int a = row >> 1, s = row & 1;
-              cx<S> acc = czero<S>();
+              cd acc = {0.0, 0.0};
               if (row < 2 * r && qc < Dr) {
                 // the last site sums both MPO blocks into its one column
 #pragma unroll
@@ -814,21 +974,24 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
                   if (last || bl == beta) {
 #pragma unroll
                     for (int ap = 0; ap < CM; ++ap)
-                      if (ap < chl) acc = cfma(acc, down<S>(L.u.q.R[a][bl * chl + ap]), L.u.q.W[bl][ap][s][bcol]);
+                      if (ap < chl) acc = cfma(acc, L.u.q.R[a][bl * chl + ap], L.u.q.W[bl][ap][s][bcol]);
                   }
                 }
               }
-              x[e] = up(acc);
+              x[e] = acc;
             }
           }
-          const double macs = (double)r * Dl * 2.0 * Dr;
-          if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+          f64 += 8.0 * (double)r * Dl * 2.0 * Dr;
           if (last) {
+            // the last site holds the norm: to its edge slot in FP64, to its site slot as stored
             if (real && qc == 0) {
 #pragma unroll
               for (int e = 0; e < RQ; ++e) {
                 const int row = qh + PQ * e;
-                if (row < 2 * r) slot[(row >> 1) * 2 * D + (row & 1) * D] = store_cast<S>(x[e], rs_state, sr);
+                if (row < 2 * r) {
+                  slot[(row >> 1) * 2 * D + (row & 1) * D] = store_cast<S>(x[e], rs_state, sr);
+                  es[(row >> 1) * 2 * D + (row & 1) * D] = x[e];
+                }
               }
             }
             if (tl == 0) {
@@ -851,11 +1014,17 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
             f64 += 8.0 * (2.0 * mm * cc * kk - (mm + cc) * kk * kk + 2.0 * kk * kk * kk / 3.0) +
                    8.0 * (2.0 * mm * kk * kk - 2.0 * kk * kk * kk / 3.0);
           }
+          cx<S> qs[RQ];  // Q as stored
+#pragma unroll
+          for (int e = 0; e < RQ; ++e) qs[e] = store_cast<S>(q[e], rs_state, sr);
           if (real && qc < kr) {
 #pragma unroll
             for (int e = 0; e < RQ; ++e) {
               const int row = qh + PQ * e;
-              if (row < m) slot[(row >> 1) * 2 * D + (row & 1) * D + qc] = store_cast<S>(q[e], rs_state, sr);
+              if (row < m) {
+                slot[(row >> 1) * 2 * D + (row & 1) * D + qc] = qs[e];
+                if (es) es[(row >> 1) * 2 * D + (row & 1) * D + qc] = q[e];
+              }
             }
           }
           if (qc < Dr) {
@@ -864,6 +1033,10 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
               const int row = qh + PQ * e;
               if (row < kr) L.u.q.R[row][qc] = x[e];
             }
+          }
+          if (kMixed && !es) {
+            comp_store_cols<PQ, RQ, KQ, D>(q, qs, qc, qh, kr, Dr, L.u.q.V, L.zbuf(), L.u.q.R);
+            f64 += 8.0 * ((double)kr * kr * m + (double)kr * kr * Dr);
           }
           if (tl == 0) L.rdim[i + 1] = kr;
           r = kr;
@@ -887,12 +1060,21 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
           const int c = 2 * chn;
           const int ncj = (ri + 1) & ~1;
           cx<S>* slot = arena + (int64_t)i * SLOT;
+          cd* es = eslot(i);
           double* wrec = warm ? warm + ((int64_t)j * n + i) * WREC : nullptr;
           const bool use_warm = wrec && wpre.r() == ncj;
           // the stored unitary is a product of exact rotations, so its unitarity drifts by
           // ~1e-16 per use; one Newton-Schulz step every 64 iterations keeps it below ~1e-13
           const bool renorm_warm = use_warm && ((k_done0 + (uint64_t)it) & 63ull) == 0ull;
-          qpre.stage(&L.u.s.Q[0][0][0], tl);
+          if (es) {
+            // an edge site (the first one holds the norm): from its complex-FP64 edge slot
+            for (int e = tl; e < KQ * 2 * KQ; e += TW) {
+              const int a = e / (2 * KQ), s = (e / KQ) & 1, b = e % KQ;
+              (&L.u.s.Q[0][0][0])[e] = (a < ri && b < rn) ? es[a * 2 * D + s * D + b] : cd{0.0, 0.0};
+            }
+          } else {
+            qpre.stage(&L.u.s.Q[0][0][0], tl);
+          }
           if (use_warm) wpre.stage(&L.u.s.W[0][0], tl);
           if (i - 1 >= 1) {
             qpre.load(arena + (int64_t)(i - 1) * SLOT, tl, L.rdim[i - 1], L.rdim[i]);
@@ -907,18 +1089,15 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
             const int row = jh + PJ * e;
             const int s = row >= chn ? 1 : 0;
             const int jj = row - s * chn;
-            cx<S> acc = czero<S>();
+            cd acc = {0.0, 0.0};
             if (jc < ri && row < c) {
 #pragma unroll
               for (int b = 0; b < KQ; ++b)
-                if (b < rn) acc = cfma(acc, L.u.s.Q[jc][s][b], down<S>(L.u.s.Y[b][jj]));
+                if (b < rn) acc = cfma(acc, L.u.s.Q[jc][s][b], L.u.s.Y[b][jj]);
             }
-            a[e] = conj(up(acc));
+            a[e] = conj(acc);
           }
-          {
-            const double macs = (double)ri * 2.0 * rn * chn;
-            if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
-          }
+          f64 += 8.0 * (double)ri * 2.0 * rn * chn;
           if (renorm_warm) {
             // one Newton-Schulz polar step W <- W (3I - W^H W) / 2 (error e -> O(e^2))
             cd* WG = &L.u.s.XU[0][0][0];  // KJ x KJ, row-major
@@ -1058,23 +1237,41 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
             }
             if (tl == 0) wrec[0] = (double)ncj;
           }
-          if (keep) {
-            const double rs = rsqrt_acc(sg);  // 1/sigma
-            if (real) {
+          const double rs = keep ? rsqrt_acc(sg) : 0.0;  // 1/sigma
+          cd wv[RJ];     // this slot's row of V^H
+          cx<S> vs[RJ];  // ... as stored
 #pragma unroll
-              for (int e = 0; e < RJ; ++e) {
-                const int row = jh + PJ * e;
-                if (row < c) {
-                  const int s = row >= chn ? 1 : 0;
-                  const int jp = row - s * chn;
-                  slot[pos * 2 * D + s * D + jp] = store_cast<S>(rs * conj(a[e]), rs_state, sr);
-                }
+          for (int e = 0; e < RJ; ++e) {
+            wv[e] = rs * conj(a[e]);
+            vs[e] = store_cast<S>(wv[e], rs_state, sr);
+          }
+          if (keep && real) {
+#pragma unroll
+            for (int e = 0; e < RJ; ++e) {
+              const int row = jh + PJ * e;
+              if (row < c) {
+                const int s = row >= chn ? 1 : 0;
+                const int jp = row - s * chn;
+                slot[pos * 2 * D + s * D + jp] = vs[e];
+                if (es) es[pos * 2 * D + s * D + jp] = wv[e];
               }
             }
+          }
+          cd yv[RU];  // this slot's column of the carry J Sigma
+#pragma unroll
+          for (int e = 0; e < RU; ++e) yv[e] = (sg * rs) * uu[e];
+          if (kMixed && !es) {
+            // the Jacobi exchange buffers are free: the kept rows and Z go there
+            comp_store_rows<PJ, RJ, RU, CM>(wv, vs, yv, keep, pos, jh, c, ri, chi_new,
+                                            reinterpret_cast<cd*>(&L.u.s.XA[0][0][0]),
+                                            reinterpret_cast<cd*>(&L.u.s.XU[0][0][0]), L.u.s.Y);
+            f64 += 8.0 * ((double)chi_new * chi_new * c + (double)chi_new * chi_new * ri);
+          }
+          if (keep) {
 #pragma unroll
             for (int e = 0; e < RU; ++e) {
               const int row = jh + PJ * e;
-              if (row < ri) L.u.s.Y[row][pos] = (sg * rs) * uu[e];
+              if (row < ri) L.u.s.Y[row][pos] = yv[e];
             }
           }
           if (tl == 0) L.bond[i] = chi_new;
@@ -1085,31 +1282,35 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
         {
           const int rn = L.rdim[1], chn = L.bond[1];
           cx<S>* slot = arena;
-          cx<S> acc = czero<S>();
+          cd acc = {0.0, 0.0};
           const bool act = tl < 2 * chn;
           const int s = tl >= chn ? 1 : 0;
           const int jj = tl - s * chn;
           if (act) {
 #pragma unroll
             for (int b = 0; b < KQ; ++b)
-              if (b < rn) acc = cfma(acc, slot[s * D + b], down<S>(L.u.s.Y[b][jj]));
+              if (b < rn) acc = cfma(acc, edges[s * D + b], L.u.s.Y[b][jj]);
           }
-          const double macs = 2.0 * rn * chn;
-          if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+          f64 += 8.0 * 2.0 * rn * chn;
           double nn = 0.0;
           if constexpr (TW <= 64) {
-            nn = tsum<TW>(act ? norm2(up(acc)) : 0.0);
+            nn = tsum<TW>(act ? norm2(acc) : 0.0);
           } else {
-            L.colv[tl] = act ? norm2(up(acc)) : 0.0;
+            L.colv[tl] = act ? norm2(acc) : 0.0;
             lds_sync();
             for (int o = 0; o < 2 * chn; ++o) nn += L.colv[o];
           }
           if (!isfinite(nn) || !(nn > 0.0)) status |= GMPS_ST_NAN;
           const double nr = sqrt(nn);
           if (diff) drift = fmax(drift, fabs(nr - 1.0));
-          const cx<S> out = store_cast<S>((diff ? 1.0 / nr : 1.0) * up(acc), rs_state, sr);
+          // site 0 now holds the norm: to its edge slot in FP64, to its site slot as stored
+          const cd outd = (diff ? 1.0 / nr : 1.0) * acc;
+          const cx<S> out = store_cast<S>(outd, rs_state, sr);
           lds_sync();
-          if (real && act) slot[s * D + jj] = out;
+          if (real && act) {
+            slot[s * D + jj] = out;
+            edges[s * D + jj] = outd;
+          }
           if (tl == 0) L.bond[0] = 1;
           team_sync_global();
         }
@@ -1177,6 +1378,13 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
   const int cap = I->cap < CM ? I->cap : CM;
   const int64_t k = bdp->k;
   cx<S>* arena = reinterpret_cast<cx<S>*>(P.arena) + I->site_off;
+  cd* edges = reinterpret_cast<cd*>(P.edge) + I->edge_off;
+  const int ew = I->ew;
+  // the complex-FP64 slot of an edge site, or null for a bulk site
+  auto eslot = [&](int i) -> cd* {
+    const int ei = edge_index(i, n, ew);
+    return ei >= 0 ? edges + (int64_t)ei * SLOT : nullptr;
+  };
   const uint64_t* W = P.marked + I->marked_off;
   const double tol2 = P.trunc_tol * P.trunc_tol;
   const double rank2 = P.rank_tol * P.rank_tol;
@@ -1203,22 +1411,26 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
         const bool diff = (j == M);
         const int xb = diff ? 0 : (int)(W[j] & 1);
         const double c0 = diff ? -1.0 : 1.0, c1 = diff ? 2.0 : -2.0;
-        const cx<S> a0 = arena[0], a1 = arena[D];
-        cx<S> o = czero<S>();
+        // the one site holds the norm: from and to its edge slot in FP64
+        const cd a0 = edges[0], a1 = edges[D];
+        cd o = {0.0, 0.0};
         if (tl < 2) {
-          const cx<S> pa = proj_apply<S>(a0, a1, tl, diff, xb);
-          const cx<S> as = sel(a0, a1, tl);
-          o = {(S)c0 * as.re + (S)c1 * pa.re, (S)c0 * as.im + (S)c1 * pa.im};
+          const cd pa = proj_apply<double>(a0, a1, tl, diff, xb);
+          const cd as = sel(a0, a1, tl);
+          o = {c0 * as.re + c1 * pa.re, c0 * as.im + c1 * pa.im};
         }
-        const double nn = gsum<PQ>(tl < 2 ? norm2(up(o)) : 0.0);
+        const double nn = gsum<PQ>(tl < 2 ? norm2(o) : 0.0);
         if (diff) {
           const double nr = sqrt(nn);
           drift = fmax(drift, fabs(nr - 1.0));
           if (!(nn > 0.0) || !isfinite(nn)) status |= GMPS_ST_NAN;
-          o = down<S>((1.0 / nr) * up(o));
+          o = (1.0 / nr) * o;
         }
         team_sync_global();
-        if (real && tl < 2) arena[tl * D] = o;
+        if (real && tl < 2) {
+          arena[tl * D] = store_cast<S>(o, rs_state, sr);
+          edges[tl * D] = o;
+        }
         team_sync_global();
       }
     }
@@ -1247,7 +1459,8 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
     static_assert(sizeof(L.u.q.W[1]) >= sizeof(X.ov), "second overlap buffer fits W[1]");
     static_assert(sizeof(L.u.q.R) >= sizeof(L.u.q.W[0]), "second staging buffer fits R");
     cd (*const ovb[2])[CM] = {X.ov, reinterpret_cast<cd (*)[CM]>(&L.u.q.W[1][0][0][0])};
-    cx<S> (*const stg[2])[CM][2][CM] = {L.u.q.W, reinterpret_cast<cx<S> (*)[CM][2][CM]>(&L.u.q.R[0][0])};
+    cx<S> (*const stg[2])[CM][2][CM] = {reinterpret_cast<cx<S> (*)[CM][2][CM]>(&L.u.q.W[0][0][0][0]),
+                                        reinterpret_cast<cx<S> (*)[CM][2][CM]>(&L.u.q.R[0][0])};
     const int nref = whole ? 2 : M + 1;
     for (int64_t it = 0; it < k; ++it) {
       for (int j = 0; j < nref; ++j) {
@@ -1269,6 +1482,7 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
             const int xb = diff ? 0 : (int)((xw >> (n - 1 - i)) & 1ull);
             const uint32_t tb = whole ? X.xbits[i] : (uint32_t)xb;
             cx<S> (*const A)[CM][2][CM] = stg[i & 1];
+            const cd* oes = eslot(i);
             opre.stage_a(A, tl, (S)1.0);
             if (i + 1 < n) opre.load(arena + (int64_t)(i + 1) * SLOT, tl, L.bond[i + 1], L.bond[i + 2]);
             lds_sync();
@@ -1281,7 +1495,9 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
                 const int xs = (int)((tb >> tt) & 1u);
                 cd acc = {0.0, 0.0};
                 for (int b = 0; b < chl; ++b) {
-                  const cd a0 = up(A[0][b][0][col]), a1 = up(A[0][b][1][col]);
+                  // an edge site from its complex-FP64 edge slot
+                  const cd a0 = oes ? oes[b * 2 * D + col] : up(A[0][b][0][col]);
+                  const cd a1 = oes ? oes[b * 2 * D + D + col] : up(A[0][b][1][col]);
                   const cd av = diff ? kInvSqrt2 * (a0 + a1) : (xs ? a1 : a0);
                   acc = cfma(acc, vin[tt][b], av);
                 }
@@ -1319,10 +1535,11 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
           const int Dl = first ? 1 : (sumv ? chl + T : 2 * chl);
           const int Dr = last ? 1 : (sumv ? chr + T : 2 * chr);
           cx<S>* slot = arena + (int64_t)i * SLOT;
+          cd* es = eslot(i);
           if (sumv) {
-            apre.stage_a(L.u.q.W, tl, (S)(last ? c0 : 1.0));
+            apre.stage_a64(L.u.q.W, es, tl, last ? c0 : 1.0);
           } else {
-            apre.stage(L.u.q.W, tl, diff, xb, (S)(last ? c0 : 1.0), (S)(last ? c1 : 1.0));
+            apre.stage64(L.u.q.W, es, tl, diff, xb, last ? c0 : 1.0, last ? c1 : 1.0);
           }
           if (i + 1 < n) apre.load(arena + (int64_t)(i + 1) * SLOT, tl, L.bond[i + 1], L.bond[i + 2]);
           lds_sync();
@@ -1335,7 +1552,7 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
             for (int e = 0; e < RQ; ++e) {
               const int row = qh + PQ * e;
               const int a = row >> 1, s = row & 1;
-              cx<S> acc = czero<S>();
+              cd acc = {0.0, 0.0};
               if (row < 2 * r && qc < Dr) {
                 // the last site sums both MPO blocks into its one column
 #pragma unroll
@@ -1343,11 +1560,11 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
                   if (last || bl == beta) {
 #pragma unroll
                     for (int ap = 0; ap < CM; ++ap)
-                      if (ap < chl) acc = cfma(acc, down<S>(L.u.q.R[a][bl * chl + ap]), L.u.q.W[bl][ap][s][bcol]);
+                      if (ap < chl) acc = cfma(acc, L.u.q.R[a][bl * chl + ap], L.u.q.W[bl][ap][s][bcol]);
                   }
                 }
               }
-              x[e] = up(acc);
+              x[e] = acc;
             }
           } else {
             // columns < chr (or the last site's one column): R_A A_i in the storage
@@ -1363,11 +1580,11 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
               if (row < 2 * r && qc < Dr) {
                 if (acol) {
                   const int bcol = last ? 0 : qc;
-                  cx<S> acc = czero<S>();
+                  cd acc = {0.0, 0.0};
 #pragma unroll
                   for (int ap = 0; ap < CM; ++ap)
-                    if (ap < chl) acc = cfma(acc, down<S>(L.u.q.R[a][ap]), L.u.q.W[0][ap][s][bcol]);
-                  xv = up(acc);
+                    if (ap < chl) acc = cfma(acc, L.u.q.R[a][ap], L.u.q.W[0][ap][s][bcol]);
+                  xv = acc;
                   if (last) {
                     for (int t = 0; t < T; ++t) {
                       const double es = diff ? kInvSqrt2 : ((int)((tb >> t) & 1u) == s ? 1.0 : 0.0);
@@ -1382,19 +1599,17 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
               x[e] = xv;
             }
           }
-          if (sumv) {
-            const double macs = (double)r * chl * 2.0 * (last ? 1 : chr);
-            if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
-          } else {
-            const double macs = (double)r * Dl * 2.0 * Dr;
-            if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
-          }
+          f64 += 8.0 * (sumv ? (double)r * chl * 2.0 * (last ? 1 : chr) : (double)r * Dl * 2.0 * Dr);
           if (last) {
+            // the last site holds the norm: to its edge slot in FP64, to its site slot as stored
             if (real && qc == 0) {
 #pragma unroll
               for (int e = 0; e < RQ; ++e) {
                 const int row = qh + PQ * e;
-                if (row < 2 * r) slot[(row >> 1) * 2 * D + (row & 1) * D] = store_cast<S>(x[e], rs_state, sr);
+                if (row < 2 * r) {
+                  slot[(row >> 1) * 2 * D + (row & 1) * D] = store_cast<S>(x[e], rs_state, sr);
+                  es[(row >> 1) * 2 * D + (row & 1) * D] = x[e];
+                }
               }
             }
             if (tl == 0) {
@@ -1417,11 +1632,17 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
             f64 += 8.0 * (2.0 * mm * cc * kk - (mm + cc) * kk * kk + 2.0 * kk * kk * kk / 3.0) +
                    8.0 * (2.0 * mm * kk * kk - 2.0 * kk * kk * kk / 3.0);
           }
+          cx<S> qs[RQ];  // Q as stored
+#pragma unroll
+          for (int e = 0; e < RQ; ++e) qs[e] = store_cast<S>(q[e], rs_state, sr);
           if (real && qc < kr) {
 #pragma unroll
             for (int e = 0; e < RQ; ++e) {
               const int row = qh + PQ * e;
-              if (row < m) slot[(row >> 1) * 2 * D + (row & 1) * D + qc] = store_cast<S>(q[e], rs_state, sr);
+              if (row < m) {
+                slot[(row >> 1) * 2 * D + (row & 1) * D + qc] = qs[e];
+                if (es) es[(row >> 1) * 2 * D + (row & 1) * D + qc] = q[e];
+              }
             }
           }
           if (qc < Dr) {
@@ -1430,6 +1651,10 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
               const int row = qh + PQ * e;
               if (row < kr) L.u.q.R[row][qc] = x[e];
             }
+          }
+          if (kMixed && !es) {
+            comp_store_cols<PQ, RQ, KQ, D>(q, qs, qc, qh, kr, Dr, L.u.q.V, L.zbuf(), L.u.q.R);
+            f64 += 8.0 * ((double)kr * kr * m + (double)kr * kr * Dr);
           }
           if (tl == 0) L.rdim[i + 1] = kr;
           r = kr;
@@ -1453,12 +1678,21 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
           const int c = 2 * chn;
           const int ncj = (ri + 1) & ~1;
           cx<S>* slot = arena + (int64_t)i * SLOT;
+          cd* es = eslot(i);
           double* wrec = warm ? warm + ((int64_t)j * n + i) * WREC : nullptr;
           const bool use_warm = wrec && wpre.r() == ncj;
           // the stored unitary is a product of exact rotations, so its unitarity drifts by
           // ~1e-16 per use; one Newton-Schulz step every 64 iterations keeps it below ~1e-13
           const bool renorm_warm = use_warm && ((k_done0 + (uint64_t)it) & 63ull) == 0ull;
-          qpre.stage(&L.u.s.Q[0][0][0], tl);
+          if (es) {
+            // an edge site (the first one holds the norm): from its complex-FP64 edge slot
+            for (int e = tl; e < KQ * 2 * KQ; e += TW) {
+              const int a = e / (2 * KQ), s = (e / KQ) & 1, b = e % KQ;
+              (&L.u.s.Q[0][0][0])[e] = (a < ri && b < rn) ? es[a * 2 * D + s * D + b] : cd{0.0, 0.0};
+            }
+          } else {
+            qpre.stage(&L.u.s.Q[0][0][0], tl);
+          }
           if (use_warm) wpre.stage(&L.u.s.W[0][0], tl);
           if (i - 1 >= 1) {
             qpre.load(arena + (int64_t)(i - 1) * SLOT, tl, L.rdim[i - 1], L.rdim[i]);
@@ -1473,18 +1707,15 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
             const int row = jh + PJ * e;
             const int s = row >= chn ? 1 : 0;
             const int jj = row - s * chn;
-            cx<S> acc = czero<S>();
+            cd acc = {0.0, 0.0};
             if (jc < ri && row < c) {
 #pragma unroll
               for (int b = 0; b < KQ; ++b)
-                if (b < rn) acc = cfma(acc, L.u.s.Q[jc][s][b], down<S>(L.u.s.Y[b][jj]));
+                if (b < rn) acc = cfma(acc, L.u.s.Q[jc][s][b], L.u.s.Y[b][jj]);
             }
-            a[e] = conj(up(acc));
+            a[e] = conj(acc);
           }
-          {
-            const double macs = (double)ri * 2.0 * rn * chn;
-            if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
-          }
+          f64 += 8.0 * (double)ri * 2.0 * rn * chn;
           if (renorm_warm) {
             // one Newton-Schulz polar step W <- W (3I - W^H W) / 2 (error e -> O(e^2))
             cd* WG = &L.u.s.XU[0][0][0];  // KJ x KJ, row-major
@@ -1624,23 +1855,41 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
             }
             if (tl == 0) wrec[0] = (double)ncj;
           }
-          if (keep) {
-            const double rs = rsqrt_acc(sg);  // 1/sigma
-            if (real) {
+          const double rs = keep ? rsqrt_acc(sg) : 0.0;  // 1/sigma
+          cd wv[RJ];     // this slot's row of V^H
+          cx<S> vs[RJ];  // ... as stored
 #pragma unroll
-              for (int e = 0; e < RJ; ++e) {
-                const int row = jh + PJ * e;
-                if (row < c) {
-                  const int s = row >= chn ? 1 : 0;
-                  const int jp = row - s * chn;
-                  slot[pos * 2 * D + s * D + jp] = store_cast<S>(rs * conj(a[e]), rs_state, sr);
-                }
+          for (int e = 0; e < RJ; ++e) {
+            wv[e] = rs * conj(a[e]);
+            vs[e] = store_cast<S>(wv[e], rs_state, sr);
+          }
+          if (keep && real) {
+#pragma unroll
+            for (int e = 0; e < RJ; ++e) {
+              const int row = jh + PJ * e;
+              if (row < c) {
+                const int s = row >= chn ? 1 : 0;
+                const int jp = row - s * chn;
+                slot[pos * 2 * D + s * D + jp] = vs[e];
+                if (es) es[pos * 2 * D + s * D + jp] = wv[e];
               }
             }
+          }
+          cd yv[RU];  // this slot's column of the carry J Sigma
+#pragma unroll
+          for (int e = 0; e < RU; ++e) yv[e] = (sg * rs) * uu[e];
+          if (kMixed && !es) {
+            // the Jacobi exchange buffers are free: the kept rows and Z go there
+            comp_store_rows<PJ, RJ, RU, CM>(wv, vs, yv, keep, pos, jh, c, ri, chi_new,
+                                            reinterpret_cast<cd*>(&L.u.s.XA[0][0][0]),
+                                            reinterpret_cast<cd*>(&L.u.s.XU[0][0][0]), L.u.s.Y);
+            f64 += 8.0 * ((double)chi_new * chi_new * c + (double)chi_new * chi_new * ri);
+          }
+          if (keep) {
 #pragma unroll
             for (int e = 0; e < RU; ++e) {
               const int row = jh + PJ * e;
-              if (row < ri) L.u.s.Y[row][pos] = (sg * rs) * uu[e];
+              if (row < ri) L.u.s.Y[row][pos] = yv[e];
             }
           }
           if (tl == 0) L.bond[i] = chi_new;
@@ -1651,31 +1900,35 @@ __device__ void run_team_pc(const IterParams& P, const Bundle* bdp, char* lds_ba
         {
           const int rn = L.rdim[1], chn = L.bond[1];
           cx<S>* slot = arena;
-          cx<S> acc = czero<S>();
+          cd acc = {0.0, 0.0};
           const bool act = tl < 2 * chn;
           const int s = tl >= chn ? 1 : 0;
           const int jj = tl - s * chn;
           if (act) {
 #pragma unroll
             for (int b = 0; b < KQ; ++b)
-              if (b < rn) acc = cfma(acc, slot[s * D + b], down<S>(L.u.s.Y[b][jj]));
+              if (b < rn) acc = cfma(acc, edges[s * D + b], L.u.s.Y[b][jj]);
           }
-          const double macs = 2.0 * rn * chn;
-          if (kMixed) f32 += 8.0 * macs; else f64 += 8.0 * macs;
+          f64 += 8.0 * 2.0 * rn * chn;
           double nn = 0.0;
           if constexpr (TW <= 64) {
-            nn = tsum<TW>(act ? norm2(up(acc)) : 0.0);
+            nn = tsum<TW>(act ? norm2(acc) : 0.0);
           } else {
-            L.colv[tl] = act ? norm2(up(acc)) : 0.0;
+            L.colv[tl] = act ? norm2(acc) : 0.0;
             lds_sync();
             for (int o = 0; o < 2 * chn; ++o) nn += L.colv[o];
           }
           if (!isfinite(nn) || !(nn > 0.0)) status |= GMPS_ST_NAN;
           const double nr = sqrt(nn);
           if (diff) drift = fmax(drift, fabs(nr - 1.0));
-          const cx<S> out = store_cast<S>((diff ? 1.0 / nr : 1.0) * up(acc), rs_state, sr);
+          // site 0 now holds the norm: to its edge slot in FP64, to its site slot as stored
+          const cd outd = (diff ? 1.0 / nr : 1.0) * acc;
+          const cx<S> out = store_cast<S>(outd, rs_state, sr);
           lds_sync();
-          if (real && act) slot[s * D + jj] = out;
+          if (real && act) {
+            slot[s * D + jj] = out;
+            edges[s * D + jj] = outd;
+          }
           if (tl == 0) L.bond[0] = 1;
           team_sync_global();
         }

@@ -24,10 +24,8 @@ static_assert(sizeof(PipeLds<double, 3>) * 2 <= 160 * 1024 - 256, "LDS");
 static_assert(sizeof(PipeLds<double, 5>) <= 160 * 1024 - 256, "LDS");
 static_assert(sizeof(PipeLds<double, 8>) <= 160 * 1024 - 256, "LDS");
 
-// the classes with a pipelined kernel (teams within one wave: bond caps 2, 3, 5 and 8). The
-// bond-2 class keeps the sequential kernel on the mixed path: its M = 1 instances need the
-// warm-started Jacobi (without it they drift, |dP| up to 5e-6 on the 4096-instance workload).
-static bool pipe_class(int w, bool mixed) { return (w >= 1 && w <= 3) || (w == 0 && !mixed); }
+// the classes with a pipelined kernel (teams within one wave: bond caps 2, 3, 5 and 8)
+static bool pipe_class(int w, bool) { return w >= 0 && w <= 3; }
 
 template <int W>
 static size_t pipe_lds(bool mixed) {

@@ -29,7 +29,7 @@ BOND_STRIDE = 64
 KERNELS = {"auto": 0, "group": 1, "team": 2}
 
 EXPORTED = ("gmps_workspace_bytes", "gmps_create", "mps_init_uniform", "grover_iterate", "marked_prob",
-            "sample_shots", "gmps_amplitudes", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
+            "sample_shots", "gmps_amplitudes", "gmps_overlap_uniform", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
             "gmps_strerror", "gsv_workspace_bytes", "gsv_create", "gsv_init_uniform", "gsv_iterate",
             "gsv_marked_prob", "gsv_amplitudes", "gsv_last_iterate_ms", "gsv_destroy")
 
@@ -82,6 +82,8 @@ def load(path: Optional[str] = None):
     lib.sample_shots.argtypes = [P, ctypes.POINTER(i64), i32, u64, ctypes.POINTER(u64), ctypes.POINTER(i64)]
     lib.gmps_amplitudes.restype = ctypes.c_int
     lib.gmps_amplitudes.argtypes = [P, i32, ctypes.POINTER(u64), i64, ctypes.POINTER(dbl)]
+    lib.gmps_overlap_uniform.restype = ctypes.c_int
+    lib.gmps_overlap_uniform.argtypes = [P, i32, ctypes.POINTER(dbl)]
     lib.gmps_diagnostics.restype = ctypes.c_int
     lib.gmps_diagnostics.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(i32),
                                      ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl)]
@@ -158,7 +160,7 @@ class Batch:
 
     def __init__(self, instances: Sequence, precision: str = "fp64", trunc_tol: float = 0.0,
                  max_sweeps: int = 0, waves_per_cu: int = 0, use_graph: bool = True, stream=None,
-                 device=None, stochastic_rounding: bool = True, jacobi_warm: Optional[bool] = None,
+                 device=None, stochastic_rounding: Optional[bool] = None, jacobi_warm: Optional[bool] = None,
                  kernel: str = "auto", precontract: bool = False, pipeline: bool = True):
         import torch
         if not torch.cuda.is_available():
@@ -181,7 +183,7 @@ class Batch:
         opt.max_sweeps = int(max_sweeps)
         opt.waves_per_cu = int(waves_per_cu)
         opt.use_graph = 1 if use_graph else -1
-        opt.round_mode = 1 if stochastic_rounding else -1
+        opt.round_mode = 0 if stochastic_rounding is None else (1 if stochastic_rounding else -1)
         opt.jacobi_warm = 0 if jacobi_warm is None else (1 if jacobi_warm else -1)
         opt.kernel = KERNELS[kernel]
         opt.precontract = 1 if precontract else -1
@@ -243,6 +245,13 @@ class Batch:
         self._check(self.lib.gmps_amplitudes(self.handle, int(inst), _ptr(xs, ctypes.c_uint64), len(xs),
                                              _ptr(out, ctypes.c_double)), "gmps_amplitudes")
         return out[0::2] + 1j * out[1::2]
+
+    def overlap_uniform(self, inst: int) -> complex:
+        """<s|psi> / ||psi|| for instance inst (|s> = |+>^n)."""
+        out = np.zeros(2, dtype=np.float64)
+        self._check(self.lib.gmps_overlap_uniform(self.handle, int(inst), _ptr(out, ctypes.c_double)),
+                    "gmps_overlap_uniform")
+        return complex(out[0], out[1])
 
     def diagnostics(self) -> dict:
         B = self.B
