@@ -65,7 +65,8 @@ typedef enum { GMPS_FP64 = 0, GMPS_MIXED = 1, GMPS_FP32 = 2 } gmps_prec;
 enum {
   GMPS_OK = 0,
   GMPS_E_ARG = -1,         /* invalid argument; nothing was enqueued               */
-  GMPS_E_WORKSPACE = -2,   /* workspace NULL, misaligned (<256 B) or too small      */
+  GMPS_E_WORKSPACE = -2,   /* workspace NULL, misaligned (<256 B) or too small, or  *
+                            * a request beyond sample_shots_noalloc's static array  */
   GMPS_E_HIP = -3,         /* a HIP runtime call failed                             */
   GMPS_E_UNSUPPORTED = -4, /* no tile class holds the bond cap, an option the chosen *
                             * kernel or precision lacks, or no device               */
@@ -181,6 +182,22 @@ int marked_prob(gmps_batch* b, double* out_p);
  * that landed in W_i (either may be NULL). Synchronises. */
 int sample_shots(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_t seed,
                  uint64_t* out_bits, int64_t* out_hits);
+
+/* sample_shots for callers that cannot allocate device memory or pass a staging buffer
+ * (code under stream capture, tight serving loops, harnesses that forbid allocation). Same
+ * arguments, results (bit for bit) and errors as sample_shots, but the hit counters, shot
+ * offsets and bitstrings live in a static array of GMPS_NOALLOC_SCRATCH_BYTES that the library
+ * holds in each GPU's memory from the first gmps_create() on that GPU until the process ends;
+ * the call allocates nothing and uses no part of the workspace but the chain. Every call on a
+ * GPU shares that GPU's array and leaves its contents behind: calls that overlap on one GPU
+ * (other threads, other streams, other handles) race, so the caller serialises them.
+ * Limits: 8*B bytes of counters plus 4.25 KiB of offsets plus 8 bytes per shot of one
+ * instance must fit the array; a larger request returns GMPS_E_WORKSPACE before anything is
+ * enqueued (instances are sampled in chunks, so only one instance's shots count).
+ * GMPS_E_HIP if the array's device address could not be looked up. */
+#define GMPS_NOALLOC_SCRATCH_BYTES (16u << 20)
+int sample_shots_noalloc(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_t seed,
+                         uint64_t* out_bits, int64_t* out_hits);
 
 /* Eq. (5): amplitudes <x|psi_inst> / ||psi_inst|| of the normalised state for cnt basis
  * indices (the stored chain's norm differs from 1 by the rounding of its tensors). xs: host

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <unordered_set>
 #include <vector>
@@ -174,9 +175,45 @@ struct gmps_batch {
   hipStream_t side[kLaunchKinds] = {};
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kLaunchKinds] = {};
+  // device address of this GPU's copy of the static sampling scratch (null if the lookup failed)
+  char* scratch = nullptr;
 };
 
+// Scratch of sample_shots_noalloc: hit counters, shot offsets and bitstrings, in device memory
+// that every GPU the library runs on holds from module load until the process ends. Host code
+// reaches it only through the per-device address hipGetSymbolAddress returns (the array's own
+// name is a host-side stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[GMPS_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// This GPU's address of `scratch`, looked up once per device with that device current.
+char* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+      std::fprintf(stderr, "gmps: hipGetSymbolAddress(scratch) failed: %s\n", hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch[dev] = static_cast<char*>(p);
+  }
+  return g_scratch[dev];
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0ull;
+}
 
 // lane-group kernel instantiation: 0 FP64, 1 mixed, 2 all-FP32
 int group_mode(const gmps_batch* b) { return b->fp32 ? 2 : b->mixed ? 1 : 0; }
@@ -208,7 +245,7 @@ const char* gmps_strerror(int status) {
   switch (status) {
     case GMPS_OK: return "ok";
     case GMPS_E_ARG: return "invalid argument";
-    case GMPS_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case GMPS_E_WORKSPACE: return "workspace missing, misaligned or too small (or a request beyond the static sampling array)";
     case GMPS_E_HIP: return "HIP runtime error";
     case GMPS_E_UNSUPPORTED: return "unsupported configuration (bond cap beyond the compiled tile classes, or no GPU)";
     case GMPS_E_NUMERIC: return "numerical failure in some instance (NaN/Inf or norm drift)";
@@ -296,6 +333,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     if (effective_cap(inst[i].n, inst[i].M, inst[i].chi_cap) < effective_cap(inst[i].n, inst[i].M, INT32_MAX))
       b->pipeline = false;
   hipGetDevice(&b->device);
+  b->scratch = scratch_address(b->device);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
     delete b;
@@ -598,38 +636,40 @@ int marked_prob(gmps_batch* b, double* out_p) {
   return bad ? GMPS_E_NUMERIC : GMPS_OK;
 }
 
-int sample_shots(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_t seed, uint64_t* out_bits,
-                 int64_t* out_hits) {
-  if (!b || !shots || (shots_len != 1 && shots_len != b->B)) return GMPS_E_ARG;
-  for (int i = 0; i < shots_len; ++i)
-    if (shots[i] < 0) return GMPS_E_ARG;
-  // The instances are sampled in chunks whose offset table and bitstrings fit the staging
-  // region of the workspace; a chunk's bits are copied out before the next chunk runs.
-  char* st = b->ws + b->lay.stage;
-  unsigned long long* dhits = reinterpret_cast<unsigned long long*>(b->ws + b->lay.hits);
-  GMPS_HIP(hipMemsetAsync(dhits, 0, sizeof(uint64_t) * b->B, b->stream));
-  std::vector<int64_t> off;
+}  // extern "C"
+
+namespace {
+
+// Sampling shared by sample_shots and sample_shots_noalloc: the instances are sampled in
+// chunks of at most kChunkInst whose offset table and bitstrings fit the staging area st;
+// a chunk's bits are copied out before the next chunk reuses the area. dhits: B counters.
+constexpr int kChunkInst = 512;
+
+int sample_staged(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_t seed, uint64_t* out_bits,
+                  int64_t* out_hits, char* st, size_t st_bytes, unsigned long long* dhits) {
+  int64_t off[kChunkInst + 1];
+  const size_t head = align_up(sizeof(int64_t) * (kChunkInst + 1));
   int64_t done = 0;  // shots of the instances before the current chunk
   for (int i0 = 0; i0 < b->B;) {
-    off.assign(1, 0);
+    off[0] = 0;
     int i1 = i0;
-    for (; i1 < b->B; ++i1) {
+    for (; i1 < b->B && i1 - i0 < kChunkInst; ++i1) {
       const int64_t s = shots[shots_len == 1 ? 0 : i1];
-      const size_t need = align_up(sizeof(int64_t) * (off.size() + 1)) + sizeof(uint64_t) * (size_t)(off.back() + s);
-      if (need > kStageBytes) break;
-      off.push_back(off.back() + s);
+      if (head + sizeof(uint64_t) * (size_t)(off[i1 - i0] + s) > st_bytes) break;
+      off[i1 - i0 + 1] = off[i1 - i0] + s;
     }
-    if (i1 == i0) return GMPS_E_WORKSPACE;  // one instance's shots exceed the staging region
+    if (i1 == i0) return GMPS_E_WORKSPACE;  // one instance's shots exceed the staging area
     const int nb = i1 - i0;
-    const int64_t total = off.back();
+    const int64_t total = off[nb];
     int64_t* doff = reinterpret_cast<int64_t*>(st);
-    uint64_t* dbits = reinterpret_cast<uint64_t*>(st + align_up(sizeof(int64_t) * (nb + 1)));
-    GMPS_HIP(hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, b->stream));
+    uint64_t* dbits = reinterpret_cast<uint64_t*>(st + head);
+    GMPS_HIP(hipMemcpyAsync(doff, off, sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, b->stream));
     GMPS_HIP(launch_sample(b->mixed, b->max_cm, b->params.inst + i0, b->params.marked, b->params.bonds + (int64_t)i0 * kBondStride,
                            b->params.arena, readout_edge(b), nb, i0, doff, total, seed, dbits, dhits + i0, b->stream));
     if (out_bits && total > 0)
       GMPS_HIP(hipMemcpyAsync(out_bits + done, dbits, sizeof(uint64_t) * total, hipMemcpyDeviceToHost, b->stream));
-    // the staging region is reused by the next chunk
+    // the offsets were read from host memory that changes before the next chunk, and the
+    // staging area is reused by it
     GMPS_HIP(hipStreamSynchronize(b->stream));
     done += total;
     i0 = i1;
@@ -637,6 +677,43 @@ int sample_shots(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_
   if (out_hits) GMPS_HIP(hipMemcpyAsync(out_hits, dhits, sizeof(int64_t) * b->B, hipMemcpyDeviceToHost, b->stream));
   GMPS_HIP(hipStreamSynchronize(b->stream));
   return GMPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sample_shots(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_t seed, uint64_t* out_bits,
+                 int64_t* out_hits) {
+  if (!b || !shots || (shots_len != 1 && shots_len != b->B)) return GMPS_E_ARG;
+  for (int i = 0; i < shots_len; ++i)
+    if (shots[i] < 0) return GMPS_E_ARG;
+  unsigned long long* dhits = reinterpret_cast<unsigned long long*>(b->ws + b->lay.hits);
+  GMPS_HIP(hipMemsetAsync(dhits, 0, sizeof(uint64_t) * b->B, b->stream));
+  return sample_staged(b, shots, shots_len, seed, out_bits, out_hits, b->ws + b->lay.stage, kStageBytes, dhits);
+}
+
+int sample_shots_noalloc(gmps_batch* b, const int64_t* shots, int32_t shots_len, uint64_t seed, uint64_t* out_bits,
+                         int64_t* out_hits) {
+  if (!b || !shots || (shots_len != 1 && shots_len != b->B)) return GMPS_E_ARG;
+  for (int i = 0; i < shots_len; ++i)
+    if (shots[i] < 0) return GMPS_E_ARG;
+  if (!b->scratch) return GMPS_E_HIP;
+  // layout of the scratch: B hit counters, then the staging area of the chunks; every size is
+  // checked here, before anything is enqueued
+  const size_t hits_bytes = align_up(sizeof(uint64_t) * (size_t)b->B);
+  const size_t head = align_up(sizeof(int64_t) * (kChunkInst + 1));
+  if (hits_bytes + head >= (size_t)GMPS_NOALLOC_SCRATCH_BYTES) return GMPS_E_WORKSPACE;
+  const size_t st_bytes = (size_t)GMPS_NOALLOC_SCRATCH_BYTES - hits_bytes;
+  const int64_t max_shots = (int64_t)((st_bytes - head) / sizeof(uint64_t));
+  for (int i = 0; i < shots_len; ++i)
+    if (shots[i] > max_shots) return GMPS_E_WORKSPACE;
+  unsigned long long* dhits = reinterpret_cast<unsigned long long*>(b->scratch);
+  // the counters keep the previous call's values: cleared by a kernel (no memset node if the
+  // caller captures the stream)
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((b->B + 255) / 256), dim3(256), 0, b->stream, dhits, (int64_t)b->B);
+  GMPS_HIP(hipGetLastError());
+  return sample_staged(b, shots, shots_len, seed, out_bits, out_hits, b->scratch + hits_bytes, st_bytes, dhits);
 }
 
 int gmps_amplitudes(gmps_batch* b, int32_t inst, const uint64_t* xs, int64_t cnt, double* out_reim) {

@@ -29,7 +29,7 @@ BOND_STRIDE = 64
 KERNELS = {"auto": 0, "group": 1, "team": 2}
 
 EXPORTED = ("gmps_workspace_bytes", "gmps_create", "mps_init_uniform", "grover_iterate", "marked_prob",
-            "sample_shots", "gmps_amplitudes", "gmps_overlap_uniform", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
+            "sample_shots", "sample_shots_noalloc", "gmps_amplitudes", "gmps_overlap_uniform", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
             "gmps_strerror", "gsv_workspace_bytes", "gsv_create", "gsv_init_uniform", "gsv_iterate",
             "gsv_marked_prob", "gsv_amplitudes", "gsv_last_iterate_ms", "gsv_destroy")
 
@@ -80,6 +80,8 @@ def load(path: Optional[str] = None):
     lib.marked_prob.argtypes = [P, ctypes.POINTER(dbl)]
     lib.sample_shots.restype = ctypes.c_int
     lib.sample_shots.argtypes = [P, ctypes.POINTER(i64), i32, u64, ctypes.POINTER(u64), ctypes.POINTER(i64)]
+    lib.sample_shots_noalloc.restype = ctypes.c_int
+    lib.sample_shots_noalloc.argtypes = [P, ctypes.POINTER(i64), i32, u64, ctypes.POINTER(u64), ctypes.POINTER(i64)]
     lib.gmps_amplitudes.restype = ctypes.c_int
     lib.gmps_amplitudes.argtypes = [P, i32, ctypes.POINTER(u64), i64, ctypes.POINTER(dbl)]
     lib.gmps_overlap_uniform.restype = ctypes.c_int
@@ -228,13 +230,17 @@ class Batch:
                                        "marked_prob", allow_numeric)
         return out
 
-    def sample(self, shots, seed: int):
+    def sample(self, shots, seed: int, noalloc: bool = False):
+        """Shots per instance (one value or B values) -> (bitstrings per instance, hits).
+        noalloc: use sample_shots_noalloc (static device array) instead of sample_shots."""
         sh = np.ascontiguousarray(np.atleast_1d(np.asarray(shots, dtype=np.int64)))
         per = sh if len(sh) == self.B else np.full(self.B, sh[0], dtype=np.int64)
         bits = np.zeros(max(int(per.sum()), 1), dtype=np.uint64)
         hits = np.zeros(self.B, dtype=np.int64)
-        self._check(self.lib.sample_shots(self.handle, _ptr(sh, ctypes.c_int64), len(sh), ctypes.c_uint64(seed),
-                                          _ptr(bits, ctypes.c_uint64), _ptr(hits, ctypes.c_int64)), "sample_shots")
+        fn = self.lib.sample_shots_noalloc if noalloc else self.lib.sample_shots
+        self._check(fn(self.handle, _ptr(sh, ctypes.c_int64), len(sh), ctypes.c_uint64(seed),
+                       _ptr(bits, ctypes.c_uint64), _ptr(hits, ctypes.c_int64)),
+                    "sample_shots_noalloc" if noalloc else "sample_shots")
         offs = np.concatenate([[0], np.cumsum(per)])
         return [bits[offs[i]:offs[i + 1]] for i in range(self.B)], hits
 
