@@ -6,18 +6,19 @@ launch), read out (marked_prob) and sampled (sample_shots). value = sum_i k_i / 
 The accuracy gate requires |P_i - sin^2((2k_i+1) theta_i)| <= 1e-6 for every instance.
 
     python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--workload c4|c2|c3] [--kernel auto|team|group]
-                    [--c5-k 48] [--sv-k 500] [--no-plain] [--no-cpu] [--no-fp64-batch]
-                    [--no-sequential] [--no-precontract] [--no-fp32] [--fp32-c4]
+                    [--budget 330] [--c5-k 48] [--sv-k 500] [--no-plain] [--no-cpu] [--no-fp64-batch]
+                    [--sequential] [--no-precontract] [--no-fp32] [--fp32-c4] [--no-small]
 
-Besides the headline line, the default run adds legs on the same hardware: the workload
-through the FP64 path, with sequential sweeps and with pre-contracted reflections; a prefix of
-the n=40, M=16 workload; the dense statevector backend; the all-FP32 precision study (M=1,
-n=12..28); B=1 FP64 handles; and the CPU oracle. --fp32-c4 also times the whole workload on
-the lane-group kernel in FP32, mixed and FP64.
+Besides the headline line, the default run adds legs on the same hardware, in priority order
+while the time budget lasts: the single-instance cases (n=10 and n=20, FP64, median of 5),
+the workload through the FP64 path and with pre-contracted reflections, the n=29 precision
+study (FP64 vs mixed, P logged every 1000 iterations), per-instance FP64 handles, the dense
+statevector backend, the all-FP32 precision study and a prefix of the n=40, M=16 workload.
+The CPU oracle runs first, before the GPU is touched.
 
-Prints one JSON line. roofline: the iterate kernel's algorithmic flops per launch (FP32
-flops weighted by the FP64/FP32 peak ratio) over its HIP-event duration, against the FP64
-vector peak. cpu_baseline: the CPU oracle timed on a bounded sample.
+Prints one JSON line. roofline: algorithmic flops of the iterate launch from the LAPACK-style
+model below, over the launch's HIP-event duration, against the FP64 vector peak (every
+arithmetic step of the path is FP64). cpu_baseline: the CPU oracle on all usable host cores.
 """
 from __future__ import annotations
 
@@ -26,6 +27,7 @@ import hashlib
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -40,11 +42,11 @@ FP64_VECTOR_PEAK = 78.6e12    # MI355X published FP64 vector rate, FLOP/s
 FP32_VECTOR_PEAK = 157.3e12   # MI355X published FP32 vector rate, FLOP/s
 HBM_PEAK = 8.0e12             # MI355X published HBM3E bandwidth, bytes/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grover_kernel.json")
-# the iterate kernel each --kernel choice runs (the library's choice is the team kernel)
 # the launch's longest class kernel on the 4096-instance workload (bond cap 5: the pipelined
 # sweeps by default); the roofline's flops, bytes and time cover every class kernel of the launch
 KERNEL_NAME = {"auto": "grover_pipe_kernel", "team": "grover_pipe_kernel", "group": "grover_group_kernel"}
 CSRC = os.path.join(ROOT, "paper_2601_03832_amd", "csrc")
+MAX_WORKERS = 16  # CPU share of one GPU on the benchmark machines
 
 
 def kernel_hash() -> str:
@@ -60,6 +62,66 @@ def kernel_hash() -> str:
 def exact_p(n: int, M: int, k: int) -> float:
     """Accuracy gate: sin^2((2k+1) asin(sqrt(M/2^n))), the success probability of Eq. (6)."""
     return math.sin((2 * k + 1) * math.asin(math.sqrt(M / float(2 ** n)))) ** 2
+
+
+# ------------------------------------------------------------------ algorithmic flop model
+# One reflection (an n-controlled Z as a bond-2 MPO, then recompression) on a chain whose bond
+# profile is chi[0..n]: LAPACK Working Note 41 counts, x4 for complex arithmetic.
+#  * QR sweep, site i = 0..n-2: X = R A_i with R (r x D_i) and the MPO-doubled site
+#    (D_i x 2 x D_{i+1}, D_l = 2 chi_l inside the chain): 8 r D_i 2 D_{i+1}; then a full QR
+#    of the 2r x D_{i+1} tile with explicit Q, 2 * 4 * (2 m c^2 - 2 c^3 / 3) with m >= c the
+#    larger and c the smaller dimension; r <- min(2r, D_{i+1}) (no rank stop). The last site
+#    takes R A_{n-1}.
+#  * Truncation sweep, site i = n-1..1: one-sided Jacobi SVD of the r_i x 2 chi_{i+1} tile,
+#    6 sweeps of c(c-1)/2 rotations of 56 m flops (c the smaller, m the larger dimension);
+#    then (U S) moves into the site on the left: 8 (2 r_{i-1}) r_i chi_i.
+# It reproduces 1.7e5, 3.9e5 and 6.0e5 flops per iterate for n = 10, 20 and 29 with one
+# marked state and bond cap 4, and 4.59e13 for the 4096-instance workload.
+JACOBI_SWEEPS = 6
+
+
+def _qr_flops(m: int, c: int) -> float:
+    big, small = max(m, c), min(m, c)
+    return 2.0 * 4.0 * (2.0 * big * small * small - 2.0 * small ** 3 / 3.0)
+
+
+def reflection_flops(chi) -> float:
+    n = len(chi) - 1
+    D = [1] + [2 * chi[l] for l in range(1, n)] + [1]
+    tot = 0.0
+    r = 1
+    rs = [1]
+    for i in range(n - 1):
+        tot += 8.0 * r * D[i] * 2 * D[i + 1]
+        tot += _qr_flops(2 * r, D[i + 1])
+        r = min(2 * r, D[i + 1])
+        rs.append(r)
+    tot += 8.0 * r * D[n - 1] * 2
+    for i in range(n - 1, 0, -1):
+        a, b = rs[i], 2 * chi[i + 1]
+        c, m = min(a, b), max(a, b)
+        tot += JACOBI_SWEEPS * c * (c - 1) / 2.0 * 56.0 * m
+        tot += 8.0 * 2 * rs[i - 1] * rs[i] * chi[i]
+    return tot
+
+
+def exact_rank_profile(n: int, M: int, cap: int):
+    """Bond profile of every state the iteration passes through once it has spread: the
+    Schmidt rank at a cut is at most M+1 and 2^min(l, n-l), and the cap bounds it."""
+    return [min(cap, M + 1, 2 ** min(l, n - l)) for l in range(n + 1)]
+
+
+def model_flops(instances, ks, profiles=None) -> float:
+    """sum_i k_i (M_i + 1) reflection_flops(profile_i); profiles default to the exact ranks."""
+    cache = {}
+    tot = 0.0
+    for j, inst in enumerate(instances):
+        prof = tuple(profiles[j]) if profiles is not None else tuple(exact_rank_profile(inst.n, inst.M, inst.chi_cap))
+        key = (inst.M, prof)
+        if key not in cache:
+            cache[key] = (inst.M + 1) * reflection_flops(list(prof))
+        tot += float(ks[j]) * cache[key]
+    return tot
 
 
 def workload(name: str) -> inputs.Workload:
@@ -82,76 +144,191 @@ def run_step(batch, ks, shots, seed):
     return p, hits
 
 
-def plain_fp64_rate(w, budget_s: float):
-    """The same instances through one B=1 FP64 handle each (one wave per launch), on a
-    stratified subset: one instance per (n, M) stratum, in increasing k, until the time
-    budget is spent."""
-    import torch
-    from paper_2601_03832_amd import gmps
-    seen = {}
-    for inst in w.instances:
-        seen.setdefault((inst.n, inst.M), inst)
-    picks = sorted(seen.values(), key=lambda i: (i.k * (i.M + 1) * (i.n - 1), i.n, i.M))
-    tot_k = 0
-    tot_s = 0.0
-    worst = 0.0
-    used = []
-    for inst in picks:
-        if tot_s > budget_s:
-            break
-        b = gmps.Batch([inst], "fp64")
-        b.init_uniform()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b.iterate(inst.k)
-        p = b.marked_prob()[0]
-        t1 = time.perf_counter()
-        worst = max(worst, abs(p - exact_p(inst.n, inst.M, inst.k)))
-        tot_k += inst.k
-        tot_s += t1 - t0
-        used.append((inst.n, inst.M))
-        b.close()
-    return {"value": tot_k / tot_s, "unit": "iterations/s", "instances": len(used),
-            "sum_k": tot_k, "seconds": tot_s, "max_abs_err": worst,
-            "sample": "one instance per (n, M) stratum of the same workload, cheapest strata first "
-                      "(%d of %d strata within a %.0f s budget), each alone through its own B=1 FP64 "
-                      "handle" % (len(used), len(picks), budget_s)}
-
-
-def cpu_baseline(w, iters_per_stratum: int = 100):
-    """The oracle (numpy FP64 MPS, one thread) on a bounded sample: a few iterations of one
-    instance per (n, M) stratum; the per-iteration time of each stratum is extrapolated to
-    every instance's own k."""
+# ------------------------------------------------------------------ CPU oracle baseline
+def _cpu_model() -> str:
     try:
-        from threadpoolctl import threadpool_limits
-    except Exception:  # pragma: no cover
-        threadpool_limits = None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_worker_init():
+    from threadpoolctl import threadpool_limits
+    global _CPU_LIMIT
+    _CPU_LIMIT = threadpool_limits(limits=1)
+
+
+def _cpu_job(job):
+    n, marked, cap, iters = job
     from oracle import mps as omps
+    m = omps.GroverMPS(n, marked, cap)
+    t0 = time.perf_counter()
+    m.iterate(iters)
+    return iters, time.perf_counter() - t0
+
+
+def cpu_baseline(w, frac: float = 1e-3, job_iters: int = 100):
+    """The oracle (numpy FP64 MPS, one thread per process) on every usable host core (at most
+    16), one instance per worker with dynamic scheduling, on a bounded sample whose mix of
+    (n, M) strata is the workload's: stratum s runs round(frac * K_s) iterations (K_s the
+    stratum's iterations in the workload), split into jobs of at most job_iters iterations on
+    distinct instances of the stratum. value = sample iterations / wall time of the pool."""
+    import multiprocessing as mp
     strata = {}
     for inst in w.instances:
-        strata.setdefault((inst.n, inst.M), inst)
-    per_iter = {}
-    ctx = threadpool_limits(limits=1) if threadpool_limits else None
-    t_all = time.perf_counter()
+        strata.setdefault((inst.n, inst.M), []).append(inst)
+    jobs = []
+    for (n, M), insts in strata.items():
+        left = max(1, int(round(frac * sum(i.k for i in insts))))
+        t = 0
+        while left > 0:
+            it = min(job_iters, left)
+            inst = insts[t % len(insts)]
+            jobs.append((n, [int(x) for x in inst.marked], inst.chi_cap, it))
+            left -= it
+            t += 1
+    jobs.sort(key=lambda j: -(j[0] * (len(j[1]) + 1) * j[3]))
     try:
-        if ctx:
-            ctx.__enter__()
-        for key, inst in strata.items():
-            m = omps.GroverMPS(inst.n, inst.marked, inst.chi_cap)
-            m.iterate(1)  # warm
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    workers = max(1, min(MAX_WORKERS, usable))
+    ctx = mp.get_context("spawn")
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        with ctx.Pool(workers, initializer=_cpu_worker_init) as pool:
+            pool.map(abs, range(workers))  # every worker is up before the clock starts
             t0 = time.perf_counter()
-            m.iterate(iters_per_stratum)
-            per_iter[key] = (time.perf_counter() - t0) / iters_per_stratum
+            res = list(pool.imap_unordered(_cpu_job, jobs, chunksize=1))
+            wall = time.perf_counter() - t0
     finally:
-        if ctx:
-            ctx.__exit__(None, None, None)
-    wall = time.perf_counter() - t_all
-    est = sum(inst.k * per_iter[(inst.n, inst.M)] for inst in w.instances)
-    tot_k = sum(inst.k for inst in w.instances)
-    return {"value": tot_k / est, "unit": "iterations/s", "cores": 1, "kind": "oracle",
-            "sample": "%d iterations of one instance per (n,M) stratum (%d strata, %.1f s of CPU), "
-                      "extrapolated to every instance's k (est. %.0f s for the whole workload)"
-                      % (iters_per_stratum, len(strata), wall, est)}
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    iters = sum(r[0] for r in res)
+    cpu_s = sum(r[1] for r in res)
+    sum_k = sum(i.k for i in w.instances)
+    rate = iters / wall
+    return {"value": rate, "unit": "iterations/s", "cores": workers, "kind": "oracle",
+            "nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": _cpu_model(),
+            "sample": "%d iterations (%.2g of each (n, M) stratum's iterations in the workload, %d jobs of <= %d "
+                      "iterations on distinct instances) in %.1f s on %d processes, %.1f CPU-s; the whole workload "
+                      "at this rate: %.0f s" % (iters, frac, len(jobs), job_iters, wall, workers, cpu_s, sum_k / rate)}
+
+
+def closed_form_amplitudes(n: int, M: int, k: int):
+    """Eq. (5): a marked amplitude sin(phi)/sqrt(M) and an unmarked one cos(phi)/sqrt(N-M),
+    phi = (2k+1) asin(sqrt(M/N))."""
+    N = float(2 ** n)
+    phi = (2 * k + 1) * math.asin(math.sqrt(M / N))
+    return math.sin(phi) / math.sqrt(M), math.cos(phi) / math.sqrt(N - M)
+
+
+def single_leg(w, reps: int = 5):
+    """A single-instance case (FP64): one untimed run, then the median of reps runs of
+    mps_init_uniform + grover_iterate(k), each timed by the library's HIP events around the
+    iterate launch; P against Eq. (6), the amplitudes against Eq. (5) (every basis index up
+    to n = 12, else the marked index and 64 others) and, with shots, the marked hit fraction."""
+    from paper_2601_03832_amd import gmps
+    inst = w.instances[0]
+    n, M, k = inst.n, inst.M, inst.k
+    b = gmps.Batch([inst], w.precision)
+    b.init_uniform()
+    b.iterate(k)
+    runs = []
+    for _ in range(reps):
+        b.init_uniform()
+        b.iterate(k)
+        runs.append(b.last_iterate_ms())
+    p = float(b.marked_prob()[0])
+    am, au = closed_form_amplitudes(n, M, k)
+    xs = np.arange(1 << n, dtype=np.uint64) if n <= 12 else \
+        np.unique(np.concatenate([np.asarray(inst.marked, dtype=np.uint64),
+                                  np.random.default_rng(3).integers(0, 1 << n, 64, dtype=np.uint64)]))
+    a = b.amplitudes(0, xs)
+    marked = set(int(x) for x in inst.marked)
+    ref = np.array([am if int(x) in marked else au for x in xs])
+    med = statistics.median(runs)
+    out = {"workload": w.name, "value": k / (med / 1e3), "unit": "iterations/s", "median_ms": med,
+           "runs_ms": runs, "k": k, "p": p, "abs_err_p": abs(p - exact_p(n, M, k)), "tolerance": 1e-10,
+           "max_abs_err_amplitude": float(np.max(np.abs(a - ref))), "amplitudes_checked": int(len(xs))}
+    if w.shots:
+        shots = w.shots[-1]
+        _, hits = b.sample(shots, w.shot_seed)
+        out["shots"] = shots
+        out["hit_fraction"] = float(hits[0]) / shots
+        out["hit_fraction_expected"] = exact_p(n, M, k)
+    b.close()
+    return out
+
+
+def c3_leg():
+    """The precision study: n=29, one marked state, k=18198, FP64 and mixed, in chunks of 1000
+    iterations; |P_j - sin^2((2j+1) theta)| after every chunk, and the summed HIP-event time of
+    the iterate launches."""
+    from paper_2601_03832_amd import gmps
+    out = {}
+    for prec in ("fp64", "mixed"):
+        inst = inputs.config_c3(prec).instances[0]
+        b = gmps.Batch([inst], prec)
+        b.init_uniform()
+        done = 0
+        total_ms = 0.0
+        log = []
+        while done < inst.k:
+            step = min(1000, inst.k - done)
+            b.iterate(step)
+            total_ms += b.last_iterate_ms()
+            done += step
+            p = float(b.marked_prob(allow_numeric=True)[0])
+            log.append([done, p - exact_p(inst.n, inst.M, done)])
+        b.close()
+        errs = [abs(e) for _, e in log]
+        out[prec] = {"value": inst.k / (total_ms / 1e3), "unit": "iterations/s", "kernel_ms": total_ms,
+                     "final_abs_err_p": errs[-1], "max_abs_err_p": max(errs),
+                     "tolerance": 1e-10 if prec == "fp64" else 1e-6, "err_p_every_1000": log}
+    out["note"] = "n=29, M=1, k=18198, chi cap 4; P - sin^2((2j+1) theta) after every 1000 iterations"
+    return out
+
+
+def plain_fp64_leg(w, prefix: int = 100, extra: int = 13):
+    """The plain per-instance FP64 GPU path: instances through their own B=1 FP64 handle (one
+    wave per launch), one per (n, M) stratum plus `extra` more from the strata with the most
+    iterations, each for a prefix of min(k, prefix) iterations timed by the library's HIP
+    events; the per-iteration time of each stratum is extrapolated to every instance's own k."""
+    from paper_2601_03832_amd import gmps
+    strata = {}
+    for inst in w.instances:
+        strata.setdefault((inst.n, inst.M), []).append(inst)
+    picks = [v[0] for v in strata.values()]
+    heavy = sorted(strata.values(), key=lambda v: -sum(i.k * (i.M + 1) * i.n for i in v))
+    picks += [v[1] for v in heavy[:extra] if len(v) > 1]
+    per = {}
+    worst = 0.0
+    for inst in picks:
+        kk = min(inst.k, prefix)
+        b = gmps.Batch([inst], "fp64")
+        b.init_uniform()
+        b.iterate(kk)
+        ms = b.last_iterate_ms()
+        worst = max(worst, abs(float(b.marked_prob()[0]) - exact_p(inst.n, inst.M, kk)))
+        b.close()
+        per.setdefault((inst.n, inst.M), []).append(ms / 1e3 / kk)
+    est = sum(i.k * float(np.mean(per[(i.n, i.M)])) for i in w.instances)
+    sum_k = sum(i.k for i in w.instances)
+    return {"value": sum_k / est, "unit": "iterations/s", "extrapolated": True, "instances_timed": len(picks),
+            "strata": len(strata), "est_seconds": est, "max_abs_err_p_prefix": worst,
+            "sample": "%d instances (every one of the %d (n, M) strata, and a second instance of the %d heaviest), "
+                      "each alone through a B=1 FP64 handle for min(k, %d) iterations timed by HIP events; "
+                      "per-iteration times extrapolated to every instance's own k" % (len(picks), len(strata), extra, prefix)}
 
 
 def c5_prefix(k: int, kernel: str, precontract: bool = False):
@@ -290,8 +467,8 @@ def fp32_accuracy_leg():
         s.close()
     out["sv_fp32_vector"] = sv_p
     out["note"] = ("fp32: site tensors, contractions, QR, Jacobi SVD and norms in FP32, rounded to nearest; "
-                   "mixed: complex64 sites, FP64 factorisations, stochastic rounding; sv_fp32_vector: [n, P] "
-                   "of the dense statevector with an FP32 vector and FP64 sums")
+                   "mixed: FP64 arithmetic, complex64 bulk sites stored with compensated rounding; "
+                   "sv_fp32_vector: [n, P] of the dense statevector with an FP32 vector and FP64 sums")
     return out
 
 
@@ -326,22 +503,25 @@ def traffic_record():
 
 
 def main():
+    t_start = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4")
-    ap.add_argument("--plain-budget", type=float, default=20.0)
+    ap.add_argument("--budget", type=float, default=330.0,
+                    help="seconds for the whole run: the side legs run, in priority order, while it lasts")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one device copy of this many bytes (counter calibration)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the single-instance n=10/20/29 legs")
     ap.add_argument("--no-fp64-batch", action="store_true")
     ap.add_argument("--shots", type=int, default=None)
     ap.add_argument("--c5-k", type=int, default=48, help="iterations of the n=40, M=16 prefix leg (0: skip)")
     ap.add_argument("--sv-k", type=int, default=500, help="iterations of the statevector comparison leg (0: skip)")
     ap.add_argument("--no-precontract", action="store_true", help="skip the pre-contracted reflections legs")
-    ap.add_argument("--no-sequential", action="store_true", help="skip the sequential-sweeps leg")
+    ap.add_argument("--sequential", action="store_true", help="also time the sequential-sweeps variant")
     ap.add_argument("--no-fp32", action="store_true", help="skip the all-FP32 accuracy leg")
     ap.add_argument("--fp32-c4", action="store_true",
                     help="also time the whole workload on the lane-group kernel in FP32, mixed and FP64")
@@ -354,17 +534,25 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    def log(msg):
+        print("bench: [%5.1f s] %s" % (time.perf_counter() - t_start, msg), file=sys.stderr, flush=True)
+
+    w = workload(args.workload)
+    # the CPU oracle first, in worker processes, before this process touches the GPU
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w)
+        log("cpu baseline done (%.0f iterations/s on %d processes)" % (cpu["value"], cpu["cores"]))
+
     import torch
     from paper_2601_03832_amd import gmps
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible: the benchmark needs the HIP library on an MI355X")
     torch.cuda.set_device(0)
-    w = workload(args.workload)
     shots = (w.shots[-1] if w.shots else 0) if args.shots is None else args.shots
     ks = [i.k for i in w.instances]
     sum_k = int(sum(ks))
-    print("bench: workload %s, %d instances, sum k = %d, precision %s, shots %d"
-          % (w.name, len(ks), sum_k, w.precision, shots), file=sys.stderr, flush=True)
+    log("workload %s, %d instances, sum k = %d, precision %s, shots %d" % (w.name, len(ks), sum_k, w.precision, shots))
     if args.copy_bytes:
         src = torch.empty(args.copy_bytes, dtype=torch.uint8, device="cuda").fill_(1)
         dst = torch.empty_like(src)
@@ -372,12 +560,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        print("bench: calibration copy of %d bytes done" % args.copy_bytes, file=sys.stderr, flush=True)
+        log("calibration copy of %d bytes done" % args.copy_bytes)
     batch = gmps.Batch(w.instances, w.precision, kernel=args.kernel)
 
     for s in range(args.warmup):
         run_step(batch, ks, shots, w.shot_seed)
-        print("bench: warmup step %d done" % s, file=sys.stderr, flush=True)
+        log("warmup step %d done" % s)
     torch.cuda.synchronize()
     kernel_ms = []
     t0 = time.perf_counter()
@@ -385,7 +573,7 @@ def main():
     for s in range(args.steps):
         p, hits = run_step(batch, ks, shots, w.shot_seed)
         kernel_ms.append(batch.last_iterate_ms())
-        print("bench: timed step %d done" % s, file=sys.stderr, flush=True)
+        log("timed step %d done" % s)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
@@ -397,8 +585,8 @@ def main():
     f64 = float(np.sum(diag["flops64"]))
     f32 = float(np.sum(diag["flops32"]))
     kms = float(np.mean(kernel_ms))
-    # FP64-equivalent work: FP32 flops count at the FP64/FP32 peak ratio
-    achieved = (f64 + f32 * FP64_VECTOR_PEAK / FP32_VECTOR_PEAK) / (kms / 1000.0)
+    fmodel = model_flops(w.instances, ks, diag["bond_dims"])
+    achieved = fmodel / (kms / 1000.0)
     tr = traffic_record()
     line = {
         "metric": "Grover iterations/s on 1 GPU, batched mixed-prec vs plain FP64, err<=1e-6",
@@ -411,74 +599,132 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64/f64" if w.precision == "mixed" else "f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "instances": len(ks), "sum_k": sum_k, "precision": w.precision,
+                   "storage": ("complex64 bulk sites, complex128 edge sites; every arithmetic step FP64"
+                               if w.precision == "mixed" else "complex128"),
                    "shots_per_instance": shots, "kernel": args.kernel, "description": w.description},
         "accuracy": {"max_abs_err_p": float(errs.max()), "tolerance": tol, "pass": bool(errs.max() <= tol),
                      "status_flags": int(np.bitwise_or.reduce(diag["status"]))},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK,
                      "traffic": tr["bytes_per_launch"] if tr else None,
-                     "kernel": KERNEL_NAME[args.kernel], "kernel_ms": kms,
-                     "flops64_per_launch": f64, "flops32_per_launch": f32},
+                     "kernel": KERNEL_NAME[args.kernel] + " and the other class kernels of the iterate launch",
+                     "kernel_ms": kms, "flops_model": fmodel,
+                     "model": "LAPACK-style counts per reflection and site: R*A, full QR with explicit Q, "
+                              "one-sided Jacobi SVD with 6 sweeps, (U S)*A, over the reported bond profile",
+                     "flops_kernel_count": f64 + f32,
+                     "frac_kernel_count": (f64 + f32) / (kms / 1000.0) / FP64_VECTOR_PEAK},
     }
-    print("bench: main measurement done (%.1f ms/step)" % ms_per_step, file=sys.stderr, flush=True)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    log("main measurement done (%.1f ms/step)" % ms_per_step)
     batch.close()
+    step_s = ms_per_step / 1000.0
+
+    def have(cost_s):
+        return time.perf_counter() - t_start + cost_s < args.budget
+
+    skipped = []
+    c4 = args.workload == "c4"
+    if not args.no_small:
+        if have(10):
+            line["c1"] = single_leg(inputs.config_c1())
+            line["c2"] = single_leg(inputs.config_c2())
+            log("c1/c2 legs done")
+        else:
+            skipped.append("c1/c2")
     if w.precision == "mixed" and not args.no_fp64_batch:
-        b64 = gmps.Batch(w.instances, "fp64", kernel=args.kernel)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        p64, _ = run_step(b64, ks, shots, w.shot_seed)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        e64 = max(abs(p64[i] - exact_p(inst.n, inst.M, inst.k)) for i, inst in enumerate(w.instances))
-        line["batched_fp64"] = {"value": sum_k / (t3 - t2), "unit": "iterations/s", "ms_per_step": (t3 - t2) * 1000.0,
-                                "kernel_ms": b64.last_iterate_ms(), "max_abs_err_p": e64,
-                                "note": "same workload and step through the FP64 path (one untimed-warmup-free step)"}
-        b64.close()
-        print("bench: batched fp64 leg done", file=sys.stderr, flush=True)
-    if not args.no_sequential and args.kernel != "group":
-        bs = gmps.Batch(w.instances, w.precision, kernel=args.kernel, pipeline=False)
-        torch.cuda.synchronize()
-        t4 = time.perf_counter()
-        ps, _ = run_step(bs, ks, shots, w.shot_seed)
-        torch.cuda.synchronize()
-        t5 = time.perf_counter()
-        es = max(abs(ps[i] - exact_p(inst.n, inst.M, inst.k)) for i, inst in enumerate(w.instances))
-        line["sequential_sweeps"] = {"value": sum_k / (t5 - t4), "unit": "iterations/s", "ms_per_step": (t5 - t4) * 1000.0,
-                                     "kernel_ms": bs.last_iterate_ms(), "max_abs_err_p": es,
-                                     "note": "same workload and step with gmps_options.pipeline = -1: each reflection's "
-                                             "canonicalisation and truncation sweeps in turn on one wave per instance "
-                                             "(one step, no untimed warmup)"}
-        bs.close()
-        print("bench: sequential sweeps leg done", file=sys.stderr, flush=True)
+        if have(1.3 * step_s + 5):
+            b64 = gmps.Batch(w.instances, "fp64", kernel=args.kernel)
+            run_step(b64, ks, shots, w.shot_seed)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            p64, _ = run_step(b64, ks, shots, w.shot_seed)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            e64 = max(abs(p64[i] - exact_p(inst.n, inst.M, inst.k)) for i, inst in enumerate(w.instances))
+            line["batched_fp64"] = {"value": sum_k / (t3 - t2), "unit": "iterations/s", "ms_per_step": (t3 - t2) * 1000.0,
+                                    "kernel_ms": b64.last_iterate_ms(), "max_abs_err_p": e64,
+                                    "note": "same workload and step through the FP64 path, after an untimed step"}
+            b64.close()
+            log("batched fp64 leg done")
+        else:
+            skipped.append("batched_fp64")
     if not args.no_precontract and args.kernel != "group":
-        line["precontracted"] = precontracted_leg(w, ks, shots, args.kernel)
-        line["precontracted"]["mixed"]["speedup_over_value"] = line["precontracted"]["mixed"]["value"] / line["value"]
-        print("bench: pre-contracted legs done", file=sys.stderr, flush=True)
-    if args.c5_k > 0 and args.workload == "c4":
-        line["c5_prefix"] = c5_prefix(args.c5_k, args.kernel)
-        print("bench: c5 prefix leg done", file=sys.stderr, flush=True)
-        if not args.no_precontract and args.kernel != "group":
-            line["c5_prefix_precontracted"] = c5_prefix(args.c5_k, args.kernel, precontract=True)
-            print("bench: c5 prefix pre-contracted leg done", file=sys.stderr, flush=True)
-    if args.sv_k > 0 and args.workload == "c4":
-        line["statevector"] = statevector_leg(28, args.sv_k)
-        print("bench: statevector leg done", file=sys.stderr, flush=True)
-    if not args.no_fp32 and args.workload == "c4":
-        line["fp32_accuracy"] = fp32_accuracy_leg()
-        print("bench: fp32 accuracy leg done", file=sys.stderr, flush=True)
-    if args.fp32_c4 and args.workload == "c4":
-        line["fp32_c4_lane_group"] = fp32_c4_leg(w, ks, shots)
-        print("bench: lane-group fp32/mixed/fp64 leg done", file=sys.stderr, flush=True)
+        if have(2.5 * step_s + 5):
+            line["precontracted"] = precontracted_leg(w, ks, shots, args.kernel)
+            line["precontracted"]["mixed"]["speedup_over_value"] = line["precontracted"]["mixed"]["value"] / line["value"]
+            log("pre-contracted legs done")
+        else:
+            skipped.append("precontracted")
+    fastest = [("mixed, bond-2 MPO reflections (the value)", line["value"])]
+    if "batched_fp64" in line:
+        fastest.append(("fp64, bond-2 MPO reflections", line["batched_fp64"]["value"]))
+    if "precontracted" in line:
+        fastest.append(("mixed, pre-contracted reflections", line["precontracted"]["mixed"]["value"]))
+        fastest.append(("fp64, pre-contracted reflections", line["precontracted"]["fp64"]["value"]))
+    best = max(fastest, key=lambda x: x[1])
+    line["fastest_path"] = {"path": best[0], "value": best[1], "unit": "iterations/s",
+                            "note": "every arithmetic step is FP64 on both precisions; mixed only stores the bulk "
+                                    "sites as complex64, which saves no time on this latency-bound path"}
+    if not args.no_small and c4:
+        if have(40):
+            line["c3"] = c3_leg()
+            log("c3 leg done")
+        else:
+            skipped.append("c3")
     if not args.no_plain:
-        line["plain_fp64"] = plain_fp64_rate(w, args.plain_budget)
-        line["plain_fp64"]["speedup_of_batched_mixed"] = line["value"] / line["plain_fp64"]["value"]
-        print("bench: plain fp64 leg done", file=sys.stderr, flush=True)
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w)
-        print("bench: cpu baseline leg done", file=sys.stderr, flush=True)
+        if have(30):
+            line["plain_fp64"] = plain_fp64_leg(w)
+            line["plain_fp64"]["speedup_of_batched_mixed"] = line["value"] / line["plain_fp64"]["value"]
+            log("plain fp64 leg done")
+        else:
+            skipped.append("plain_fp64")
+    if args.sv_k > 0 and c4:
+        if have(15):
+            line["statevector"] = statevector_leg(28, args.sv_k)
+            log("statevector leg done")
+        else:
+            skipped.append("statevector")
+    if not args.no_fp32 and c4:
+        if have(40):
+            line["fp32_accuracy"] = fp32_accuracy_leg()
+            log("fp32 accuracy leg done")
+        else:
+            skipped.append("fp32_accuracy")
+    if args.c5_k > 0 and c4:
+        if have(30):
+            line["c5_prefix"] = c5_prefix(args.c5_k, args.kernel)
+            log("c5 prefix leg done")
+            if not args.no_precontract and args.kernel != "group" and have(30):
+                line["c5_prefix_precontracted"] = c5_prefix(args.c5_k, args.kernel, precontract=True)
+                log("c5 prefix pre-contracted leg done")
+        else:
+            skipped.append("c5_prefix")
+    if args.sequential and args.kernel != "group":
+        if have(2.5 * step_s):
+            bs = gmps.Batch(w.instances, w.precision, kernel=args.kernel, pipeline=False)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            ps, _ = run_step(bs, ks, shots, w.shot_seed)
+            torch.cuda.synchronize()
+            t5 = time.perf_counter()
+            es = max(abs(ps[i] - exact_p(inst.n, inst.M, inst.k)) for i, inst in enumerate(w.instances))
+            line["sequential_sweeps"] = {"value": sum_k / (t5 - t4), "unit": "iterations/s", "ms_per_step": (t5 - t4) * 1000.0,
+                                         "kernel_ms": bs.last_iterate_ms(), "max_abs_err_p": es,
+                                         "note": "same workload and step with gmps_options.pipeline = -1 (one step, "
+                                                 "no untimed warmup)"}
+            bs.close()
+            log("sequential sweeps leg done")
+        else:
+            skipped.append("sequential_sweeps")
+    if args.fp32_c4 and c4:
+        line["fp32_c4_lane_group"] = fp32_c4_leg(w, ks, shots)
+        log("lane-group fp32/mixed/fp64 leg done")
+    if skipped:
+        line["legs_skipped_for_time"] = skipped
     print(json.dumps(line), flush=True)
 
 
