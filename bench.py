@@ -6,14 +6,15 @@ launch), read out (marked_prob) and sampled (sample_shots). value = sum_i k_i / 
 The accuracy gate requires |P_i - sin^2((2k_i+1) theta_i)| <= 1e-6 for every instance.
 
     python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--workload c4|c2|c3] [--kernel auto|team|group]
-                    [--budget 330] [--c5-k 48] [--sv-k 500] [--no-plain] [--no-cpu] [--no-fp64-batch]
+                    [--budget 330] [--c5-k 5000] [--sv-k 500] [--no-plain] [--no-cpu] [--no-fp64-batch]
                     [--sequential] [--no-precontract] [--no-fp32] [--fp32-c4] [--no-small]
 
 Besides the headline line, the default run adds legs on the same hardware, in priority order
 while the time budget lasts: the single-instance cases (n=10 and n=20, FP64, median of 5),
 the workload through the FP64 path and with pre-contracted reflections, the n=29 precision
 study (FP64 vs mixed, P logged every 1000 iterations), per-instance FP64 handles, the dense
-statevector backend, the all-FP32 precision study and a prefix of the n=40, M=16 workload.
+statevector backend, the all-FP32 precision study and a 5000-iteration prefix of the n=40,
+M=16 workload (pre-contracted reflections, FP64 and mixed, with 1/8/4096-shot hit fractions).
 The CPU oracle runs first, before the GPU is touched.
 
 Prints one JSON line. roofline: algorithmic flops of the iterate launch from the LAPACK-style
@@ -331,35 +332,38 @@ def plain_fp64_leg(w, prefix: int = 100, extra: int = 13):
                       "per-iteration times extrapolated to every instance's own k" % (len(picks), len(strata), extra, prefix)}
 
 
-def c5_prefix(k: int, kernel: str, precontract: bool = False):
-    """256 instances at n=40, M=16, cap 32 (bond 17), mixed, for a prefix of k iterations:
-    the full k=205887 takes hours, so the rate and the accuracy are reported on the prefix."""
+def c5_prefix(k: int, kernel: str, precontract: bool = False, precision: str = "mixed"):
+    """256 instances at n=40, M=16, cap 32 (bond 17) for a prefix of k iterations (the full
+    k = 205887 is not run): P against Eq. (6), and the marked hit fraction of 1, 8 and 4096
+    perfect-sampling shots per instance (mean, min and max over the instances)."""
     import torch
     from paper_2601_03832_amd import gmps
     w = inputs.config_c5(k=k)
-    b = gmps.Batch(w.instances, w.precision, kernel=kernel, precontract=precontract)
+    b = gmps.Batch(w.instances, precision, kernel=kernel, precontract=precontract)
     b.init_uniform()
-    b.iterate(k)  # warm (graph capture)
     torch.cuda.synchronize()
-    b.init_uniform()
     t0 = time.perf_counter()
     b.iterate(k)
     p = b.marked_prob(allow_numeric=True)
     t1 = time.perf_counter()
-    err = float(np.max(np.abs(p - exact_p(40, 16, k))))
+    kms = b.last_iterate_ms()
+    pe = exact_p(40, 16, k)
+    err = float(np.max(np.abs(p - pe)))
     frac = {}
     for shots in w.shots:
         _, hits = b.sample(shots, w.shot_seed)
-        frac[str(shots)] = float(np.mean(hits / shots))
-    kms = b.last_iterate_ms()
+        f = hits / shots
+        frac[str(shots)] = {"mean": float(np.mean(f)), "min": float(np.min(f)), "max": float(np.max(f))}
     d = b.diagnostics()
     b.close()
     n_inst = len(w.instances)
     return {"value": n_inst * k / (t1 - t0), "unit": "iterations/s", "instances": n_inst, "k_prefix": k,
-            "seconds": t1 - t0, "kernel_ms": kms, "max_abs_err_p": err, "p_exact": exact_p(40, 16, k),
-            "mean_hit_fraction": frac, "flops_per_launch": float(np.sum(d["flops64"]) + np.sum(d["flops32"])),
-            "note": "256 x (n=40, M=16, cap 32) for the first %d of k=205887 iterations, mixed%s; not extrapolated"
-                    % (k, ", pre-contracted reflections" if precontract else "")}
+            "precision": precision, "precontract": precontract, "seconds": t1 - t0, "kernel_ms": kms,
+            "max_abs_err_p": err, "max_rel_err_p": err / pe, "p_exact": pe, "hit_fraction": frac,
+            "status_flags": int(np.bitwise_or.reduce(d["status"])),
+            "flops_model": model_flops(w.instances, [k] * n_inst, d["bond_dims"]),
+            "note": "256 x (n=40, M=16, cap 32) for the first %d of k=205887 iterations, %s%s; not extrapolated"
+                    % (k, precision, ", pre-contracted reflections" if precontract else ", bond-2 MPO reflections")}
 
 
 def precontracted_leg(w, ks, shots, kernel: str):
@@ -518,7 +522,8 @@ def main():
     ap.add_argument("--no-small", action="store_true", help="skip the single-instance n=10/20/29 legs")
     ap.add_argument("--no-fp64-batch", action="store_true")
     ap.add_argument("--shots", type=int, default=None)
-    ap.add_argument("--c5-k", type=int, default=48, help="iterations of the n=40, M=16 prefix leg (0: skip)")
+    ap.add_argument("--c5-k", type=int, default=5000,
+                    help="iterations of the n=40, M=16 prefix legs, pre-contracted, FP64 and mixed (0: skip)")
     ap.add_argument("--sv-k", type=int, default=500, help="iterations of the statevector comparison leg (0: skip)")
     ap.add_argument("--no-precontract", action="store_true", help="skip the pre-contracted reflections legs")
     ap.add_argument("--sequential", action="store_true", help="also time the sequential-sweeps variant")
@@ -694,15 +699,15 @@ def main():
             log("fp32 accuracy leg done")
         else:
             skipped.append("fp32_accuracy")
-    if args.c5_k > 0 and c4:
-        if have(30):
-            line["c5_prefix"] = c5_prefix(args.c5_k, args.kernel)
-            log("c5 prefix leg done")
-            if not args.no_precontract and args.kernel != "group" and have(30):
-                line["c5_prefix_precontracted"] = c5_prefix(args.c5_k, args.kernel, precontract=True)
-                log("c5 prefix pre-contracted leg done")
-        else:
-            skipped.append("c5_prefix")
+    if args.c5_k > 0 and c4 and args.kernel != "group":
+        # pre-contracted reflections: FP64 (the accurate path at n = 40), then mixed beside it
+        for prec, cost in (("fp64", 8.0), ("mixed", 11.5)):
+            key = "c5_prefix_%s_precontracted" % prec
+            if have(cost * args.c5_k / 1000.0 + 10):
+                line[key] = c5_prefix(args.c5_k, args.kernel, precontract=True, precision=prec)
+                log("c5 prefix %s pre-contracted leg done" % prec)
+            else:
+                skipped.append(key)
     if args.sequential and args.kernel != "group":
         if have(2.5 * step_s):
             bs = gmps.Batch(w.instances, w.precision, kernel=args.kernel, pipeline=False)

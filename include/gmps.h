@@ -35,8 +35,12 @@
  *    edge slots of the workspace. On the lane-group kernel GMPS_MIXED instead runs the MPO
  *    application and the site contractions in complex64 and the factorisations in FP64 on
  *    up-converted tiles. Either way Schmidt components below trunc_tol (5e-7) of the
- *    largest are dropped: in the first iterations at n above about 40 the marked component
- *    lies near that floor (amplitude ~2^(-n/2)), so such runs need GMPS_FP64. Near the
+ *    largest are dropped. Accuracy of the team kernel's GMPS_MIXED, measured against the
+ *    rotation angle (2k+1) theta: at n <= 29 the angle error stays near 1e-8 with bond-2 MPO
+ *    reflections; pre-contracted reflections (precontract = 1) drift by up to 3e-10 per
+ *    iteration at M = 4 (1e-6 over a 3000-iteration run). At n = 40, where the marked
+ *    amplitudes start at ~2^-20, the angle drifts by ~2e-9 (MPO) and ~3e-10 (pre-contracted)
+ *    per iteration, far beyond 1e-6 in P over the full k: such runs need GMPS_FP64. Near the
  *    peak of P, in the one iteration where the unmarked component passes through a few
  *    1e-6, the mixed path's rotation angle (2k+1) theta can shift by up to about 2e-6 rad;
  *    P, flat there, moves by ~1e-12, but the shift stays with the state if it is iterated
