@@ -123,8 +123,8 @@ typedef struct {
                            team of 16-256 threads; bond caps up to 32), 0 = library choice
                            (the team kernel; the lane-group kernel for GMPS_FP32) */
   int32_t precontract;  /* 1: projector pre-contraction, a recompression variant of Section III-B
-                           (team kernel only; with kernel = 1: GMPS_E_UNSUPPORTED; instances
-                           whose effective bond cap exceeds 17 keep the bond-2 MPOs). A reflection
+                           (team kernel only; with kernel = 1, or with an instance whose effective
+                           bond cap exceeds 17, gmps_create returns GMPS_E_UNSUPPORTED). A reflection
                            c0 I + c1 sum_t |p_t><p_t| over product states p_t (Eqs. (3)-(4): the
                            marked basis states for O, |s> for D) maps psi to
                            c0 psi + c1 sum_t <p_t|psi> p_t, an MPS of bond chi + T built from
@@ -134,8 +134,12 @@ typedef struct {
                            and M fits the tile class, O is one reflection with T = M, so an
                            iteration takes two QR+SVD sweeps instead of M+1; otherwise each
                            marked index is one reflection with T = 1. Same result up to
-                           rounding; 0 or -1 (default): one bond-2 MPO per projector, as in
-                           the paper. */
+                           rounding on GMPS_FP64. On GMPS_MIXED the rotation angle drifts by up
+                           to ~3e-10 per iteration (M = 4, n <= 28; also at n = 40), against
+                           ~2e-12 with the bond-2 MPOs: the exact product terms add directions
+                           outside the complex64-rounded bond spaces, which the M+1 cap cuts with
+                           a little in-plane weight. 0 or -1 (default): one bond-2 MPO per
+                           projector, as in the paper. */
   int32_t pipeline;     /* 0 or 1 (default): the team classes with bond caps 2, 3, 5 and 8 run
                            the per-projector reflections with alternating sweep directions on
                            two waves, the truncation sweep of each reflection and the
@@ -159,8 +163,8 @@ size_t gmps_workspace_bytes(const gmps_instance* inst, int32_t B, gmps_prec prec
  * The chain is left uninitialised: call mps_init_uniform() next.
  * Errors: GMPS_E_ARG (bad instance, duplicate or out-of-range marked index, unknown
  * kernel or precision), GMPS_E_WORKSPACE, GMPS_E_UNSUPPORTED (no tile class holds the bond
- * cap; precontract without the team kernel; GMPS_FP32 with kernel = 2 or an effective bond
- * cap above 6), GMPS_E_HIP. */
+ * cap; precontract without the team kernel or with an effective bond cap above 17; GMPS_FP32
+ * with kernel = 2 or an effective bond cap above 6), GMPS_E_HIP. */
 int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const uint64_t* marked,
                 gmps_prec prec, const gmps_options* opt, void* dev_workspace, size_t ws_bytes,
                 void* hip_stream);

@@ -282,6 +282,8 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   for (int i = 0; i < B; ++i) {
     const int c = pick_class(inst[i].n, inst[i].M, inst[i].chi_cap, path);
     if (c < 0 || (fp32 && is_wide(c))) return GMPS_E_UNSUPPORTED;
+    // the pre-contracted reflections are built for bond caps up to 17 only
+    if (precontract && !(is_wide(c) && team_pc_class(c - kWideBase))) return GMPS_E_UNSUPPORTED;
   }
   if (!compute_layout(inst, B, prec, path, &L, &cls, &site_off, &warm_off, &edge_off)) return GMPS_E_ARG;
   // marked sets: in range and distinct within an instance

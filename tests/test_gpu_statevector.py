@@ -51,18 +51,28 @@ def test_iterate_additive_and_k0(gpu):
     assert abs(a.marked_prob() - cf.p_marked(n, 2, 20)) < 1e-12
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
-def test_n24_full_k(gpu, precision, tol):
+# FP32 vector (FP64 sums): every iteration applies the unitary G exactly up to the FP64 mean
+# and rounds each amplitude to FP32, a perturbation of norm at most u = 2^-24 of the unit state.
+# G does not grow errors, so after k iterations ||psi~ - psi|| <= k u and |P~ - P| <= 2 k u:
+# 3.8e-4 at n = 24, checked half way (where P moves at first order) and at the full k.
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_n24_full_k(gpu, precision):
     n, M = 24, 1
     W = inputs.draw_marked(n, M, inputs.SplitMix64(24))
     k = inputs.k_rule(n, M)
+    tol = 1e-10 if precision == "fp64" else 2 * k * 2.0 ** -24
     say("case: statevector n=24 k=%d %s" % (k, precision))
     s = gmps.StateVector(n, W, precision)
     s.init_uniform()
-    s.iterate(k)
+    s.iterate(k // 2)
+    ph = s.marked_prob()
+    say("   half k: |dP| = %.3e (gate %.1e)" % (abs(ph - cf.p_marked(n, M, k // 2)), tol))
+    assert abs(ph - cf.p_marked(n, M, k // 2)) < tol, ph
+    s.iterate(k - k // 2)
     p = s.marked_prob()
     say("   |dP| = %.3e" % abs(p - cf.p_marked(n, M, k)))
     assert abs(p - cf.p_marked(n, M, k)) < tol, p
     am, au = cf.amplitudes_wr(n, M, k)
     got = s.amplitudes(np.array([W[0], 0, 12345, (1 << n) - 1], dtype=np.uint64))
-    assert abs(got[0] - am) < tol and np.max(np.abs(got[1:] - au)) < 10 * tol * abs(au)
+    # each amplitude is within ||psi~ - psi|| of its exact value (tol / 2 on the FP32 vector)
+    assert abs(got[0] - am) < tol and np.max(np.abs(got[1:] - au)) < (1e-9 * abs(au) if precision == "fp64" else tol / 2)
