@@ -137,6 +137,16 @@ def workload(name: str) -> inputs.Workload:
     raise SystemExit("unknown workload " + name)
 
 
+def plan_name(kernel: str, plan) -> str:
+    """The launch plan in words: the kernel choice and, when autotuned, the plan it picked."""
+    if not plan:
+        return kernel + " (library default plan)"
+    return "%s: %s sweeps, %s reflections, %s workgroups per CU (autotuned)" % (
+        "team" if kernel == "auto" else kernel, "pipelined" if plan["pipeline"] else "sequential",
+        "pre-contracted" if plan["precontract"] else "bond-2 MPO",
+        "occupancy-limited" if plan["waves_per_cu"] == 0 else str(plan["waves_per_cu"]))
+
+
 def run_step(batch, ks, shots, seed):
     batch.init_uniform()
     batch.iterate(ks)
@@ -530,6 +540,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the all-FP32 accuracy leg")
     ap.add_argument("--fp32-c4", action="store_true",
                     help="also time the whole workload on the lane-group kernel in FP32, mixed and FP64")
+    ap.add_argument("--no-tune", action="store_true", help="run the library's default launch plan")
+    ap.add_argument("--tune-probe", type=int, default=64, help="iterations of the longest chain per autotuner probe")
+    ap.add_argument("--tune-cache", default=None, help="plan cache file of the autotuner (default: none)")
     ap.add_argument("--kernel", default="auto", choices=sorted(["auto", "group", "team"]),
                     help="iterate kernel: lane-group, team, or the library's choice")
     args = ap.parse_args()
@@ -567,6 +580,11 @@ def main():
         del src, dst
         log("calibration copy of %d bytes done" % args.copy_bytes)
     batch = gmps.Batch(w.instances, w.precision, kernel=args.kernel)
+    plan = None
+    if not args.no_tune:
+        # the launch plan: timed probes of every plan that keeps the batch's parity (untimed here)
+        plan = batch.autotune(ks, probe_iters=args.tune_probe, cache_path=args.tune_cache)
+        log("autotuned plan: %s" % plan)
 
     for s in range(args.warmup):
         run_step(batch, ks, shots, w.shot_seed)
@@ -609,7 +627,8 @@ def main():
         "config": {"workload": w.name, "instances": len(ks), "sum_k": sum_k, "precision": w.precision,
                    "storage": ("complex64 bulk sites, complex128 edge sites; every arithmetic step FP64"
                                if w.precision == "mixed" else "complex128"),
-                   "shots_per_instance": shots, "kernel": args.kernel, "description": w.description},
+                   "shots_per_instance": shots, "kernel": plan_name(args.kernel, plan), "autotune": plan,
+                   "description": w.description},
         "accuracy": {"max_abs_err_p": float(errs.max()), "tolerance": tol, "pass": bool(errs.max() <= tol),
                      "status_flags": int(np.bitwise_or.reduce(diag["status"]))},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
@@ -643,6 +662,7 @@ def main():
     if w.precision == "mixed" and not args.no_fp64_batch:
         if have(1.3 * step_s + 5):
             b64 = gmps.Batch(w.instances, "fp64", kernel=args.kernel)
+            plan64 = None if args.no_tune else b64.autotune(ks, probe_iters=args.tune_probe, cache_path=args.tune_cache)
             run_step(b64, ks, shots, w.shot_seed)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
@@ -652,7 +672,8 @@ def main():
             e64 = max(abs(p64[i] - exact_p(inst.n, inst.M, inst.k)) for i, inst in enumerate(w.instances))
             line["batched_fp64"] = {"value": sum_k / (t3 - t2), "unit": "iterations/s", "ms_per_step": (t3 - t2) * 1000.0,
                                     "kernel_ms": b64.last_iterate_ms(), "max_abs_err_p": e64,
-                                    "note": "same workload and step through the FP64 path, after an untimed step"}
+                                    "kernel": plan_name(args.kernel, plan64),
+                                    "note": "same workload and step through the FP64 path (autotuned), after an untimed step"}
             b64.close()
             log("batched fp64 leg done")
         else:
@@ -664,9 +685,9 @@ def main():
             log("pre-contracted legs done")
         else:
             skipped.append("precontracted")
-    fastest = [("mixed, bond-2 MPO reflections (the value)", line["value"])]
+    fastest = [("mixed, %s (the value)" % line["config"]["kernel"], line["value"])]
     if "batched_fp64" in line:
-        fastest.append(("fp64, bond-2 MPO reflections", line["batched_fp64"]["value"]))
+        fastest.append(("fp64, %s" % line["batched_fp64"]["kernel"], line["batched_fp64"]["value"]))
     if "precontracted" in line:
         fastest.append(("mixed, pre-contracted reflections", line["precontracted"]["mixed"]["value"]))
         fastest.append(("fp64, pre-contracted reflections", line["precontracted"]["fp64"]["value"]))

@@ -220,6 +220,33 @@ int gmps_amplitudes(gmps_batch* b, int32_t inst, const uint64_t* xs, int64_t cnt
  * rotation angle. out_reim: host [2]. Synchronises. */
 int gmps_overlap_uniform(gmps_batch* b, int32_t inst, double* out_reim);
 
+/* The launch plan grover_iterate uses, as chosen by gmps_autotune. */
+typedef struct {
+  int32_t pipeline;     /* 1: pipelined sweeps, -1: sequential sweeps                      */
+  int32_t precontract;  /* 1: pre-contracted reflections, -1: one bond-2 MPO per projector */
+  int32_t waves_per_cu; /* workgroups per CU and class kernel; 0: the occupancy limit      */
+  int32_t cached;       /* 1: taken from the cache file, 0: timed in this call             */
+  int32_t candidates;   /* plans this batch allows                                         */
+  int32_t reserved;
+  double ms;            /* probe time of the plan (timed in this call or when cached)      */
+} gmps_plan;
+
+/* Batch orchestration: picks grover_iterate's launch plan by timing short runs of every plan
+ * that keeps this batch's parity -- pipelined and sequential sweeps (pipelined only where
+ * gmps_options.pipeline may apply), pre-contracted reflections (GMPS_FP64 and lossless bond
+ * caps up to 17 only; on GMPS_MIXED their rotation angle drifts), and 0, 1 or 2 workgroups per CU and class
+ * kernel -- and switches the batch to the fastest. k: host, k_len == 1 or B, the iteration
+ * counts of the run to be tuned for; each probe scales them so that the longest chain runs
+ * probe_iters (>= 1) iterations, and is timed by HIP events after an untimed run that captures
+ * its graph. cache_path (may be NULL): a text file of "key pipeline precontract waves_per_cu ms"
+ * lines; the key hashes the device, the library's device sources, the precision, the kernel
+ * and the batch's (class, n, M, probe k) multiset. A cached plan is applied without timing; a
+ * timed one is appended (file errors are ignored). Leaves every instance at |s>, as
+ * mps_init_uniform does. out (may be NULL): the plan. Synchronises. Errors: GMPS_E_ARG,
+ * GMPS_E_HIP. */
+int gmps_autotune(gmps_batch* b, const int64_t* k, int32_t k_len, int32_t probe_iters, const char* cache_path,
+                  gmps_plan* out);
+
 /* Per-instance diagnostics; any pointer may be NULL. Synchronises.
  *  norm_drift:   host [B], largest |norm - 1| seen before a renormalisation
  *  trunc_weight: host [B], largest fraction of weight dropped by one truncation

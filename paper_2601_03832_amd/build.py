@@ -4,6 +4,7 @@
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -27,8 +28,19 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libgmps)")
 
 
+def source_hash() -> str:
+    """Hash of the device sources and the public headers; it keys the autotuner's plan cache."""
+    h = hashlib.sha256()
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for name in sorted(os.listdir(d)):
+            if name.endswith((".hip", ".h")):
+                with open(os.path.join(d, name), "rb") as f:
+                    h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
 def flags(extra=()):
-    return ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+    return ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, '-DGMPS_SOURCE_HASH="%s"' % source_hash(),
             # packed FP32 instructions are kept out of every kernel
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I" + os.path.join(ROOT, "include"), *extra]

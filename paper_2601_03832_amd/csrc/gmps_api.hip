@@ -5,8 +5,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
+#include <string>
 #include <mutex>
 #include <new>
 #include <unordered_set>
@@ -177,6 +179,11 @@ struct gmps_batch {
   hipEvent_t join_ev[kLaunchKinds] = {};
   // device address of this GPU's copy of the static sampling scratch (null if the lookup failed)
   char* scratch = nullptr;
+  // launch plans the autotuner may choose: pipelined sweeps (team kernel, no lossy cap) and
+  // pre-contracted reflections (team kernel, every bond cap <= 17)
+  bool pipeline_ok = false;
+  bool pc_ok = false;
+  std::string device_name;
 };
 
 // Scratch of sample_shots_noalloc: hit counters, shot offsets and bitstrings, in device memory
@@ -209,6 +216,13 @@ char* scratch_address(int dev) {
     g_scratch[dev] = static_cast<char*>(p);
   }
   return g_scratch[dev];
+}
+
+// Pre-contracted reflections: one reflection for the whole oracle when the cap keeps every
+// exact Schmidt rank (so no state exceeds rank M+1) and chi + M columns fit the class tile.
+bool whole_oracle(bool precontract, const InstDev& d) {
+  return precontract && is_wide(d.cls) && team_pc_class(d.cls - kWideBase) &&
+         d.cap == effective_cap(d.n, d.M, INT32_MAX) && d.M <= class_cm(d.cls);
 }
 
 __global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
@@ -331,9 +345,14 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   // A cap below the exact rank drops weight, and what a truncation drops depends on the sweep
   // order: such a batch keeps the sequential sweeps, whose truncations run right to left as
   // in the CPU oracle's MPS.
-  for (int i = 0; i < B && b->pipeline; ++i)
+  b->pipeline_ok = path == kPathTeam;
+  for (int i = 0; i < B; ++i)
     if (effective_cap(inst[i].n, inst[i].M, inst[i].chi_cap) < effective_cap(inst[i].n, inst[i].M, INT32_MAX))
-      b->pipeline = false;
+      b->pipeline_ok = false;
+  b->pipeline = b->pipeline && b->pipeline_ok;
+  b->pc_ok = path == kPathTeam;
+  for (int i = 0; i < B; ++i)
+    if (!(is_wide(cls[i]) && team_pc_class(cls[i] - kWideBase))) b->pc_ok = false;
   hipGetDevice(&b->device);
   b->scratch = scratch_address(b->device);
   hipDeviceProp_t prop;
@@ -342,6 +361,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     return GMPS_E_HIP;
   }
   b->num_cus = prop.multiProcessorCount;
+  b->device_name = std::string(prop.name) + "/" + prop.gcnArchName + "/" + std::to_string(b->num_cus);
 
   b->inst_h.resize(B);
   int64_t moff = 0;
@@ -353,10 +373,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     d.M = inst[i].M;
     d.cap = effective_cap(inst[i].n, inst[i].M, inst[i].chi_cap);
     d.cls = cls[i];
-    // one reflection for the whole oracle: the cap keeps every exact Schmidt rank (so no
-    // state exceeds rank M+1) and chi + M columns fit the class tile
-    d.whole = (precontract && is_wide(cls[i]) && team_pc_class(cls[i] - kWideBase) &&
-               d.cap == effective_cap(inst[i].n, inst[i].M, INT32_MAX) && inst[i].M <= class_cm(cls[i])) ? 1 : 0;
+    d.whole = whole_oracle(precontract, d) ? 1 : 0;
     d.marked_off = moff;
     d.site_off = site_off[i];
     d.warm_off = warm_off[i];
@@ -613,6 +630,154 @@ int gmps_last_iterate_ms(gmps_batch* b, double* ms) {
   float f = 0.f;
   GMPS_HIP(hipEventElapsedTime(&f, b->ev_start, b->ev_stop));
   *ms = f;
+  return GMPS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+#ifndef GMPS_SOURCE_HASH
+#define GMPS_SOURCE_HASH "unhashed"
+#endif
+
+uint64_t fnv1a(const std::string& t) {
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char c : t) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// Switches the batch to a launch plan: the flags the kernels and the bundling read, the
+// whole-oracle flag of every instance (device table rewritten; the caller re-initialises the
+// chain), and the cached graph, whose kernels the plan changes.
+int set_plan(gmps_batch* b, bool pipeline, bool precontract, int wpc) {
+  const bool pc_changed = precontract != b->precontract;
+  b->pipeline = pipeline;
+  b->precontract = precontract;
+  b->waves_per_cu = wpc;
+  if (pc_changed) {
+    for (auto& d : b->inst_h) d.whole = whole_oracle(precontract, d) ? 1 : 0;
+    GMPS_HIP(hipMemcpyAsync(b->params.inst, b->inst_h.data(), sizeof(InstDev) * b->B, hipMemcpyHostToDevice, b->stream));
+    GMPS_HIP(hipStreamSynchronize(b->stream));
+  }
+  if (b->graph) {
+    GMPS_HIP(hipStreamSynchronize(b->stream));
+    hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    b->graph_key.clear();
+  }
+  return GMPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gmps_autotune(gmps_batch* b, const int64_t* k, int32_t k_len, int32_t probe_iters, const char* cache_path,
+                  gmps_plan* out) {
+  if (!b || !k || (k_len != 1 && k_len != b->B) || probe_iters < 1) return GMPS_E_ARG;
+  int64_t kmax = 0;
+  for (int i = 0; i < k_len; ++i) {
+    if (k[i] < 0) return GMPS_E_ARG;
+    kmax = std::max(kmax, k[i]);
+  }
+  // the probe keeps the proportions of the run: the longest chain takes probe_iters iterations
+  std::vector<int64_t> kp(b->B);
+  for (int i = 0; i < b->B; ++i) {
+    const int64_t ki = k[k_len == 1 ? 0 : i];
+    kp[i] = ki == 0 ? 0 : std::max<int64_t>(1, (int64_t)std::llround((double)ki * probe_iters / (double)std::max<int64_t>(kmax, 1)));
+  }
+  // plans that keep the batch's parity: pipelined or sequential sweeps where the pipeline is
+  // allowed; pre-contracted reflections on FP64 with lossless caps only (on complex64 storage
+  // their angle drifts, and a lossy truncation is checked against the oracle on the
+  // per-projector reflections); the library's occupancy or one or two workgroups per CU and
+  // class kernel
+  struct Plan {
+    bool pipe, pc;
+    int wpc;
+  };
+  std::vector<Plan> plans;
+  const bool team = b->path == kPathTeam;
+  for (int pipe = 0; pipe < 2; ++pipe) {
+    if (pipe && !(team && b->pipeline_ok)) continue;
+    for (int pc = 0; pc < 2; ++pc) {
+      if (pc && !(team && b->pc_ok && b->pipeline_ok && !b->mixed)) continue;
+      for (int wpc : {0, 1, 2}) plans.push_back({pipe != 0, pc != 0, wpc});
+    }
+  }
+  // cache key: device, device sources, precision and the batch's (class, n, M, k) multiset
+  std::vector<std::string> items;
+  for (int i = 0; i < b->B; ++i) {
+    const InstDev& d = b->inst_h[i];
+    items.push_back(std::to_string(d.cls) + ":" + std::to_string(d.n) + ":" + std::to_string(d.M) + ":" +
+                    std::to_string(kp[i]));
+  }
+  std::sort(items.begin(), items.end());
+  std::string sig = b->device_name + "|" GMPS_SOURCE_HASH "|" + (b->fp32 ? "fp32" : b->mixed ? "mixed" : "fp64") +
+                    "|" + std::to_string(b->path) + "|" + std::to_string(probe_iters);
+  for (auto& t : items) sig += "|" + t;
+  char key[17];
+  std::snprintf(key, sizeof(key), "%016llx", (unsigned long long)fnv1a(sig));
+  gmps_plan best{};
+  bool found = false;
+  if (cache_path && *cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[256];
+      while (std::fgets(line, sizeof(line), f)) {
+        char kk[64];
+        int pp = 0, cc = 0, ww = 0;
+        double ms = 0.0;
+        if (std::sscanf(line, "%63s %d %d %d %lf", kk, &pp, &cc, &ww, &ms) == 5 && std::strcmp(kk, key) == 0) {
+          // a cached plan is used only if it is still one of this batch's candidates
+          for (auto& pl : plans)
+            if (pl.pipe == (pp > 0) && pl.pc == (cc > 0) && pl.wpc == ww) {
+              best.pipeline = pp > 0 ? 1 : -1;
+              best.precontract = cc > 0 ? 1 : -1;
+              best.waves_per_cu = ww;
+              best.ms = ms;
+              found = true;
+            }
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  int rc;
+  if (!found) {
+    double best_ms = 1e300;
+    for (auto& pl : plans) {
+      if ((rc = set_plan(b, pl.pipe, pl.pc, pl.wpc)) != GMPS_OK) return rc;
+      double ms = 1e300;
+      for (int rep = 0; rep < 2; ++rep) {  // the first run also captures the plan's graph
+        if ((rc = mps_init_uniform(b)) != GMPS_OK) return rc;
+        if ((rc = grover_iterate(b, kp.data(), b->B)) != GMPS_OK) return rc;
+        double t = 0.0;
+        if ((rc = gmps_last_iterate_ms(b, &t)) != GMPS_OK) return rc;
+        if (rep > 0) ms = t;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best.pipeline = pl.pipe ? 1 : -1;
+        best.precontract = pl.pc ? 1 : -1;
+        best.waves_per_cu = pl.wpc;
+        best.ms = ms;
+      }
+    }
+    if (cache_path && *cache_path) {
+      if (FILE* f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "%s %d %d %d %.6f\n", key, best.pipeline, best.precontract, best.waves_per_cu, best.ms);
+        std::fclose(f);
+      }
+    }
+  }
+  if ((rc = set_plan(b, best.pipeline > 0, best.precontract > 0, best.waves_per_cu)) != GMPS_OK) return rc;
+  if ((rc = mps_init_uniform(b)) != GMPS_OK) return rc;
+  best.cached = found ? 1 : 0;
+  best.candidates = (int32_t)plans.size();
+  if (out) *out = best;
   return GMPS_OK;
 }
 

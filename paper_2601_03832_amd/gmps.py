@@ -29,7 +29,7 @@ BOND_STRIDE = 64
 KERNELS = {"auto": 0, "group": 1, "team": 2}
 
 EXPORTED = ("gmps_workspace_bytes", "gmps_create", "mps_init_uniform", "grover_iterate", "marked_prob",
-            "sample_shots", "sample_shots_noalloc", "gmps_amplitudes", "gmps_overlap_uniform", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
+            "sample_shots", "sample_shots_noalloc", "gmps_amplitudes", "gmps_overlap_uniform", "gmps_autotune", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
             "gmps_strerror", "gsv_workspace_bytes", "gsv_create", "gsv_init_uniform", "gsv_iterate",
             "gsv_marked_prob", "gsv_amplitudes", "gsv_last_iterate_ms", "gsv_destroy")
 
@@ -45,6 +45,12 @@ class GmpsOptions(ctypes.Structure):
                 ("round_mode", ctypes.c_int32), ("jacobi_warm", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("precontract", ctypes.c_int32),
                 ("pipeline", ctypes.c_int32)]
+
+
+class GmpsPlan(ctypes.Structure):
+    _fields_ = [("pipeline", ctypes.c_int32), ("precontract", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("cached", ctypes.c_int32), ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 class GmpsError(RuntimeError):
@@ -86,6 +92,8 @@ def load(path: Optional[str] = None):
     lib.gmps_amplitudes.argtypes = [P, i32, ctypes.POINTER(u64), i64, ctypes.POINTER(dbl)]
     lib.gmps_overlap_uniform.restype = ctypes.c_int
     lib.gmps_overlap_uniform.argtypes = [P, i32, ctypes.POINTER(dbl)]
+    lib.gmps_autotune.restype = ctypes.c_int
+    lib.gmps_autotune.argtypes = [P, ctypes.POINTER(i64), i32, i32, ctypes.c_char_p, ctypes.POINTER(GmpsPlan)]
     lib.gmps_diagnostics.restype = ctypes.c_int
     lib.gmps_diagnostics.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(i32),
                                      ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl)]
@@ -223,6 +231,17 @@ class Batch:
     def iterate(self, k):
         ks = np.ascontiguousarray(np.atleast_1d(np.asarray(k, dtype=np.int64)))
         self._check(self.lib.grover_iterate(self.handle, _ptr(ks, ctypes.c_int64), len(ks)), "grover_iterate")
+
+    def autotune(self, k, probe_iters: int = 64, cache_path: Optional[str] = None) -> dict:
+        """gmps_autotune: time the launch plans this batch allows on a probe scaled from the
+        iteration counts k, switch to the fastest, leave every instance at |s>."""
+        ks = np.ascontiguousarray(np.atleast_1d(np.asarray(k, dtype=np.int64)))
+        plan = GmpsPlan()
+        path = cache_path.encode() if cache_path else None
+        self._check(self.lib.gmps_autotune(self.handle, _ptr(ks, ctypes.c_int64), len(ks), int(probe_iters), path,
+                                           ctypes.byref(plan)), "gmps_autotune")
+        return {"pipeline": plan.pipeline > 0, "precontract": plan.precontract > 0, "waves_per_cu": plan.waves_per_cu,
+                "cached": bool(plan.cached), "candidates": plan.candidates, "probe_ms": plan.ms}
 
     def marked_prob(self, allow_numeric: bool = False) -> np.ndarray:
         out = np.zeros(self.B, dtype=np.float64)

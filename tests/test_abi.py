@@ -144,7 +144,8 @@ def test_binding_refuses_to_run_without_a_gpu():
 
 
 def test_struct_layouts_match_the_binding(tmp_path):
-    """The ctypes mirrors of gmps_options and gmps_instance have the header's field offsets."""
+    """The ctypes mirrors of gmps_options, gmps_instance and gmps_plan have the header's field
+    offsets."""
     import shutil
     import subprocess
     cc = shutil.which("gcc") or shutil.which("cc")
@@ -153,10 +154,13 @@ def test_struct_layouts_match_the_binding(tmp_path):
     src = tmp_path / "layout.c"
     opt_fields = [f for f, _ in gmps.GmpsOptions._fields_]
     inst_fields = [f for f, _ in gmps.GmpsInstance._fields_]
+    plan_fields = [f for f, _ in gmps.GmpsPlan._fields_]
     body = ["#include <stdio.h>", "#include <stddef.h>", '#include "gmps.h"', "int main(void) {",
-            'printf("%zu\\n", sizeof(gmps_options));', 'printf("%zu\\n", sizeof(gmps_instance));']
+            'printf("%zu\\n", sizeof(gmps_options));', 'printf("%zu\\n", sizeof(gmps_instance));',
+            'printf("%zu\\n", sizeof(gmps_plan));']
     body += ['printf("%%zu\\n", offsetof(gmps_options, %s));' % f for f in opt_fields]
     body += ['printf("%%zu\\n", offsetof(gmps_instance, %s));' % f for f in inst_fields]
+    body += ['printf("%%zu\\n", offsetof(gmps_plan, %s));' % f for f in plan_fields]
     body += ["return 0; }"]
     src.write_text("\n".join(body) + "\n")
     exe = tmp_path / "layout"
@@ -164,8 +168,10 @@ def test_struct_layouts_match_the_binding(tmp_path):
     vals = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     assert vals[0] == ctypes.sizeof(gmps.GmpsOptions)
     assert vals[1] == ctypes.sizeof(gmps.GmpsInstance)
-    offs = vals[2:]
-    got = [getattr(gmps.GmpsOptions, f).offset for f in opt_fields] + [getattr(gmps.GmpsInstance, f).offset for f in inst_fields]
+    assert vals[2] == ctypes.sizeof(gmps.GmpsPlan)
+    offs = vals[3:]
+    got = [getattr(gmps.GmpsOptions, f).offset for f in opt_fields] + [getattr(gmps.GmpsInstance, f).offset for f in inst_fields] + \
+        [getattr(gmps.GmpsPlan, f).offset for f in plan_fields]
     assert offs == got
 
 

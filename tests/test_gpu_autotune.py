@@ -1,0 +1,81 @@
+"""gmps_autotune: the plan it picks is one of the batch's candidates, a cached plan is applied
+without timing, and the batch still meets the parity bar under the chosen plan."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import closed_form as cf
+from paper_2601_03832_amd import gmps, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _check_p(b, insts, tol):
+    p = b.marked_prob(allow_numeric=True)
+    for i, inst in enumerate(insts):
+        assert abs(p[i] - cf.p_marked(inst.n, inst.M, inst.k)) <= tol, (i, inst.n, inst.M, p[i])
+
+
+@pytest.mark.parametrize("precision,tol,candidates", [("fp64", 1e-10, 12), ("mixed", 1e-6, 6)])
+def test_autotune_picks_a_candidate_and_caches_it(gpu, tmp_path, precision, tol, candidates):
+    insts = inputs.random_batch(48, 8, 18, (1, 2, 4), seed=515, k_scale=0.7, cap_extra=2)
+    ks = [i.k for i in insts]
+    cache = str(tmp_path / "plans.txt")
+    say("case: autotune %s, 48 instances, probe 16" % precision)
+    b = gmps.Batch(insts, precision, kernel="team")
+    plan = b.autotune(ks, probe_iters=16, cache_path=cache)
+    say("  plan %s" % plan)
+    assert plan["candidates"] == candidates and not plan["cached"]
+    assert plan["waves_per_cu"] in (0, 1, 2) and plan["probe_ms"] > 0
+    if precision == "mixed":
+        assert not plan["precontract"]  # excluded: its rotation angle drifts on complex64 storage
+    # the chain is left at |s>: iterating the full k meets the bar under the chosen plan
+    b.iterate(ks)
+    _check_p(b, insts, tol)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1
+    # a second handle over the same batch takes the plan from the cache
+    b2 = gmps.Batch(insts, precision, kernel="team")
+    plan2 = b2.autotune(ks, probe_iters=16, cache_path=cache)
+    assert plan2["cached"]
+    assert {k: plan2[k] for k in ("pipeline", "precontract", "waves_per_cu")} == \
+        {k: plan[k] for k in ("pipeline", "precontract", "waves_per_cu")}
+    b2.iterate(ks)
+    _check_p(b2, insts, tol)
+    assert len(open(cache).read().splitlines()) == 1
+    b.close()
+    b2.close()
+
+
+def test_autotune_keeps_sequential_sweeps_for_a_lossy_cap(gpu):
+    """A cap below the exact rank makes the truncation order part of the result: only the
+    sequential per-projector plans are candidates, and the tuned batch follows the oracle's P."""
+    rng = inputs.SplitMix64(516)
+    insts = [inputs.Instance(10, inputs.draw_marked(10, 6, rng), 6, 5)]
+    b = gmps.Batch(insts, "fp64", kernel="team")
+    plan = b.autotune([6], probe_iters=4)
+    say("  lossy plan %s" % plan)
+    assert not plan["pipeline"] and not plan["precontract"] and plan["candidates"] == 3
+    b.iterate([6])
+    from oracle import mps as omps
+    ref = omps.run(10, insts[0].marked, 6, 5)
+    # the dropped weight shows as norm drift and truncation flags; P is still the oracle's
+    assert b.diagnostics()["status"][0] & gmps.ST_TRUNC
+    assert abs(b.marked_prob(allow_numeric=True)[0] - ref.marked_prob()) < 1e-10
+    b.close()
+
+
+def test_autotune_rejects_bad_arguments(gpu):
+    insts = inputs.random_batch(3, 6, 8, (1,), seed=517)
+    b = gmps.Batch(insts, "fp64")
+    for args in (([1, 2], 8), ([-1], 8), ([5], 0)):
+        with pytest.raises(gmps.GmpsError) as e:
+            b.autotune(args[0], probe_iters=args[1])
+        assert e.value.code == gmps.GMPS_E_ARG
+    b.close()
