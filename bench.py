@@ -1,8 +1,9 @@
 """Benchmark: Grover iterations/s on one MI355X, batched mixed precision vs plain FP64.
 
 One step is one pass of the whole hot path over the batched workload: every instance is
-reset to |s> (mps_init_uniform), iterated to its own k (grover_iterate, one persistent
-launch), read out (marked_prob) and sampled (sample_shots). value = sum_i k_i / step time.
+reset to |s> (mps_init_uniform), iterated to its own k and sampled in the same graph launch
+(grover_iterate_sample: the persistent class kernels, then perfect sampling of every final
+state), and read out (marked_prob). value = sum_i k_i / step time.
 The accuracy gate requires |P_i - sin^2((2k_i+1) theta_i)| <= 1e-6 for every instance.
 
     python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--workload c4|c2|c3] [--kernel auto|team|group]
@@ -148,10 +149,15 @@ def plan_name(kernel: str, plan) -> str:
 
 
 def run_step(batch, ks, shots, seed):
+    """One pass of the hot path: reset, iterate and (with shots) sample in one graph launch,
+    then the marked probability of every instance."""
     batch.init_uniform()
-    batch.iterate(ks)
+    if shots:
+        hits = batch.iterate_sample(ks, shots, seed)
+    else:
+        batch.iterate(ks)
+        hits = None
     p = batch.marked_prob(allow_numeric=True)
-    _, hits = batch.sample(shots, seed) if shots else (None, None)
     return p, hits
 
 

@@ -178,6 +178,17 @@ int mps_init_uniform(gmps_batch* b);
  * (per-instance, each >= 0). Additive: k_done += k. Asynchronous. */
 int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len);
 
+/* grover_iterate and then perfect sampling of every instance's final state in the same graph
+ * launch (a hit-counter fill kernel, the class kernels, the sampling kernel), for runs that
+ * need the hit counts only. The draws are sample_shots' (same Philox stream, seed and shot
+ * numbering), so out_hits equals sample_shots' out_hits after grover_iterate. shots: host,
+ * shots_len == 1 or B (each >= 0); the shot offsets pass through the workspace's staging region.
+ * out_hits: host [B] (may be NULL). gmps_last_iterate_ms then covers the sampling too.
+ * Synchronises. Errors: GMPS_E_ARG, GMPS_E_WORKSPACE (B + 1 offsets beyond the staging
+ * region), GMPS_E_HIP. */
+int grover_iterate_sample(gmps_batch* b, const int64_t* k, int32_t k_len, const int64_t* shots, int32_t shots_len,
+                          uint64_t seed, int64_t* out_hits);
+
 /* Eq. (6): out_p[i] = sum_{x in W_i} |<x|psi_i>|^2 / <psi_i|psi_i>, accumulated in FP64.
  * out_p: host [B]. Synchronises. Returns GMPS_E_NUMERIC if any status bit is set. */
 int marked_prob(gmps_batch* b, double* out_p);

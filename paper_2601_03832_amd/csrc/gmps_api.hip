@@ -445,10 +445,57 @@ int mps_init_uniform(gmps_batch* b) {
   return GMPS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Sampling appended to an iterate launch: hits only, every instance of the batch.
+struct SampleReq {
+  const int64_t* shot_off;  // device [B + 1], in the staging region
+  int64_t total;
+  uint64_t seed;
+};
+
+int iterate_impl(gmps_batch* b, const int64_t* k, int32_t k_len, const SampleReq* smp);
+
+}  // namespace
+
+extern "C" {
+
 int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
   if (!b || !k || (k_len != 1 && k_len != b->B)) return GMPS_E_ARG;
   for (int i = 0; i < k_len; ++i)
     if (k[i] < 0) return GMPS_E_ARG;
+  return iterate_impl(b, k, k_len, nullptr);
+}
+
+int grover_iterate_sample(gmps_batch* b, const int64_t* k, int32_t k_len, const int64_t* shots, int32_t shots_len,
+                          uint64_t seed, int64_t* out_hits) {
+  if (!b || !k || (k_len != 1 && k_len != b->B) || !shots || (shots_len != 1 && shots_len != b->B)) return GMPS_E_ARG;
+  for (int i = 0; i < k_len; ++i)
+    if (k[i] < 0) return GMPS_E_ARG;
+  for (int i = 0; i < shots_len; ++i)
+    if (shots[i] < 0) return GMPS_E_ARG;
+  if (align_up(sizeof(int64_t) * ((size_t)b->B + 1)) > kStageBytes) return GMPS_E_WORKSPACE;
+  // the shot offsets go to the staging region ahead of the graph launch that reads them
+  std::vector<int64_t> off(b->B + 1, 0);
+  for (int i = 0; i < b->B; ++i) off[i + 1] = off[i] + shots[shots_len == 1 ? 0 : i];
+  int64_t* doff = reinterpret_cast<int64_t*>(b->ws + b->lay.stage);
+  GMPS_HIP(hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (b->B + 1), hipMemcpyHostToDevice, b->stream));
+  SampleReq smp{doff, off[b->B], seed};
+  int rc = iterate_impl(b, k, k_len, &smp);
+  if (rc != GMPS_OK) return rc;
+  if (out_hits)
+    GMPS_HIP(hipMemcpyAsync(out_hits, b->ws + b->lay.hits, sizeof(int64_t) * b->B, hipMemcpyDeviceToHost, b->stream));
+  GMPS_HIP(hipStreamSynchronize(b->stream));  // also keeps off alive until the copy has run
+  return GMPS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int iterate_impl(gmps_batch* b, const int64_t* k, int32_t k_len, const SampleReq* smp) {
   // Bundle instances that share (class, n, M, k), then order each kernel's bundles by
   // estimated cost, longest first, so the persistent queue hands out the long serial
   // chains early.
@@ -510,7 +557,7 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
     b->queue_pin[kd].next = 0;
     b->queue_pin[kd].nbundles = count[kd];
   }
-  if (nb == 0) return GMPS_OK;
+  if (nb == 0 && !smp) return GMPS_OK;
   GMPS_HIP(hipMemcpyAsync(b->ws + b->lay.bundles, b->bundles_pin, sizeof(Bundle) * nb, hipMemcpyHostToDevice,
                           b->stream));
   GMPS_HIP(hipMemcpyAsync(b->ws + b->lay.queue, b->queue_pin, sizeof(QueueState) * kLaunchKinds, hipMemcpyHostToDevice,
@@ -543,6 +590,8 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
       grid[kd] = std::max(1, std::min(grid[kd], (int)(cap_wg[kd] * work[kd] / work_total)));
     key.insert(key.end(), {kd, grid[kd], (int64_t)lds[kd], first[kd]});
   }
+  // sampling appended to the launch: its total and seed are kernel arguments of the graph
+  if (smp) key.insert(key.end(), {-1, smp->total, (int64_t)smp->seed});
   Bundle* dev_bundles = reinterpret_cast<Bundle*>(b->ws + b->lay.bundles);
   QueueState* dev_queue = reinterpret_cast<QueueState*>(b->ws + b->lay.queue);
   // the kernels of different classes run side by side: the first on st, the others on side
@@ -556,8 +605,15 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
       GMPS_HIP(hipEventCreateWithFlags(&b->join_ev[kd], hipEventDisableTiming));
     }
   }
+  unsigned long long* dhits = reinterpret_cast<unsigned long long*>(b->ws + b->lay.hits);
   auto launch_all = [&](hipStream_t st) -> hipError_t {
-    hipError_t e = launch_queue_reset(dev_queue, st);
+    hipError_t e = hipSuccess;
+    if (smp) {
+      // hit counters cleared by a kernel: no memset node in the graph
+      hipLaunchKernelGGL(zero_u64_kernel, dim3((b->B + 255) / 256), dim3(256), 0, st, dhits, (int64_t)b->B);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = launch_queue_reset(dev_queue, st);
     if (e == hipSuccess && nkinds > 1) e = hipEventRecord(b->fork_ev, st);
     bool on_main = true;
     for (int kd = 0; kd < kLaunchKinds && e == hipSuccess; ++kd) {
@@ -587,6 +643,10 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
       }
       on_main = false;
     }
+    // perfect sampling of every final state, after the class kernels have joined
+    if (e == hipSuccess && smp && smp->total > 0)
+      e = launch_sample(b->mixed, b->max_cm, b->params.inst, b->params.marked, b->params.bonds, b->params.arena,
+                        readout_edge(b), b->B, 0, smp->shot_off, smp->total, smp->seed, nullptr, dhits, st);
     return e;
   };
 
@@ -619,6 +679,10 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
   b->timed = true;
   return GMPS_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int gmps_last_iterate_ms(gmps_batch* b, double* ms) {
   if (!b || !ms) return GMPS_E_ARG;

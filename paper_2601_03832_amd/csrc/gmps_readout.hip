@@ -347,7 +347,7 @@ __global__ void sample_kernel(const InstDev* inst, const uint64_t* marked, const
     if (!zero) x |= 1ull << (n - 1 - i);
     chl = chr;
   }
-  bits[t] = x;
+  if (bits) bits[t] = x;  // null: hits only
   for (int j = 0; j < I.M; ++j)
     if (marked[I.marked_off + j] == x) {
       atomicAdd(hits + lo, 1ull);

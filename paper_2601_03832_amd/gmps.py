@@ -28,7 +28,7 @@ ST_NAN, ST_DRIFT, ST_TRUNC = 1, 2, 4
 BOND_STRIDE = 64
 KERNELS = {"auto": 0, "group": 1, "team": 2}
 
-EXPORTED = ("gmps_workspace_bytes", "gmps_create", "mps_init_uniform", "grover_iterate", "marked_prob",
+EXPORTED = ("gmps_workspace_bytes", "gmps_create", "mps_init_uniform", "grover_iterate", "grover_iterate_sample", "marked_prob",
             "sample_shots", "sample_shots_noalloc", "gmps_amplitudes", "gmps_overlap_uniform", "gmps_autotune", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
             "gmps_strerror", "gsv_workspace_bytes", "gsv_create", "gsv_init_uniform", "gsv_iterate",
             "gsv_marked_prob", "gsv_amplitudes", "gsv_last_iterate_ms", "gsv_destroy")
@@ -82,6 +82,9 @@ def load(path: Optional[str] = None):
     lib.mps_init_uniform.argtypes = [P]
     lib.grover_iterate.restype = ctypes.c_int
     lib.grover_iterate.argtypes = [P, ctypes.POINTER(i64), i32]
+    lib.grover_iterate_sample.restype = ctypes.c_int
+    lib.grover_iterate_sample.argtypes = [P, ctypes.POINTER(i64), i32, ctypes.POINTER(i64), i32, u64,
+                                          ctypes.POINTER(i64)]
     lib.marked_prob.restype = ctypes.c_int
     lib.marked_prob.argtypes = [P, ctypes.POINTER(dbl)]
     lib.sample_shots.restype = ctypes.c_int
@@ -242,6 +245,17 @@ class Batch:
                                            ctypes.byref(plan)), "gmps_autotune")
         return {"pipeline": plan.pipeline > 0, "precontract": plan.precontract > 0, "waves_per_cu": plan.waves_per_cu,
                 "cached": bool(plan.cached), "candidates": plan.candidates, "probe_ms": plan.ms}
+
+    def iterate_sample(self, k, shots, seed: int) -> np.ndarray:
+        """grover_iterate_sample: iterate, then sample every final state in the same graph
+        launch; returns the per-instance hit counts."""
+        ks = np.ascontiguousarray(np.atleast_1d(np.asarray(k, dtype=np.int64)))
+        sh = np.ascontiguousarray(np.atleast_1d(np.asarray(shots, dtype=np.int64)))
+        hits = np.zeros(self.B, dtype=np.int64)
+        self._check(self.lib.grover_iterate_sample(self.handle, _ptr(ks, ctypes.c_int64), len(ks),
+                                                   _ptr(sh, ctypes.c_int64), len(sh), ctypes.c_uint64(seed),
+                                                   _ptr(hits, ctypes.c_int64)), "grover_iterate_sample")
+        return hits
 
     def marked_prob(self, allow_numeric: bool = False) -> np.ndarray:
         out = np.zeros(self.B, dtype=np.float64)
