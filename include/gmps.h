@@ -36,11 +36,9 @@
  *    application and the site contractions in complex64 and the factorisations in FP64 on
  *    up-converted tiles. Either way Schmidt components below trunc_tol (5e-7) of the
  *    largest are dropped. Accuracy of the team kernel's GMPS_MIXED, measured against the
- *    rotation angle (2k+1) theta: at n <= 29 the angle error stays near 1e-8 with bond-2 MPO
- *    reflections; pre-contracted reflections (precontract = 1) drift by up to 3e-10 per
- *    iteration at M = 4 (1e-6 over a 3000-iteration run). At n = 40, where the marked
- *    amplitudes start at ~2^-20, the angle drifts by ~2e-9 (MPO) and ~3e-10 (pre-contracted)
- *    per iteration, far beyond 1e-6 in P over the full k: such runs need GMPS_FP64. Near the
+ *    rotation angle (2k+1) theta: at n <= 29 the angle error stays near 1e-8. At n = 40,
+ *    where the marked amplitudes start at ~2^-20, the angle drifts by ~2e-9 per iteration, far
+ *    beyond 1e-6 in P over the full k: such runs need GMPS_FP64. Near the
  *    peak of P, in the one iteration where the unmarked component passes through a few
  *    1e-6, the mixed path's rotation angle (2k+1) theta can shift by up to about 2e-6 rad;
  *    P, flat there, moves by ~1e-12, but the shift stays with the state if it is iterated
@@ -123,8 +121,9 @@ typedef struct {
                            team of 16-256 threads; bond caps up to 32), 0 = library choice
                            (the team kernel; the lane-group kernel for GMPS_FP32) */
   int32_t precontract;  /* 1: projector pre-contraction, a recompression variant of Section III-B
-                           (team kernel only; with kernel = 1, or with an instance whose effective
-                           bond cap exceeds 17, gmps_create returns GMPS_E_UNSUPPORTED). A reflection
+                           (team kernel and GMPS_FP64 only; with kernel = 1, another precision, or
+                           an instance whose effective bond cap exceeds 17, gmps_create returns
+                           GMPS_E_UNSUPPORTED). A reflection
                            c0 I + c1 sum_t |p_t><p_t| over product states p_t (Eqs. (3)-(4): the
                            marked basis states for O, |s> for D) maps psi to
                            c0 psi + c1 sum_t <p_t|psi> p_t, an MPS of bond chi + T built from
@@ -134,12 +133,12 @@ typedef struct {
                            and M fits the tile class, O is one reflection with T = M, so an
                            iteration takes two QR+SVD sweeps instead of M+1; otherwise each
                            marked index is one reflection with T = 1. Same result up to
-                           rounding on GMPS_FP64. On GMPS_MIXED the rotation angle drifts by up
-                           to ~3e-10 per iteration (M = 4, n <= 28; also at n = 40), against
-                           ~2e-12 with the bond-2 MPOs: the exact product terms add directions
-                           outside the complex64-rounded bond spaces, which the M+1 cap cuts with
-                           a little in-plane weight. 0 or -1 (default): one bond-2 MPO per
-                           projector, as in the paper. */
+                           rounding. It is refused on GMPS_MIXED: with complex64 storage the exact
+                           product terms add directions outside the rounded bond spaces, which the
+                           M+1 cap cuts with some in-plane weight (the angle drifted by up to 3e-10
+                           per iteration at M = 4, and at n = 40, M = 16 truncations ran away and
+                           one instance lost 60% of P within 5000 iterations). 0 or -1 (default):
+                           one bond-2 MPO per projector, as in the paper. */
   int32_t pipeline;     /* 0 or 1 (default): the team classes with bond caps 2, 3, 5 and 8 run
                            the per-projector reflections with alternating sweep directions on
                            two waves, the truncation sweep of each reflection and the
@@ -163,7 +162,8 @@ size_t gmps_workspace_bytes(const gmps_instance* inst, int32_t B, gmps_prec prec
  * The chain is left uninitialised: call mps_init_uniform() next.
  * Errors: GMPS_E_ARG (bad instance, duplicate or out-of-range marked index, unknown
  * kernel or precision), GMPS_E_WORKSPACE, GMPS_E_UNSUPPORTED (no tile class holds the bond
- * cap; precontract without the team kernel or with an effective bond cap above 17; GMPS_FP32
+ * cap; precontract without the team kernel, on another precision than GMPS_FP64 or with an
+ * effective bond cap above 17; GMPS_FP32
  * with kernel = 2 or an effective bond cap above 6), GMPS_E_HIP. */
 int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const uint64_t* marked,
                 gmps_prec prec, const gmps_options* opt, void* dev_workspace, size_t ws_bytes,

@@ -289,7 +289,10 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   if (fp32 && opt && opt->kernel == kPathTeam) return GMPS_E_UNSUPPORTED;
   const int path = fp32 ? kPathGroup : resolve_path(opt ? opt->kernel : kPathAuto);
   const bool precontract = opt && opt->precontract > 0;
-  if (precontract && path != kPathTeam) return GMPS_E_UNSUPPORTED;
+  // pre-contracted reflections run on the team kernel in FP64 only: on complex64 storage the
+  // exact product terms leave directions outside the rounded bond spaces, which the bond cap
+  // cuts with some of the state (a drifting angle, and at n = 40 runaway truncations)
+  if (precontract && (path != kPathTeam || prec != GMPS_FP64)) return GMPS_E_UNSUPPORTED;
   Layout L;
   std::vector<int> cls;
   std::vector<int64_t> site_off, warm_off, edge_off;

@@ -1999,21 +1999,20 @@ hipError_t launch_team_pc_w(bool mixed, const IterParams& P, int grid, size_t ld
 template <int W>
 hipError_t occupancy_team_pc_w(bool mixed, size_t lds, int* blocks_per_cu);
 
+// Instantiated for FP64 storage only: gmps_create refuses pre-contraction on the mixed path.
 #define GMPS_TEAM_PC_CLASS(W)                                                                        \
   template <>                                                                                        \
   hipError_t launch_team_pc_w<W>(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st) { \
     constexpr int nt = kWide[W].TW < 64 ? 64 : kWide[W].TW;                                           \
-    if (mixed)                                                                                       \
-      grover_team_pc_kernel<float, W><<<grid, nt, lds, st>>>(P);                                      \
-    else                                                                                             \
-      grover_team_pc_kernel<double, W><<<grid, nt, lds, st>>>(P);                                     \
+    if (mixed) return hipErrorInvalidValue;                                                          \
+    grover_team_pc_kernel<double, W><<<grid, nt, lds, st>>>(P);                                       \
     return hipGetLastError();                                                                        \
   }                                                                                                  \
   template <>                                                                                        \
   hipError_t occupancy_team_pc_w<W>(bool mixed, size_t lds, int* blocks_per_cu) {                   \
     constexpr int nt = kWide[W].TW < 64 ? 64 : kWide[W].TW;                                           \
-    return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_team_pc_kernel<float, W>, nt, lds) \
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_team_pc_kernel<double, W>, nt, lds); \
+    if (mixed) return hipErrorInvalidValue;                                                          \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_team_pc_kernel<double, W>, nt, lds); \
   }
 
 }  // namespace gmps

@@ -24,8 +24,9 @@ Single unmarked amplitudes carry errors outside the span of |s> and the marked s
 sees only at second order; they are checked element by element against the statevector oracle
 in the smaller parity tests.
 
-Cases: the 4096-instance mixed batch (n 12..28, M 1/2/4, own k) at half and full k on every
-team-kernel variant with 4096 shots per instance against the binomial law; the longest chain of
+Cases: the 4096-instance mixed batch (n 12..28, M 1/2/4, own k) at half and full k on the
+pipelined and sequential sweeps with 4096 shots per instance against the binomial law, and the
+same batch in FP64 through the pre-contracted reflections; the longest chain of
 that batch (n=28, M=4) every 500 iterations; n=29, k=18198 (the precision study) every 1000
 iterations, FP64 and mixed.
 """
@@ -70,7 +71,7 @@ def check_angle(b, idx, inst, k, precision, label=""):
     return dphi, spread
 
 
-@pytest.mark.parametrize("pc,pipe", [(False, True), (False, False), (True, True)], ids=["mpo", "mpo-seq", "precontract"])
+@pytest.mark.parametrize("pc,pipe", [(False, True), (False, False)], ids=["mpo", "mpo-seq"])
 def test_batched_mixed_full_size(gpu, pc, pipe):
     say("case: 4096-instance mixed batch, half and full k, precontract=%s pipeline=%s" % (pc, pipe))
     w = inputs.config_c4()
@@ -107,6 +108,31 @@ def test_batched_mixed_full_size(gpu, pc, pipe):
         sd = math.sqrt(4096 * q * (1 - q)) + 1.0
         assert abs(hits[i] - 4096 * q) <= 6 * sd, (i, hits[i], q)
     say("sampling ok")
+
+
+def test_batched_fp64_precontracted_full_size(gpu):
+    """The 4096-instance workload in FP64 through the pre-contracted reflections (the fastest
+    path): P of every instance at half and full k, and 4096-shot hit counts."""
+    say("case: 4096-instance batch, fp64, pre-contracted reflections, half and full k")
+    w = inputs.config_c4()
+    ks = np.array([i.k for i in w.instances])
+    half = ks // 2
+    b = gmps.Batch(w.instances, "fp64", precontract=True)
+    b.init_uniform()
+    for stage, kk, step in (("half k", half, half), ("full k", ks, ks - half)):
+        b.iterate(step)
+        p = b.marked_prob()
+        exp = np.array([cf.p_marked(i.n, i.M, int(kk[j])) for j, i in enumerate(w.instances)])
+        err = np.abs(p - exp)
+        say("  %s: max |dP| = %.3g" % (stage, err.max()))
+        assert err.max() <= TOL["fp64"], (stage, int(np.argmax(err)))
+    exp = np.array([cf.p_marked(i.n, i.M, i.k) for i in w.instances])
+    _, hits = b.sample(4096, w.shot_seed)
+    for i in range(len(w.instances)):
+        q = exp[i]
+        sd = math.sqrt(4096 * q * (1 - q)) + 1.0
+        assert abs(hits[i] - 4096 * q) <= 6 * sd, (i, hits[i], q)
+    b.close()
 
 
 @pytest.mark.parametrize("pipe", [True, False], ids=["pipelined", "sequential"])

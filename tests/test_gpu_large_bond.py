@@ -31,8 +31,8 @@ def bound_ok(prof, n, M):
     return all(prof[l] <= min(2 ** l, 2 ** (n - l), M + 1) for l in range(1, n))
 
 
-@pytest.mark.parametrize("pc", [False, True], ids=["mpo", "precontract"])
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision,pc", [("fp64", False), ("fp64", True), ("mixed", False)],
+                         ids=["fp64-mpo", "fp64-precontract", "mixed-mpo"])
 def test_large_cap_small_n_statevector(gpu, precision, pc):
     say("case: large caps at small n, %s, precontract=%s" % (precision, pc))
     rng = inputs.SplitMix64(4711)
@@ -66,15 +66,20 @@ def test_large_cap_small_n_statevector(gpu, precision, pc):
         assert d["status"][i] == 0
 
 
-def test_precontract_beyond_bond_17_is_refused(gpu):
-    """The pre-contracted variant is not built for the bond-32 class: gmps_create refuses it
-    rather than running the MPO reflections under the pre-contract flag."""
+def test_precontract_beyond_bond_17_or_on_mixed_is_refused(gpu):
+    """The pre-contracted variant is not built for the bond-32 class, and it runs on FP64
+    only: gmps_create refuses both rather than running something else under the flag."""
     W = inputs.draw_marked(12, 24, inputs.SplitMix64(4712))
     inst = inputs.Instance(12, W, inputs.k_rule(12, 24), 27)
     for precision in ("fp64", "mixed"):
         with pytest.raises(gmps.GmpsError) as e:
             gmps.Batch([inst], precision, kernel="team", precontract=True)
         assert e.value.code == gmps.GMPS_E_UNSUPPORTED
+    small = inputs.Instance(12, W[:4], inputs.k_rule(12, 4), 6)
+    with pytest.raises(gmps.GmpsError) as e:
+        gmps.Batch([small], "mixed", kernel="team", precontract=True)
+    assert e.value.code == gmps.GMPS_E_UNSUPPORTED
+    gmps.Batch([small], "fp64", kernel="team", precontract=True).close()
 
 
 @pytest.mark.skip(reason="the pre-contracted kernel of the bond-32 class (CM = 32, 256-thread teams) is not "

@@ -43,6 +43,12 @@ def say(msg):
 
 
 def run(instances, precision, k=None, kernel="auto", **kw):
+    if kernel == "team-pc" and precision != "fp64":
+        # pre-contracted reflections are refused on the mixed path: check that, then skip
+        with pytest.raises(gmps.GmpsError) as e:
+            gmps.Batch(instances, precision, **batch_kw(kernel), **kw)
+        assert e.value.code == gmps.GMPS_E_UNSUPPORTED
+        pytest.skip("pre-contracted reflections run on FP64 only (the refusal was checked)")
     b = gmps.Batch(instances, precision, **batch_kw(kernel), **kw)
     b.init_uniform()
     b.iterate([i.k for i in instances] if k is None else k)
@@ -203,6 +209,8 @@ def test_sampling_many_instances_matches_oracle(gpu, kernel):
     say("case: sampling replay, 12 instances x 64 shots, fp64 and mixed, %s" % kernel)
     insts = inputs.random_batch(12, 5, 12, (1, 2, 4), seed=99)
     for precision, tie in (("fp64", 1e-9), ("mixed", 1e-5)):
+        if kernel == "team-pc" and precision == "mixed":
+            continue  # pre-contracted reflections run on FP64 only
         b = run(insts, precision, kernel=kernel)
         bits, hits = b.sample(64, 4242)
         for i, inst in enumerate(insts):
@@ -231,7 +239,7 @@ def test_precontract_needs_the_team_kernel(gpu):
     assert e.value.code == gmps.GMPS_E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64"])
 def test_precontract_matches_mpo_path(gpu, precision):
     say("case: pre-contracted vs bond-2 MPO reflections, ragged n 3..16, M 1..6, %s" % precision)
     insts = inputs.random_batch(41, 3, 16, (1, 2, 3, 4, 5, 6), seed=57, cap_extra=1)
