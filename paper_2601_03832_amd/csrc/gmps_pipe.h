@@ -217,15 +217,9 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
           }
         }
       }
-      if (tl == 0) {
-        if (lr) {
-          rdo[n - 1] = r;
-          rdo[n] = 1;
-        } else {
-          rdo[1] = r;
-          rdo[0] = 1;
-        }
-      }
+      // the rank next to the boundary (r) was read from rdo above and stays; only the
+      // boundary's own entry is written (a rewrite of r would race with that read)
+      if (tl == 0) rdo[lr ? n : 0] = 1;
       wave_sync();
       return;
     }
