@@ -14,7 +14,8 @@ Cases: the bond-32 class (CM = 32, 256-thread teams, four waves) with bond-2 MPO
 pre-contracted reflections at n = 12, M = 24 and 31 (the cases whose GPU build of the
 pre-contracted variant failed; the variant stays off on the GPU); the pipelined two-wave
 kernel of the bond-5 class (the headline launch's longest chains), mixed under
-ThreadSanitizer and FP64 under AddressSanitizer.
+ThreadSanitizer and FP64 under AddressSanitizer; under ThreadSanitizer also the pipelined
+bond-2 class (four 16-lane teams per wave) and the sequential team kernel of the bond-5 class.
 """
 import os
 import shutil
@@ -100,3 +101,12 @@ def test_pipelined_bond5_kernel(tree, s, sanitize, tol):
     st, drift, kd, bonds, amps = run(exe, 10, 4, 6, 3, W)
     assert st == 0 and kd == 3
     assert np.max(np.abs(amps - sv.grover_sv(10, W, 3))) < tol
+
+
+@pytest.mark.parametrize("kind,w,M", [(2, 0, 1), (0, 2, 4)], ids=["pipelined-bond2", "sequential-bond5"])
+def test_more_classes_under_thread_sanitizer(tree, kind, w, M):
+    W = inputs.draw_marked(10, M, inputs.SplitMix64(30 + M))
+    exe = build(tree, kind, w, "float", "thread")
+    st, drift, kd, bonds, amps = run(exe, 10, M, M + 1, 2, W)
+    assert st == 0 and kd == 2
+    assert np.max(np.abs(amps - sv.grover_sv(10, W, 2))) < 1e-6
