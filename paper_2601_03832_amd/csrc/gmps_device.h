@@ -44,6 +44,12 @@ template <class T>
 __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
   return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
+// a / b (b not near the underflow threshold: |b|^2 is formed directly)
+template <class T>
+__device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) {
+  const T d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
 template <class S>
 __device__ __forceinline__ cx<S> down(cd a) { return {(S)a.re, (S)a.im}; }
 template <class S>

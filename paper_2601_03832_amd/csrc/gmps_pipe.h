@@ -53,7 +53,26 @@ struct PipeLds {
   int32_t rdim[2][kBondStride];  // bonds of the canonicalised chain, by reflection parity
 };
 
-template <class S, int CM, int TW>
+// Pre-contracted reflections on the pipelined kernel (FP64 storage). Reflection j maps psi to
+// c0 psi + c1 sum_t <p_t|psi> p_t, an MPS of bond chi + T whose sites are diag(A_i, e_t(i)),
+// e_t(i) the one-site factor of the product state p_t (a marked bit, or |+>). The
+// canonicalisation wave runs one site behind the truncation wave that produces psi, so the
+// overlaps are complete only at its last site. The term columns therefore enter the sweep
+// with predicted weights c1 <p_t|psi>: the reflections are exact, so the overlaps of the next
+// reflection's terms follow from this one's, <q|psi'> = c0 <q|psi> + c1 sum_t <p_t|psi> <q|p_t>
+// (<w|w'> = [w = w'], <+|w> = 2^(-n/2)). The wave contracts the overlaps of psi with both
+// reflections' terms as it stages each site, and at the last site rescales each term column
+// from its predicted to its measured coefficient, which takes in the truncation and rounding
+// of the previous step. Columns with physical weights keep the rank-stopped QR from measuring
+// them against the rounding noise of psi's small Schmidt directions. The first reflection of a
+// call takes its overlaps from a pass over the input chain.
+template <int CM>
+struct PipeOv {
+  cd OV[2][CM + 1][CM];  // overlap rows: a row vector (left to right) or column, by step parity
+  cd om[2][CM + 1];      // first-site weights of the term columns, by reflection parity
+};
+
+template <class S, int CM, int TW, bool PC = false>
 __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base) {
   using T = TeamShape<CM, TW>;
   constexpr int TEAMS = 64 / TW;
@@ -73,6 +92,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
   // inst[] is indexed per lane: read it from memory, not from a register copy
   const int me = bdp->inst[real ? team : 0];
   PipeLds<S, CM>& L = reinterpret_cast<PipeLds<S, CM>*>(lds_base)[team];
+  PipeOv<CM>& X = reinterpret_cast<PipeOv<CM>*>(lds_base + (64 / TW) * sizeof(PipeLds<S, CM>))[team];
   InstDev* I = P.inst + me;
   const int n = I->n;
   const int M = I->M;
@@ -98,14 +118,98 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
 
   double f64 = 0.0, f32 = 0.0, drift = 0.0, truncw = 0.0;
   int status = 0;
-  const int nrefl = M + 1;
+  // pre-contracted: the M oracle terms in one reflection when the host says so (lossless cap,
+  // M within the class), else one reflection per marked index; the diffusion comes last
+  const bool whole = PC && I->whole != 0;
+  const int nrefl = whole ? 2 : M + 1;
   const int64_t J = k * nrefl;  // reflections of this call
+  int opar = 0;                 // pre-contracted: parity of the current term weights
+
+  // ---------------------------------------------------------------- pre-contracted terms
+  // Overlap rows u of reflection jr: with the whole oracle in one reflection the M marked
+  // states and |+> (row M); else row 0 is this reflection's term, row 1 the next one's. A
+  // row's kind is its marked index, or -1 for |+>.
+  auto ov_rows = [&](bool ident) -> int { return ident ? 0 : (whole ? M + 1 : 2); };
+  auto row_kind = [&](int jr, int u) -> int {
+    if (whole) return u < M ? u : -1;
+    const int j = u == 0 ? jr : (jr + 1) % nrefl;
+    return j == nrefl - 1 ? -1 : j;
+  };
+  auto this_row = [&](int jr, int t) -> int { return whole ? (jr == nrefl - 1 ? M : t) : 0; };
+  auto next_row = [&](int jr, int t) -> int { return whole ? (jr == nrefl - 1 ? t : M) : 1; };
+  auto terms_of = [&](int jr) -> int { return (whole && jr != nrefl - 1) ? M : 1; };
+  auto efac = [&](int kind, int i, int s) -> double {
+    if (kind < 0) return kInvSqrt2;
+    return (int)((Wm[kind] >> (n - 1 - i)) & 1ull) == s ? 1.0 : 0.0;
+  };
+  auto gram = [&](int ka, int kb) -> double {
+    if (ka < 0 && kb < 0) return 1.0;
+    if (ka < 0 || kb < 0) return exp2(-0.5 * n);
+    return Wm[ka] == Wm[kb] ? 1.0 : 0.0;
+  };
+  // stage site i as A itself into W[0] and advance the overlap rows through it
+  auto stage_ov = [&](int jr, bool ident, bool lr, int i, const cd (*h)[2][CM]) {
+    const int chl = L.bond[i], chr = L.bond[i + 1];
+    const bool first = lr ? (i == 0) : (i == n - 1);
+    const cx<S>* slot = arena + (int64_t)i * SLOT;
+    const cd* es = eslot(i);
+    const int U = ov_rows(ident);
+    if (first && tl < U) X.OV[0][tl][0] = {1.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tl + t * TW;
+      if (e < CM * CM) {
+        const int a = e / CM, b = e % CM;
+        cd a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+        if (a < chl && b < chr) {
+          if (h) {
+            a0 = h[a][0][b];
+            a1 = h[a][1][b];
+          } else if (es) {
+            a0 = es[a * 2 * D + b];
+            a1 = es[a * 2 * D + D + b];
+          } else {
+            a0 = up(slot[a * 2 * D + b]);
+            a1 = up(slot[a * 2 * D + D + b]);
+          }
+        }
+        L.W[0][a][0][b] = a0;
+        L.W[0][a][1][b] = a1;
+      }
+    }
+    wave_sync();
+    if (U > 0) {
+      // <p_u| A_0 .. A_i: left to right a row over the right bond of site i, right to left a
+      // column over its left bond
+      const int step = lr ? i : n - 1 - i;
+      const cd(*vin)[CM] = X.OV[step & 1];
+      cd(*vout)[CM] = X.OV[(step + 1) & 1];
+      const int nin = lr ? chl : chr, nout = lr ? chr : chl;
+      for (int el = tl; el < U * CM; el += TW) {
+        const int u = el / CM, o = el % CM;
+        if (o < nout) {
+          const int kind = row_kind(jr, u);
+          const double e0 = efac(kind, i, 0), e1 = efac(kind, i, 1);
+          cd acc = {0.0, 0.0};
+          for (int v = 0; v < CM; ++v)
+            if (v < nin) {
+              const cd w0 = lr ? L.W[0][v][0][o] : L.W[0][o][0][v];
+              const cd w1 = lr ? L.W[0][v][1][o] : L.W[0][o][1][v];
+              acc = cfma(acc, vin[u][v], cd{e0 * w0.re + e1 * w1.re, e0 * w0.im + e1 * w1.im});
+            }
+          vout[u][o] = acc;
+        }
+      }
+      f64 += 8.0 * (double)U * nin * nout;
+      wave_sync();
+    }
+  };
 
   // ---------------------------------------------------------------- canonicalisation step
   // Reflection jr (0..M, M = diffusion) at site i, direction lr; the site tensor comes from
   // the handover buffer h (null: from its arena slot). rdo: the ranks it produces.
   auto canon_step = [&](int jr, bool ident, bool lr, int i, const cd (*h)[2][CM], int32_t* rdo) {
-    const bool diff = (jr == M);
+    const bool diff = (jr == nrefl - 1);
     const int xb = (diff || ident) ? 0 : (int)((Wm[jr] >> (n - 1 - i)) & 1ull);
     const double c0 = ident ? 1.0 : (diff ? -1.0 : 1.0);
     const double c1 = ident ? 0.0 : (diff ? 2.0 : -2.0);
@@ -115,14 +219,23 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
     const bool last = lr ? (i == n - 1) : (i == 0);
     cx<S>* slot = arena + (int64_t)i * SLOT;
     cd* es = eslot(i);
+    const int T = (!PC || ident) ? 0 : terms_of(jr);  // pre-contracted: product terms
+    const int step = lr ? i : n - 1 - i;               // position in the sweep
     if (first && tl == 0) {
       rdo[lr ? 0 : n] = 1;
       L.R[0][0] = {1.0, 0.0};
-      L.R[0][1] = {1.0, 0.0};
+      if constexpr (PC) {
+        // the term blocks enter with their predicted weights (R~ = L^H right to left)
+        for (int t = 0; t < T; ++t) L.R[0][1 + t] = lr ? X.om[opar][t] : conj(X.om[opar][t]);
+      } else {
+        L.R[0][1] = {1.0, 0.0};
+      }
     }
-    // stage [c0 A | c1 P A] (coefficients on the last site only): the site as the truncation
-    // wave handed it over, else from its edge slot (complex FP64) or its site slot
-    {
+    if constexpr (PC) {
+      stage_ov(jr, ident, lr, i, h);
+    } else {
+      // stage [c0 A | c1 P A] (coefficients on the last site only): the site as the truncation
+      // wave handed it over, else from its edge slot (complex FP64) or its site slot
       const double s0 = mpo_last ? c0 : 1.0, s1 = mpo_last ? c1 : 1.0;
 #pragma unroll
       for (int t = 0; t < NE; ++t) {
@@ -149,12 +262,48 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
           L.W[1][a][1][b] = s1 * proj_apply<double>(a0, a1, 1, diff, xb);
         }
       }
+      wave_sync();
     }
-    wave_sync();
     const int r = first ? 1 : rdo[lr ? i : i + 1];
     cd x[RQ];
     int Dr;  // columns of the QR tile
-    if (lr) {
+    if constexpr (PC) {
+      // the tile of the site diag(A_i, e_1(i), .., e_T(i)) after the carry: left to right
+      // X[(a, s)][b] = sum R[a][a'] A[a'][s][b] and X[(a, s)][chr + t] = R[a][chl + t] e_t[s];
+      // right to left the conjugate-transposed tile of the mirrored product (as in the MPO form
+      // below). At the sweep's last site the columns sum into one: c0 on the A block, and on
+      // term t the measured coefficient c1 <p_t|psi> over the predicted weight it carries.
+      const int nA = lr ? chr : chl;  // A-block columns
+      const int nS = lr ? chl : chr;  // bond summed over
+      Dr = last ? 1 : nA + T;
+#pragma unroll
+      for (int e = 0; e < RQ; ++e) {
+        const int row = qh + PQ * e;
+        const int a = row >> 1, s = row & 1;
+        cd acc = {0.0, 0.0};
+        if (row < 2 * r && qc < Dr) {
+          if (last || qc < nA) {
+            const int col = last ? 0 : qc;
+#pragma unroll
+            for (int u = 0; u < CM; ++u)
+              if (u < nS) acc = lr ? cfma(acc, L.R[a][u], L.W[0][u][s][col]) : cfma(acc, conj(L.W[0][col][s][u]), L.R[a][u]);
+            if (last) {
+              acc = c0 * acc;
+              for (int t = 0; t < T; ++t) {
+                const cd g = cdiv(c1 * X.OV[(step + 1) & 1][this_row(jr, t)][0], X.om[opar][t]);
+                const double ev = efac(row_kind(jr, this_row(jr, t)), i, s);
+                const cd cw = {ev * g.re, ev * g.im};
+                acc = lr ? cfma(acc, L.R[a][nS + t], cw) : cfma(acc, conj(cw), L.R[a][nS + t]);
+              }
+            }
+          } else {
+            const int t = qc - nA;
+            acc = efac(row_kind(jr, this_row(jr, t)), i, s) * L.R[a][nS + t];
+          }
+        }
+        x[e] = (!lr && last) ? conj(acc) : acc;
+      }
+    } else if (lr) {
       // X = R_{i-1} * MPO(A_i): rows (a, s) = 2a + s, columns (beta, b)
       Dr = last ? 1 : 2 * chr;
       const int beta = (!last && qc >= chr) ? 1 : 0;
@@ -201,7 +350,10 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
         x[e] = last ? conj(acc) : acc;
       }
     }
-    f64 += 8.0 * (double)r * (first ? 1 : 2 * (lr ? chl : chr)) * 2.0 * Dr;
+    if constexpr (PC)
+      f64 += 8.0 * (double)r * (first ? 1 : (lr ? chl : chr)) * 2.0 * (last ? 1 : (lr ? chr : chl));
+    else
+      f64 += 8.0 * (double)r * (first ? 1 : 2 * (lr ? chl : chr)) * 2.0 * Dr;
     if (last) {
       // the boundary site holds the norm: its tile goes to its edge slot and, as stored, to its
       // site slot (left to right the column (a, s) of site n-1, right to left the row (s, c) of
@@ -221,6 +373,28 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
       // boundary's own entry is written (a rewrite of r would race with that read)
       if (tl == 0) rdo[lr ? n : 0] = 1;
       wave_sync();
+      if constexpr (PC) {
+        if (!ident) {
+          // predicted weights of the next reflection's terms
+          const int jn = (jr + 1) % nrefl;
+          const double c1n = jn == nrefl - 1 ? 2.0 : -2.0;
+          const cd(*fin)[CM] = X.OV[(step + 1) & 1];
+          if (tl < terms_of(jn)) {
+            const int qr = next_row(jr, tl), qk = row_kind(jr, qr);
+            cd pr = c0 * fin[qr][0];
+            for (int t = 0; t < T; ++t) {
+              const int pt = this_row(jr, t);
+              pr = pr + (c1 * gram(qk, row_kind(jr, pt))) * fin[pt][0];
+            }
+            cd w = c1n * pr;
+            // a vanishing prediction: a tiny finite weight (the column then carries nothing)
+            if (fabs(w.re) + fabs(w.im) < 1e-150) w = {1e-150, 0.0};
+            X.om[opar ^ 1][tl] = w;
+          }
+          opar ^= 1;
+          wave_sync();
+        }
+      }
       return;
     }
     const int m = 2 * r;
@@ -312,7 +486,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
   // slot from h.
   auto trunc_step = [&](int jr, bool lr, int i, const int32_t* rdi, cd (*h)[2][CM], bool keep_slot) {
     const bool wr = real && keep_slot;
-    const bool diff = (jr == M);
+    const bool diff = (jr == nrefl - 1);
     const bool first = lr ? (i == 0) : (i == n - 1);
     const bool edge = lr ? (i == n - 1) : (i == 0);  // absorbs the carry, holds the norm
     cx<S>* slot = arena + (int64_t)i * SLOT;
@@ -512,6 +686,19 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
   // ranks; the truncation wave leaves the arena to the canonicalisation wave, which rewrites
   // each slot anyway), so the intermediate barriers order LDS only; the last one of a stage
   // also orders the arena, which the next stage reads.
+  if constexpr (PC) {
+    // the first reflection's weights from its overlaps with the input chain
+    if (wave == 1 && J > 0) {
+      for (int i = 0; i < n; ++i) stage_ov(0, false, true, i, nullptr);
+      const double c1f = nrefl == 1 ? 2.0 : -2.0;
+      if (tl < terms_of(0)) {
+        cd w = c1f * X.OV[n & 1][this_row(0, tl)][0];
+        if (fabs(w.re) + fabs(w.im) < 1e-150) w = {1e-150, 0.0};
+        X.om[0][tl] = w;
+      }
+      wave_sync();
+    }
+  }
   const int64_t nstage = J == 0 ? 0 : J + 1;
   const bool fix = J > 0 && ((J - 1) & 1) == 1;  // last truncation ran left to right
   for (int64_t stg = 0; stg < nstage + (fix ? 1 : 0); ++stg) {
@@ -581,7 +768,7 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
 
 // Persistent kernel of the pipelined reflections for team class W (a bundle per workgroup of
 // two waves).
-template <class S, int W>
+template <class S, int W, bool PC = false>
 __global__ __launch_bounds__(128) void grover_pipe_kernel(IterParams P) {
   extern __shared__ __align__(16) char lds[];
   __shared__ unsigned int next_bundle;
@@ -591,26 +778,36 @@ __global__ __launch_bounds__(128) void grover_pipe_kernel(IterParams P) {
     const unsigned int bi = next_bundle;
     lds_sync();
     if ((int)bi >= P.queue->nbundles) break;
-    run_pipe<S, kWide[W].CM, kWide[W].TW>(P, P.bundles + bi, lds);
+    run_pipe<S, kWide[W].CM, kWide[W].TW, PC>(P, P.bundles + bi, lds);
   }
 }
 
 template <int W>
-hipError_t launch_pipe_w(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st);
+hipError_t launch_pipe_w(bool mixed, bool pc, const IterParams& P, int grid, size_t lds, hipStream_t st);
 template <int W>
-hipError_t occupancy_pipe_w(bool mixed, size_t lds, int* blocks_per_cu);
+hipError_t occupancy_pipe_w(bool mixed, bool pc, size_t lds, int* blocks_per_cu);
 
+// The pre-contracted form is instantiated for FP64 storage only (gmps_create refuses it on the
+// mixed path).
 #define GMPS_PIPE_CLASS(W)                                                                           \
   template <>                                                                                        \
-  hipError_t launch_pipe_w<W>(bool mixed, const IterParams& P, int grid, size_t lds, hipStream_t st) { \
-    if (mixed)                                                                                       \
+  hipError_t launch_pipe_w<W>(bool mixed, bool pc, const IterParams& P, int grid, size_t lds, hipStream_t st) { \
+    if (pc) {                                                                                        \
+      if (mixed) return hipErrorInvalidValue;                                                        \
+      grover_pipe_kernel<double, W, true><<<grid, 128, lds, st>>>(P);                                 \
+    } else if (mixed) {                                                                              \
       grover_pipe_kernel<float, W><<<grid, 128, lds, st>>>(P);                                        \
-    else                                                                                             \
+    } else {                                                                                         \
       grover_pipe_kernel<double, W><<<grid, 128, lds, st>>>(P);                                       \
+    }                                                                                                \
     return hipGetLastError();                                                                        \
   }                                                                                                  \
   template <>                                                                                        \
-  hipError_t occupancy_pipe_w<W>(bool mixed, size_t lds, int* blocks_per_cu) {                      \
+  hipError_t occupancy_pipe_w<W>(bool mixed, bool pc, size_t lds, int* blocks_per_cu) {             \
+    if (pc) {                                                                                        \
+      if (mixed) return hipErrorInvalidValue;                                                        \
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_pipe_kernel<double, W, true>, 128, lds); \
+    }                                                                                                \
     return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_pipe_kernel<float, W>, 128, lds) \
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_pipe_kernel<double, W>, 128, lds); \
   }

@@ -19,18 +19,21 @@ static_assert(sizeof(TeamLds<double, 8, 64>) + sizeof(PcLds<8>) <= 160 * 1024 - 
 static_assert(sizeof(TeamLds<double, 17, 192>) + sizeof(PcLds<17>) <= 160 * 1024 - 64, "LDS");
 static_assert(sizeof(TeamLds<double, 32, 256>) <= 160 * 1024 - 64, "LDS");
 
-static_assert(sizeof(PipeLds<double, 2>) * 4 <= 160 * 1024 - 256, "LDS");
-static_assert(sizeof(PipeLds<double, 3>) * 2 <= 160 * 1024 - 256, "LDS");
-static_assert(sizeof(PipeLds<double, 5>) <= 160 * 1024 - 256, "LDS");
-static_assert(sizeof(PipeLds<double, 8>) <= 160 * 1024 - 256, "LDS");
+// the pipelined kernel, with the pre-contracted reflections' overlap block
+static_assert((sizeof(PipeLds<double, 2>) + sizeof(PipeOv<2>)) * 4 <= 160 * 1024 - 256, "LDS");
+static_assert((sizeof(PipeLds<double, 3>) + sizeof(PipeOv<3>)) * 2 <= 160 * 1024 - 256, "LDS");
+static_assert(sizeof(PipeLds<double, 5>) + sizeof(PipeOv<5>) <= 160 * 1024 - 256, "LDS");
+static_assert(sizeof(PipeLds<double, 8>) + sizeof(PipeOv<8>) <= 160 * 1024 - 256, "LDS");
 
-// the classes with a pipelined kernel (teams within one wave: bond caps 2, 3, 5 and 8)
-static bool pipe_class(int w, bool) { return w >= 0 && w <= 3; }
+// the classes with a pipelined kernel (teams within one wave: bond caps 2, 3, 5 and 8); the
+// pre-contracted form is FP64 only
+static bool pipe_class(int w, bool mixed, bool pc) { return w >= 0 && w <= 3 && !(pc && mixed); }
 
 template <int W>
-static size_t pipe_lds(bool mixed) {
+static size_t pipe_lds(bool mixed, bool pc) {
   constexpr int CM = kWide[W].CM, TW = kWide[W].TW;
-  return (mixed ? sizeof(PipeLds<float, CM>) : sizeof(PipeLds<double, CM>)) * (64 / TW);
+  const size_t per = (mixed ? sizeof(PipeLds<float, CM>) : sizeof(PipeLds<double, CM>)) + (pc ? sizeof(PipeOv<CM>) : 0);
+  return per * (64 / TW);
 }
 
 template <int W>
@@ -43,12 +46,12 @@ static size_t class_lds(bool mixed, bool pc) {
 }
 
 size_t team_lds_bytes(bool mixed, bool pc, bool pipe, int cls) {
-  if (pipe && !pc && pipe_class(cls - kWideBase, mixed)) {
+  if (pipe && pipe_class(cls - kWideBase, mixed, pc)) {
     switch (cls - kWideBase) {
-      case 0: return pipe_lds<0>(mixed);
-      case 1: return pipe_lds<1>(mixed);
-      case 2: return pipe_lds<2>(mixed);
-      case 3: return pipe_lds<3>(mixed);
+      case 0: return pipe_lds<0>(mixed, pc);
+      case 1: return pipe_lds<1>(mixed, pc);
+      case 2: return pipe_lds<2>(mixed, pc);
+      case 3: return pipe_lds<3>(mixed, pc);
     }
   }
   switch (cls - kWideBase) {
@@ -65,12 +68,12 @@ size_t team_lds_bytes(bool mixed, bool pc, bool pipe, int cls) {
 hipError_t launch_team(bool mixed, bool pc, bool pipe, int cls, const IterParams& P, int grid, size_t lds,
                        hipStream_t st) {
   const int w = cls - kWideBase;
-  if (pipe && !pc && pipe_class(w, mixed)) {
+  if (pipe && pipe_class(w, mixed, pc)) {
     switch (w) {
-      case 0: return launch_pipe_w<0>(mixed, P, grid, lds, st);
-      case 1: return launch_pipe_w<1>(mixed, P, grid, lds, st);
-      case 2: return launch_pipe_w<2>(mixed, P, grid, lds, st);
-      case 3: return launch_pipe_w<3>(mixed, P, grid, lds, st);
+      case 0: return launch_pipe_w<0>(mixed, pc, P, grid, lds, st);
+      case 1: return launch_pipe_w<1>(mixed, pc, P, grid, lds, st);
+      case 2: return launch_pipe_w<2>(mixed, pc, P, grid, lds, st);
+      case 3: return launch_pipe_w<3>(mixed, pc, P, grid, lds, st);
     }
   }
   if (pc && w >= 0 && w < kNumWide && team_pc_class(w)) {
@@ -96,12 +99,12 @@ hipError_t launch_team(bool mixed, bool pc, bool pipe, int cls, const IterParams
 
 hipError_t team_occupancy(bool mixed, bool pc, bool pipe, int cls, size_t lds, int* blocks_per_cu) {
   const int w = cls - kWideBase;
-  if (pipe && !pc && pipe_class(w, mixed)) {
+  if (pipe && pipe_class(w, mixed, pc)) {
     switch (w) {
-      case 0: return occupancy_pipe_w<0>(mixed, lds, blocks_per_cu);
-      case 1: return occupancy_pipe_w<1>(mixed, lds, blocks_per_cu);
-      case 2: return occupancy_pipe_w<2>(mixed, lds, blocks_per_cu);
-      case 3: return occupancy_pipe_w<3>(mixed, lds, blocks_per_cu);
+      case 0: return occupancy_pipe_w<0>(mixed, pc, lds, blocks_per_cu);
+      case 1: return occupancy_pipe_w<1>(mixed, pc, lds, blocks_per_cu);
+      case 2: return occupancy_pipe_w<2>(mixed, pc, lds, blocks_per_cu);
+      case 3: return occupancy_pipe_w<3>(mixed, pc, lds, blocks_per_cu);
     }
   }
   if (pc && w >= 0 && w < kNumWide && team_pc_class(w)) {

@@ -4,7 +4,8 @@
 // gives it, and the result goes to stdout for comparison with the oracle. Built with
 // sanitizers by tests/test_host_emulation.py:
 //   EMU_KIND 0: run_team (bond-2 MPO reflections), 1: run_team_pc (pre-contracted),
-//            2: run_pipe (pipelined sweeps); EMU_W: team class; EMU_S: double or float.
+//            2: run_pipe (pipelined sweeps), 3: run_pipe pre-contracted; EMU_W: team class;
+//            EMU_S: double or float.
 // stdin: n M cap k, then the M marked indices. stdout: status drift trunc_w, the bonds, then
 // the 2^n amplitudes (re im per line).
 #include "hip/hip_runtime.h"
@@ -64,13 +65,15 @@ constexpr int W = EMU_W;
 constexpr int KIND = EMU_KIND;
 constexpr int CM = kWide[W].CM, TW = kWide[W].TW;
 constexpr bool kMixed = sizeof(S) == sizeof(float);
-constexpr int NT = KIND == 2 ? 128 : (TW < 64 ? 64 : TW);
+constexpr int NT = KIND >= 2 ? 128 : (TW < 64 ? 64 : TW);
 
 // templates on every parameter, so that the branches for the other kernels are not instantiated
 template <int K, class SS, int C, int T>
 size_t lds_size() {
   if constexpr (K == 2)
     return sizeof(PipeLds<SS, C>) * (64 / T);
+  else if constexpr (K == 3)
+    return (sizeof(PipeLds<SS, C>) + sizeof(PipeOv<C>)) * (64 / T);
   else
     return (sizeof(TeamLds<SS, C, T>) + (K == 1 ? sizeof(PcLds<C>) : 0)) * TeamShape<C, T>::TEAMS;
 }
@@ -80,8 +83,10 @@ void body(const IterParams& P, const Bundle* bundle, char* lds) {
     run_team<SS, C, T>(P, bundle, lds);
   else if constexpr (K == 1)
     run_team_pc<SS, C, T>(P, bundle, lds);
-  else
+  else if constexpr (K == 2)
     run_pipe<SS, C, T>(P, bundle, lds);
+  else
+    run_pipe<SS, C, T, true>(P, bundle, lds);
 }
 
 int main() {
@@ -114,7 +119,7 @@ int main() {
   inst->M = M;
   inst->cap = eff;
   inst->cls = kWideBase + W;
-  inst->whole = (KIND == 1 && eff == exact && M <= CM) ? 1 : 0;
+  inst->whole = ((KIND == 1 || KIND == 3) && eff == exact && M <= CM) ? 1 : 0;
   inst->ew = ew;
   const double h = 0.70710678118654752440;
   for (int i = 0; i < n; ++i) {

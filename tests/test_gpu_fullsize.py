@@ -110,14 +110,16 @@ def test_batched_mixed_full_size(gpu, pc, pipe):
     say("sampling ok")
 
 
-def test_batched_fp64_precontracted_full_size(gpu):
+@pytest.mark.parametrize("pipe", [True, False], ids=["pipelined", "sequential"])
+def test_batched_fp64_precontracted_full_size(gpu, pipe):
     """The 4096-instance workload in FP64 through the pre-contracted reflections (the fastest
-    path): P of every instance at half and full k, and 4096-shot hit counts."""
-    say("case: 4096-instance batch, fp64, pre-contracted reflections, half and full k")
+    path), pipelined and sequential sweeps: P of every instance at half and full k, and
+    4096-shot hit counts."""
+    say("case: 4096-instance batch, fp64, pre-contracted reflections, pipeline=%s, half and full k" % pipe)
     w = inputs.config_c4()
     ks = np.array([i.k for i in w.instances])
     half = ks // 2
-    b = gmps.Batch(w.instances, "fp64", precontract=True)
+    b = gmps.Batch(w.instances, "fp64", precontract=True, pipeline=pipe)
     b.init_uniform()
     for stage, kk, step in (("half k", half, half), ("full k", ks, ks - half)):
         b.iterate(step)

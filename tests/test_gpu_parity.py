@@ -20,11 +20,11 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-10, "mixed": 1e-6}
 
 
-@pytest.fixture(params=["group", "team", "team-seq", "team-pc"])
+@pytest.fixture(params=["group", "team", "team-seq", "team-pc", "team-pc-seq"])
 def kernel(request):
     """Both iterate kernels run every parity case; the team kernel with its pipelined sweeps
     (the default), with each reflection's sweeps in turn, and with pre-contracted
-    reflections."""
+    reflections, pipelined and in turn."""
     return request.param
 
 
@@ -32,6 +32,8 @@ def batch_kw(kernel):
     """Batch keywords of a kernel variant name."""
     if kernel == "team-pc":
         return {"kernel": "team", "precontract": True}
+    if kernel == "team-pc-seq":
+        return {"kernel": "team", "precontract": True, "pipeline": False}
     if kernel == "team-seq":
         return {"kernel": "team", "pipeline": False}
     return {"kernel": kernel}
@@ -43,7 +45,7 @@ def say(msg):
 
 
 def run(instances, precision, k=None, kernel="auto", **kw):
-    if kernel == "team-pc" and precision != "fp64":
+    if kernel.startswith("team-pc") and precision != "fp64":
         # pre-contracted reflections are refused on the mixed path: check that, then skip
         with pytest.raises(gmps.GmpsError) as e:
             gmps.Batch(instances, precision, **batch_kw(kernel), **kw)
@@ -209,7 +211,7 @@ def test_sampling_many_instances_matches_oracle(gpu, kernel):
     say("case: sampling replay, 12 instances x 64 shots, fp64 and mixed, %s" % kernel)
     insts = inputs.random_batch(12, 5, 12, (1, 2, 4), seed=99)
     for precision, tie in (("fp64", 1e-9), ("mixed", 1e-5)):
-        if kernel == "team-pc" and precision == "mixed":
+        if kernel.startswith("team-pc") and precision == "mixed":
             continue  # pre-contracted reflections run on FP64 only
         b = run(insts, precision, kernel=kernel)
         bits, hits = b.sample(64, 4242)
@@ -239,12 +241,13 @@ def test_precontract_needs_the_team_kernel(gpu):
     assert e.value.code == gmps.GMPS_E_UNSUPPORTED
 
 
+@pytest.mark.parametrize("variant", ["team-pc", "team-pc-seq"])
 @pytest.mark.parametrize("precision", ["fp64"])
-def test_precontract_matches_mpo_path(gpu, precision):
-    say("case: pre-contracted vs bond-2 MPO reflections, ragged n 3..16, M 1..6, %s" % precision)
+def test_precontract_matches_mpo_path(gpu, precision, variant):
+    say("case: pre-contracted (%s) vs bond-2 MPO reflections, ragged n 3..16, M 1..6, %s" % (variant, precision))
     insts = inputs.random_batch(41, 3, 16, (1, 2, 3, 4, 5, 6), seed=57, cap_extra=1)
     a = run(insts, precision, kernel="team")
-    c = run(insts, precision, kernel="team-pc")
+    c = run(insts, precision, kernel=variant)
     pa, pc = a.marked_prob(), c.marked_prob()
     for i, inst in enumerate(insts):
         ex = cf.p_marked(inst.n, inst.M, inst.k)
@@ -258,15 +261,15 @@ def test_precontract_matches_mpo_path(gpu, precision):
             assert dc["flops64"][i] + dc["flops32"][i] < da["flops64"][i] + da["flops32"][i], i
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_pipelined_sweeps_both_end_directions(gpu, precision):
-    say("case: pipelined sweeps, k = 1..4 (the last truncation in either direction), %s" % precision)
+@pytest.mark.parametrize("precision,variant", [("fp64", "team"), ("mixed", "team"), ("fp64", "team-pc")])
+def test_pipelined_sweeps_both_end_directions(gpu, precision, variant):
+    say("case: pipelined sweeps, k = 1..4 (the last truncation in either direction), %s %s" % (precision, variant))
     rng = inputs.SplitMix64(5)
-    for n, M in ((6, 3), (8, 4), (9, 5), (12, 7)):
+    for n, M in ((6, 3), (8, 4), (9, 5), (12, 7), (4, 9), (5, 12)):
         W = inputs.draw_marked(n, M, rng)
         for k in (1, 2, 3, 4):
             inst = inputs.Instance(n, W, k, M + 1)
-            b = run([inst], precision, kernel="team")
+            b = run([inst], precision, kernel=variant)
             psi = sv.grover_sv(n, W, k)
             amps = b.amplitudes(0, np.arange(1 << n, dtype=np.uint64))
             assert np.max(np.abs(amps - psi)) < (1e-12 if precision == "fp64" else 1e-6), (n, M, k)

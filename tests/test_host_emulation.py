@@ -10,7 +10,8 @@ the LDS block or a global buffer, and ThreadSanitizer sees any LDS or global acc
 lanes that no barrier or wave fence orders. Each run is then compared with the statevector
 oracle.
 
-Cases: the bond-32 class (CM = 32, 256-thread teams, four waves) with bond-2 MPO and with
+Cases: the pipelined pre-contracted reflections (one reflection for the whole oracle, and one
+per marked index where M exceeds the class bond); the bond-32 class (CM = 32, 256-thread teams, four waves) with bond-2 MPO and with
 pre-contracted reflections at n = 12, M = 24 and 31 (the cases whose GPU build of the
 pre-contracted variant failed; the variant stays off on the GPU); the pipelined two-wave
 kernel of the bond-5 class (the headline launch's longest chains), mixed under
@@ -110,3 +111,15 @@ def test_more_classes_under_thread_sanitizer(tree, kind, w, M):
     st, drift, kd, bonds, amps = run(exe, 10, M, M + 1, 2, W)
     assert st == 0 and kd == 2
     assert np.max(np.abs(amps - sv.grover_sv(10, W, 2))) < 1e-6
+
+
+@pytest.mark.parametrize("w,n,M,k,sanitize", [(2, 10, 4, 3, "thread"), (0, 9, 1, 4, "thread"),
+                                              (2, 5, 8, 2, "address,undefined")],
+                         ids=["bond5-whole-oracle-tsan", "bond2-tsan", "bond5-per-index-asan"])
+def test_pipelined_precontracted(tree, w, n, M, k, sanitize):
+    W = inputs.draw_marked(n, M, inputs.SplitMix64(40 + n))
+    exe = build(tree, 3, w, "double", sanitize)
+    st, drift, kd, bonds, amps = run(exe, n, M, M + 1, k, W)
+    assert st == 0 and kd == k
+    assert max(bonds) > 1
+    assert np.max(np.abs(amps - sv.grover_sv(n, W, k))) < 1e-12
