@@ -127,27 +127,31 @@ typedef struct {
                            c0 I + c1 sum_t |p_t><p_t| over product states p_t (Eqs. (3)-(4): the
                            marked basis states for O, |s> for D) maps psi to
                            c0 psi + c1 sum_t <p_t|psi> p_t, an MPS of bond chi + T built from
-                           the site tensors and the overlaps <p_t|psi> (contracted during the
-                           QR sweep), instead of a bond-2 MPO per projector (bond 2 chi).
+                           the site tensors and the overlaps <p_t|psi> (contracted in a pass
+                           before the QR sweep; with pipelined sweeps during it, the term
+                           columns carrying overlaps predicted from the previous reflection
+                           until the last site rescales them to the measured ones), instead
+                           of a bond-2 MPO per projector (bond 2 chi).
                            When the bond cap is lossless (chi_cap >= min(M+1, 2^floor(n/2)))
                            and M fits the tile class, O is one reflection with T = M, so an
                            iteration takes two QR+SVD sweeps instead of M+1; otherwise each
                            marked index is one reflection with T = 1. Same result up to
                            rounding. It is refused on GMPS_MIXED: with complex64 storage the exact
-                           product terms add directions outside the rounded bond spaces, which the
-                           M+1 cap cuts with some in-plane weight (the angle drifted by up to 3e-10
-                           per iteration at M = 4, and at n = 40, M = 16 truncations ran away and
-                           one instance lost 60% of P within 5000 iterations). 0 or -1 (default):
-                           one bond-2 MPO per projector, as in the paper. */
+                           product terms meet bond spaces tilted by the rounding of the stored
+                           sites, and the rotation angle drifts, faster with n (sequential
+                           sweeps: up to 3e-10 per iteration at M = 4 on the 4096-instance
+                           workload, and at n = 40, M = 16 truncations ran away; pipelined
+                           sweeps: |dP| 1.7e-5 on that workload). 0 or -1 (default): one bond-2
+                           MPO per projector, as in the paper. */
   int32_t pipeline;     /* 0 or 1 (default): the team classes with bond caps 2, 3, 5 and 8 run
-                           the per-projector reflections with alternating sweep directions on
-                           two waves, the truncation sweep of each reflection and the
-                           canonicalisation sweep of the next in lock step one site apart;
-                           ignored with precontract, on the lane-group kernel, and in a batch
-                           where some bond cap is below the exact rank (a lossy truncation
-                           depends on the sweep order; such a batch keeps the sequential,
-                           right-to-left truncations). -1: one wave per instance, each
-                           reflection's two sweeps in turn                                */
+                           the reflections (bond-2 MPO or pre-contracted) with alternating sweep
+                           directions on two waves, the truncation sweep of each reflection and
+                           the canonicalisation sweep of the next in lock step one site apart;
+                           ignored on the lane-group kernel and in a batch where some bond cap
+                           is below the exact rank (a lossy truncation depends on the sweep
+                           order; such a batch keeps the sequential, right-to-left
+                           truncations). -1: one wave per instance, each reflection's two
+                           sweeps in turn                                                  */
 } gmps_options;
 
 /* Bytes of device workspace gmps_create() needs for this batch with either iterate kernel

@@ -290,8 +290,8 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
   const int path = fp32 ? kPathGroup : resolve_path(opt ? opt->kernel : kPathAuto);
   const bool precontract = opt && opt->precontract > 0;
   // pre-contracted reflections run on the team kernel in FP64 only: on complex64 storage the
-  // exact product terms leave directions outside the rounded bond spaces, which the bond cap
-  // cuts with some of the state (a drifting angle, and at n = 40 runaway truncations)
+  // exact product terms meet bond spaces tilted by the rounding of the stored sites, and the
+  // rotation angle drifts, faster with n (both sweep orders)
   if (precontract && (path != kPathTeam || prec != GMPS_FP64)) return GMPS_E_UNSUPPORTED;
   Layout L;
   std::vector<int> cls;
@@ -353,7 +353,7 @@ int gmps_create(gmps_batch** out, const gmps_instance* inst, int32_t B, const ui
     if (effective_cap(inst[i].n, inst[i].M, inst[i].chi_cap) < effective_cap(inst[i].n, inst[i].M, INT32_MAX))
       b->pipeline_ok = false;
   b->pipeline = b->pipeline && b->pipeline_ok;
-  b->pc_ok = path == kPathTeam;
+  b->pc_ok = path == kPathTeam && !b->mixed;
   for (int i = 0; i < B; ++i)
     if (!(is_wide(cls[i]) && team_pc_class(cls[i] - kWideBase))) b->pc_ok = false;
   hipGetDevice(&b->device);
@@ -721,6 +721,7 @@ uint64_t fnv1a(const std::string& t) {
 // whole-oracle flag of every instance (device table rewritten; the caller re-initialises the
 // chain), and the cached graph, whose kernels the plan changes.
 int set_plan(gmps_batch* b, bool pipeline, bool precontract, int wpc) {
+  if (precontract && !b->pc_ok) return GMPS_E_UNSUPPORTED;
   const bool pc_changed = precontract != b->precontract;
   b->pipeline = pipeline;
   b->precontract = precontract;
@@ -771,7 +772,7 @@ int gmps_autotune(gmps_batch* b, const int64_t* k, int32_t k_len, int32_t probe_
   for (int pipe = 0; pipe < 2; ++pipe) {
     if (pipe && !(team && b->pipeline_ok)) continue;
     for (int pc = 0; pc < 2; ++pc) {
-      if (pc && !(team && b->pc_ok && b->pipeline_ok && !b->mixed)) continue;
+      if (pc && !(team && b->pc_ok && b->pipeline_ok)) continue;
       for (int wpc : {0, 1, 2}) plans.push_back({pipe != 0, pc != 0, wpc});
     }
   }

@@ -94,6 +94,8 @@ __host__ __device__ constexpr int class_kj(int CM) { return ((CM + 1) + 1) & ~1;
 // KJ x KJ complex unitary, row-major.
 // Team classes with a pre-contracted reflection kernel (bond caps up to 17).
 __host__ __device__ constexpr bool team_pc_class(int w) { return kWide[w].CM <= 17; }
+// Team classes with the pipelined two-wave kernel (teams within one wave: bond caps up to 8).
+__host__ __device__ constexpr bool team_pipe_class(int w) { return w >= 0 && kWide[w].TW <= 64; }
 __host__ __device__ constexpr int64_t wide_warm_doubles(int CM) { return 2 + 2 * (int64_t)class_kj(CM) * class_kj(CM); }
 
 // Elements of one site slot: (D, 2, D) with row stride 2*D and physical stride D.

@@ -53,7 +53,8 @@ struct PipeLds {
   int32_t rdim[2][kBondStride];  // bonds of the canonicalised chain, by reflection parity
 };
 
-// Pre-contracted reflections on the pipelined kernel (FP64 storage). Reflection j maps psi to
+// Pre-contracted reflections on the pipelined kernel (instantiated for FP64 storage: on
+// complex64 storage the rotation angle drifts, faster with n). Reflection j maps psi to
 // c0 psi + c1 sum_t <p_t|psi> p_t, an MPS of bond chi + T whose sites are diag(A_i, e_t(i)),
 // e_t(i) the one-site factor of the product state p_t (a marked bit, or |+>). The
 // canonicalisation wave runs one site behind the truncation wave that produces psi, so the
@@ -787,13 +788,12 @@ hipError_t launch_pipe_w(bool mixed, bool pc, const IterParams& P, int grid, siz
 template <int W>
 hipError_t occupancy_pipe_w(bool mixed, bool pc, size_t lds, int* blocks_per_cu);
 
-// The pre-contracted form is instantiated for FP64 storage only (gmps_create refuses it on the
-// mixed path).
 #define GMPS_PIPE_CLASS(W)                                                                           \
   template <>                                                                                        \
   hipError_t launch_pipe_w<W>(bool mixed, bool pc, const IterParams& P, int grid, size_t lds, hipStream_t st) { \
-    if (pc) {                                                                                        \
-      if (mixed) return hipErrorInvalidValue;                                                        \
+    if (pc && mixed) {                                                                               \
+      return hipErrorInvalidValue;                                                                   \
+    } else if (pc) {                                                                                 \
       grover_pipe_kernel<double, W, true><<<grid, 128, lds, st>>>(P);                                 \
     } else if (mixed) {                                                                              \
       grover_pipe_kernel<float, W><<<grid, 128, lds, st>>>(P);                                        \
@@ -804,10 +804,9 @@ hipError_t occupancy_pipe_w(bool mixed, bool pc, size_t lds, int* blocks_per_cu)
   }                                                                                                  \
   template <>                                                                                        \
   hipError_t occupancy_pipe_w<W>(bool mixed, bool pc, size_t lds, int* blocks_per_cu) {             \
-    if (pc) {                                                                                        \
-      if (mixed) return hipErrorInvalidValue;                                                        \
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_pipe_kernel<double, W, true>, 128, lds); \
-    }                                                                                                \
+    if (pc)                                                                                          \
+      return mixed ? hipErrorInvalidValue                                                            \
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_pipe_kernel<double, W, true>, 128, lds); \
     return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_pipe_kernel<float, W>, 128, lds) \
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_pipe_kernel<double, W>, 128, lds); \
   }

@@ -25,9 +25,8 @@ static_assert((sizeof(PipeLds<double, 3>) + sizeof(PipeOv<3>)) * 2 <= 160 * 1024
 static_assert(sizeof(PipeLds<double, 5>) + sizeof(PipeOv<5>) <= 160 * 1024 - 256, "LDS");
 static_assert(sizeof(PipeLds<double, 8>) + sizeof(PipeOv<8>) <= 160 * 1024 - 256, "LDS");
 
-// the classes with a pipelined kernel (teams within one wave: bond caps 2, 3, 5 and 8); the
-// pre-contracted form is FP64 only
-static bool pipe_class(int w, bool mixed, bool pc) { return w >= 0 && w <= 3 && !(pc && mixed); }
+// the classes with a pipelined kernel (teams within one wave: bond caps 2, 3, 5 and 8)
+static bool pipe_class(int w, bool, bool) { return w >= 0 && w < kNumWide && team_pipe_class(w); }
 
 template <int W>
 static size_t pipe_lds(bool mixed, bool pc) {

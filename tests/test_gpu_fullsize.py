@@ -25,10 +25,11 @@ sees only at second order; they are checked element by element against the state
 in the smaller parity tests.
 
 Cases: the 4096-instance mixed batch (n 12..28, M 1/2/4, own k) at half and full k on the
-pipelined and sequential sweeps with 4096 shots per instance against the binomial law, and the
-same batch in FP64 through the pre-contracted reflections; the longest chain of
-that batch (n=28, M=4) every 500 iterations; n=29, k=18198 (the precision study) every 1000
-iterations, FP64 and mixed.
+pipelined and sequential sweeps, with 4096 shots per instance against the binomial law, and the
+same batch in FP64 through the pre-contracted reflections, pipelined and sequential; the longest
+chain of that batch (n=28, M=4) every 500 iterations (FP64 and mixed, both sweep orders, and
+FP64 pre-contracted); n=29, k=18198 (the precision study) every 1000 iterations, FP64 and
+mixed.
 """
 import math
 import sys
@@ -137,14 +138,15 @@ def test_batched_fp64_precontracted_full_size(gpu, pipe):
     b.close()
 
 
-@pytest.mark.parametrize("pipe", [True, False], ids=["pipelined", "sequential"])
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_longest_chain_every_500(gpu, precision, pipe):
+@pytest.mark.parametrize("precision,pipe,pc", [("fp64", True, False), ("fp64", False, False), ("mixed", True, False),
+                                               ("mixed", False, False), ("fp64", True, True)],
+                         ids=["fp64-pipelined", "fp64-sequential", "mixed-pipelined", "mixed-sequential", "fp64-pc"])
+def test_longest_chain_every_500(gpu, precision, pipe, pc):
     """The workload's longest chain, n=28, M=4, k=6434, checked every 500 iterations."""
     w = inputs.config_c4()
     inst = next(i for i in w.instances if i.n == 28 and i.M == 4)
-    say("case: n=28 M=4 k=%d %s pipeline=%s, every 500 iterations" % (inst.k, precision, pipe))
-    b = gmps.Batch([inst], precision, pipeline=pipe)
+    say("case: n=28 M=4 k=%d %s pipeline=%s precontract=%s, every 500 iterations" % (inst.k, precision, pipe, pc))
+    b = gmps.Batch([inst], precision, pipeline=pipe, precontract=pc)
     b.init_uniform()
     done = 0
     worst = 0.0

@@ -66,20 +66,26 @@ def test_large_cap_small_n_statevector(gpu, precision, pc):
         assert d["status"][i] == 0
 
 
-def test_precontract_beyond_bond_17_or_on_mixed_is_refused(gpu):
-    """The pre-contracted variant is not built for the bond-32 class, and it runs on FP64
-    only: gmps_create refuses both rather than running something else under the flag."""
+def test_precontract_refusals(gpu):
+    """The pre-contracted variant is not built for the bond-32 class, and it runs on FP64 only
+    (on complex64 storage its rotation angle drifts, in both sweep orders): gmps_create refuses
+    both rather than running something else under the flag."""
     W = inputs.draw_marked(12, 24, inputs.SplitMix64(4712))
     inst = inputs.Instance(12, W, inputs.k_rule(12, 24), 27)
     for precision in ("fp64", "mixed"):
         with pytest.raises(gmps.GmpsError) as e:
             gmps.Batch([inst], precision, kernel="team", precontract=True)
         assert e.value.code == gmps.GMPS_E_UNSUPPORTED
-    small = inputs.Instance(12, W[:4], inputs.k_rule(12, 4), 6)
-    with pytest.raises(gmps.GmpsError) as e:
-        gmps.Batch([small], "mixed", kernel="team", precontract=True)
-    assert e.value.code == gmps.GMPS_E_UNSUPPORTED
-    gmps.Batch([small], "fp64", kernel="team", precontract=True).close()
+    small = inputs.Instance(12, W[:4], inputs.k_rule(12, 4), 6)   # bond-5 class (pipelined)
+    mid = inputs.Instance(12, W[:12], inputs.k_rule(12, 12), 13)  # bond-17 class
+    lossy = inputs.Instance(12, W[:4], inputs.k_rule(12, 4), 4)   # cap below the exact rank 5
+    for bad in (small, mid, lossy):
+        for pipe in (True, False):
+            with pytest.raises(gmps.GmpsError) as e:
+                gmps.Batch([bad], "mixed", kernel="team", precontract=True, pipeline=pipe)
+            assert e.value.code == gmps.GMPS_E_UNSUPPORTED
+    for ok in (small, mid, lossy):
+        gmps.Batch([ok], "fp64", kernel="team", precontract=True).close()
 
 
 @pytest.mark.skip(reason="the pre-contracted kernel of the bond-32 class (CM = 32, 256-thread teams) is not "
