@@ -13,7 +13,8 @@ The accuracy gate requires |P_i - sin^2((2k_i+1) theta_i)| <= 1e-6 for every ins
 Besides the headline line, the default run adds legs on the same hardware, in priority order
 while the time budget lasts: the single-instance cases (n=10 and n=20, FP64, median of 5),
 the workload through the FP64 path and with pre-contracted reflections, the n=29 precision
-study (FP64 vs mixed, P logged every 1000 iterations), per-instance FP64 handles, the dense
+study (FP64 vs mixed, P logged every 1000 iterations), the Common method against the Iterative
+one on the single-instance cases, per-instance FP64 handles, the dense
 statevector backend, the all-FP32 precision study and a 5000-iteration prefix of the n=40,
 M=16 workload (pre-contracted reflections in FP64, with 1/8/4096-shot hit fractions).
 The CPU oracle runs first, before the GPU is touched.
@@ -313,6 +314,56 @@ def c3_leg():
                      "final_abs_err_p": errs[-1], "max_abs_err_p": max(errs),
                      "tolerance": 1e-10 if prec == "fp64" else 1e-6, "err_p_every_1000": log}
     out["note"] = "n=29, M=1, k=18198, chi cap 4; P - sin^2((2j+1) theta) after every 1000 iterations"
+    return out
+
+
+def common_leg(reps: int = 3):
+    """The Common method against the Iterative one (Section III-A, Fig. 1; Section IV, Fig. 2),
+    FP64, one instance each of C1, C2 and C3: the iterative path (the library's default plan,
+    and sequential sweeps: the team kernel the circuit runs on), and the k-layer gate-level
+    circuit, its construction (host gate list and upload, wall clock) and its simulation (HIP
+    events), medians over reps runs (one for C3) after an untimed run of each."""
+    from paper_2601_03832_amd import gmps
+    out = {}
+    for w in (inputs.config_c1(), inputs.config_c2(), inputs.config_c3("fp64")):
+        inst = w.instances[0]
+        r = 1 if inst.n >= 29 else reps
+        res = {"k": inst.k, "n": inst.n}
+        for label, pipe in (("iterative_ms", True), ("iterative_sequential_ms", False)):
+            b = gmps.Batch([inst], "fp64", kernel="team", pipeline=pipe)
+            runs = []
+            for rep in range(r + 1):
+                b.init_uniform()
+                b.iterate(inst.k)
+                if rep:
+                    runs.append(b.last_iterate_ms())
+            res[label] = statistics.median(runs)
+            res["abs_err_p_" + label[:-3]] = abs(float(b.marked_prob()[0]) - exact_p(inst.n, inst.M, inst.k))
+            b.close()
+        b = gmps.Batch([inst], "fp64", kernel="team")
+        build, run = [], []
+        nbytes = 0
+        for rep in range(r + 1):
+            t0 = time.perf_counter()
+            nbytes = b.build_circuit(inst.k)
+            t1 = time.perf_counter()
+            b.init_uniform()
+            b.run_circuit()
+            ms = b.last_iterate_ms()
+            if rep:
+                build.append((t1 - t0) * 1e3)
+                run.append(ms)
+        res["common_build_ms"] = statistics.median(build)
+        res["common_run_ms"] = statistics.median(run)
+        res["gates"] = nbytes // 4
+        res["abs_err_p_common"] = abs(float(b.marked_prob()[0]) - exact_p(inst.n, inst.M, inst.k))
+        res["common_over_iterative"] = (res["common_build_ms"] + res["common_run_ms"]) / res["iterative_ms"]
+        res["common_run_over_iterative_sequential"] = res["common_run_ms"] / res["iterative_sequential_ms"]
+        b.close()
+        out[w.name] = res
+    out["note"] = ("Common: the k stacked Grover layers of Fig. 1(A) as one gate list (H, X, n-controlled Z), "
+                   "built on the host and simulated gate by gate (n-controlled Z as its bond-2 MPO with the QR "
+                   "and SVD sweeps, single-qubit gates fused per qubit into the next staging)")
     return out
 
 
@@ -707,6 +758,12 @@ def main():
             log("c3 leg done")
         else:
             skipped.append("c3")
+    if not args.no_small and c4 and args.kernel != "group":
+        if have(60):
+            line["common_method"] = common_leg()
+            log("common method leg done")
+        else:
+            skipped.append("common_method")
     if not args.no_plain:
         if have(30):
             line["plain_fp64"] = plain_fp64_leg(w)

@@ -182,6 +182,37 @@ int mps_init_uniform(gmps_batch* b);
  * (per-instance, each >= 0). Additive: k_done += k. Asynchronous. */
 int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len);
 
+/* The Common method (Section III-A, Fig. 1(B)): instead of re-applying G, the whole circuit of
+ * k stacked Grover layers is built once, as a gate list, and simulated gate by gate. Each layer
+ * holds the gates of Fig. 1(A) in order: per marked x, an X on every qubit where x has a 0 (qubit
+ * 0 the most significant bit), the n-controlled Z, the same X gates; then the diffusion as H and X
+ * on every qubit, the n-controlled Z, X and H on every qubit. (As gates the diffusion is
+ * 2|s><s| - I up to a sign, so a layer is -G and k layers give (-1)^k G^k |s>.) The initial H
+ * layer is mps_init_uniform's. Every n-controlled Z is applied to the MPS as its exact bond-2 MPO
+ * I - 2|1..1><1..1| with the QR and truncated-SVD sweeps of a reflection, the state renormalised
+ * after it; the single-qubit gates between two of them act on the sites' physical index as the
+ * QR sweep stages them (the gates on one qubit multiplied first), and those after the last one
+ * act on the sites in place. The gate list lives in device memory that the caller owns: one
+ * 32-bit word per gate (type in bits 8-15: 0 = H, 1 = X, 2 = n-controlled Z; qubit in bits 0-7).
+ * FP64 and the team kernel only, bond caps up to 17, n >= 2.
+ *
+ * gmps_circuit_bytes: bytes of the gate lists of k layers for every instance (k: host, k_len == 1
+ * or B, each >= 0; inst and marked as for gmps_create); 0 on invalid input. */
+size_t gmps_circuit_bytes(const gmps_instance* inst, int32_t B, const uint64_t* marked, const int64_t* k,
+                          int32_t k_len);
+
+/* Builds every instance's k-layer gate list on the host and copies it into dev_gates (device,
+ * at least gmps_circuit_bytes() bytes, 4-byte aligned, owned by the caller and read by
+ * grover_circuit_run until the next build). Synchronises. Errors: GMPS_E_ARG, GMPS_E_WORKSPACE
+ * (buffer too small or misaligned), GMPS_E_UNSUPPORTED (GMPS_MIXED, the lane-group kernel, an
+ * instance with n < 2 or an effective bond cap above 17), GMPS_E_HIP. */
+int gmps_circuit_build(gmps_batch* b, const int64_t* k, int32_t k_len, void* dev_gates, size_t bytes);
+
+/* Runs the built circuits on the current chains (normally |s> from mps_init_uniform): one
+ * launch of the sequential team kernels; k_done grows by each circuit's k. Asynchronous;
+ * gmps_last_iterate_ms times it. Errors: GMPS_E_ARG (no circuit built), GMPS_E_HIP. */
+int grover_circuit_run(gmps_batch* b);
+
 /* grover_iterate and then perfect sampling of every instance's final state in the same graph
  * launch (a hit-counter fill kernel, the class kernels, the sampling kernel), for runs that
  * need the hit counts only. The draws are sample_shots' (same Philox stream, seed and shot

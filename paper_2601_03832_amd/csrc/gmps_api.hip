@@ -25,6 +25,9 @@ int team_per_bundle(int cls);
 size_t team_lds_bytes(bool mixed, bool pc, bool pipe, int cls);
 hipError_t launch_team(bool mixed, bool pc, bool pipe, int cls, const IterParams& P, int grid, size_t lds, hipStream_t st);
 hipError_t team_occupancy(bool mixed, bool pc, bool pipe, int cls, size_t lds, int* blocks_per_cu);
+size_t team_circ_lds_bytes(int cls);
+hipError_t launch_team_circ(int cls, const IterParams& P, int grid, size_t lds, hipStream_t st);
+hipError_t team_circ_occupancy(int cls, size_t lds, int* blocks_per_cu);
 hipError_t launch_queue_reset(QueueState* q, hipStream_t st);
 hipError_t launch_init(bool mixed, InstDev* inst, int B, const int64_t* site_start, int32_t* bonds, void* arena,
                        int64_t total_sites, char* warm, void* edge, hipStream_t st);
@@ -184,6 +187,10 @@ struct gmps_batch {
   bool pipeline_ok = false;
   bool pc_ok = false;
   std::string device_name;
+  // gate-level circuits (gmps_circuit_build): the caller's device buffer of gate streams and
+  // the layers each instance's circuit holds
+  const uint32_t* circuit = nullptr;
+  std::vector<int64_t> circ_k;
 };
 
 // Scratch of sample_shots_noalloc: hit counters, shot offsets and bitstrings, in device memory
@@ -459,7 +466,7 @@ struct SampleReq {
   uint64_t seed;
 };
 
-int iterate_impl(gmps_batch* b, const int64_t* k, int32_t k_len, const SampleReq* smp);
+int iterate_impl(gmps_batch* b, const int64_t* k, int32_t k_len, const SampleReq* smp, bool circuit = false);
 
 }  // namespace
 
@@ -470,6 +477,99 @@ int grover_iterate(gmps_batch* b, const int64_t* k, int32_t k_len) {
   for (int i = 0; i < k_len; ++i)
     if (k[i] < 0) return GMPS_E_ARG;
   return iterate_impl(b, k, k_len, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Gates of one layer of Fig. 1(A) for instance (n, marked): per marked x, X on each qubit where
+// x has a 0, the n-controlled Z, the same X gates; then the diffusion as H, X on every qubit,
+// the n-controlled Z, X and H on every qubit.
+int64_t layer_gates(int n, const uint64_t* x, int M) {
+  int64_t g = 0;
+  for (int t = 0; t < M; ++t) g += 2 * (n - __builtin_popcountll(x[t])) + 1;
+  return g + 4 * (int64_t)n + 1;
+}
+
+void append_layer(std::vector<uint32_t>& out, int n, const uint64_t* x, int M) {
+  for (int t = 0; t < M; ++t) {
+    for (int q = 0; q < n; ++q)
+      if (!((x[t] >> (n - 1 - q)) & 1ull)) out.push_back(gate_word(kGateX, q));
+    out.push_back(gate_word(kGateMCZ, 0));
+    for (int q = 0; q < n; ++q)
+      if (!((x[t] >> (n - 1 - q)) & 1ull)) out.push_back(gate_word(kGateX, q));
+  }
+  for (int q = 0; q < n; ++q) out.push_back(gate_word(kGateH, q));
+  for (int q = 0; q < n; ++q) out.push_back(gate_word(kGateX, q));
+  out.push_back(gate_word(kGateMCZ, 0));
+  for (int q = 0; q < n; ++q) out.push_back(gate_word(kGateX, q));
+  for (int q = 0; q < n; ++q) out.push_back(gate_word(kGateH, q));
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gmps_circuit_bytes(const gmps_instance* inst, int32_t B, const uint64_t* marked, const int64_t* k,
+                          int32_t k_len) {
+  if (!inst || B <= 0 || !marked || !k || (k_len != 1 && k_len != B)) return 0;
+  size_t total = 0;
+  for (int i = 0; i < B; ++i) {
+    const int64_t ki = k[k_len == 1 ? 0 : i];
+    if (!valid_instance(inst[i]) || ki < 0) return 0;
+    total += sizeof(uint32_t) * (size_t)(ki * layer_gates(inst[i].n, marked + inst[i].marked_off, inst[i].M));
+  }
+  return total;
+}
+
+int gmps_circuit_build(gmps_batch* b, const int64_t* k, int32_t k_len, void* dev_gates, size_t bytes) {
+  if (!b || !k || (k_len != 1 && k_len != b->B)) return GMPS_E_ARG;
+  if (b->path != kPathTeam || b->mixed) return GMPS_E_UNSUPPORTED;
+  for (int i = 0; i < b->B; ++i) {
+    const InstDev& d = b->inst_h[i];
+    if (k[k_len == 1 ? 0 : i] < 0) return GMPS_E_ARG;
+    if (d.n < 2 || !(is_wide(d.cls) && team_pc_class(d.cls - kWideBase))) return GMPS_E_UNSUPPORTED;
+  }
+  // the marked sets as the library holds them (packed per instance)
+  std::vector<uint64_t> mk(b->lay.total_marked);
+  GMPS_HIP(hipMemcpyAsync(mk.data(), b->params.marked, sizeof(uint64_t) * mk.size(), hipMemcpyDeviceToHost, b->stream));
+  GMPS_HIP(hipStreamSynchronize(b->stream));
+  size_t need = 0;
+  for (int i = 0; i < b->B; ++i) {
+    const InstDev& d = b->inst_h[i];
+    need += sizeof(uint32_t) * (size_t)(k[k_len == 1 ? 0 : i] * layer_gates(d.n, mk.data() + d.marked_off, d.M));
+  }
+  if (need > 0 && (!dev_gates || bytes < need || (reinterpret_cast<uintptr_t>(dev_gates) % 4) != 0))
+    return GMPS_E_WORKSPACE;
+  // each instance's k layers, built on the host and copied in turn
+  uint32_t* dst = static_cast<uint32_t*>(dev_gates);
+  int64_t off = 0;
+  std::vector<uint32_t> g;
+  b->circ_k.assign(b->B, 0);
+  for (int i = 0; i < b->B; ++i) {
+    InstDev& d = b->inst_h[i];
+    const int64_t ki = k[k_len == 1 ? 0 : i];
+    const uint64_t* x = mk.data() + d.marked_off;
+    g.clear();
+    g.reserve((size_t)(ki * layer_gates(d.n, x, d.M)));
+    for (int64_t l = 0; l < ki; ++l) append_layer(g, d.n, x, d.M);
+    if (!g.empty()) GMPS_HIP(hipMemcpy(dst + off, g.data(), sizeof(uint32_t) * g.size(), hipMemcpyHostToDevice));
+    d.circ_off = off;
+    d.circ_len = (int64_t)g.size();
+    off += (int64_t)g.size();
+    b->circ_k[i] = ki;
+  }
+  GMPS_HIP(hipMemcpyAsync(b->params.inst, b->inst_h.data(), sizeof(InstDev) * b->B, hipMemcpyHostToDevice, b->stream));
+  GMPS_HIP(hipStreamSynchronize(b->stream));
+  b->circuit = static_cast<const uint32_t*>(dev_gates);
+  return GMPS_OK;
+}
+
+int grover_circuit_run(gmps_batch* b) {
+  if (!b) return GMPS_E_ARG;
+  if (b->circ_k.size() != (size_t)b->B) return GMPS_E_ARG;  // no circuit built
+  return iterate_impl(b, b->circ_k.data(), b->B, nullptr, true);
 }
 
 int grover_iterate_sample(gmps_batch* b, const int64_t* k, int32_t k_len, const int64_t* shots, int32_t shots_len,
@@ -498,7 +598,7 @@ int grover_iterate_sample(gmps_batch* b, const int64_t* k, int32_t k_len, const 
 
 namespace {
 
-int iterate_impl(gmps_batch* b, const int64_t* k, int32_t k_len, const SampleReq* smp) {
+int iterate_impl(gmps_batch* b, const int64_t* k, int32_t k_len, const SampleReq* smp, bool circuit) {
   // Bundle instances that share (class, n, M, k), then order each kernel's bundles by
   // estimated cost, longest first, so the persistent queue hands out the long serial
   // chains early.
@@ -535,7 +635,8 @@ int iterate_impl(gmps_batch* b, const int64_t* k, int32_t k_len, const SampleReq
     // a site step of either kernel takes roughly (CM + 1) times a fixed latency
     const int refl = g.first.whole ? 2 : g.first.M + 1;  // reflections per iteration
     const double cost = (double)g.first.k * refl * std::max(1, g.first.n - 1) * (class_cm(cls) + 1.0);
-    lds[kind] = std::max(lds[kind], team ? team_lds_bytes(b->mixed, b->precontract, b->pipeline, cls) : group_lds_bytes(group_mode(b), cls) * per);
+    lds[kind] = std::max(lds[kind], team ? (circuit ? team_circ_lds_bytes(cls) : team_lds_bytes(b->mixed, b->precontract, b->pipeline, cls))
+                                         : group_lds_bytes(group_mode(b), cls) * per);
     for (size_t s = 0; s < g.second.size(); s += per) {
       Bundle bd;
       std::memset(&bd, 0, sizeof(bd));
@@ -579,6 +680,7 @@ int iterate_impl(gmps_batch* b, const int64_t* k, int32_t k_len, const SampleReq
     if (count[kd] == 0) continue;
     int per_cu = 0;
     if (kd == 0) GMPS_HIP(group_occupancy(group_mode(b), lds[kd], &per_cu));
+    else if (circuit) GMPS_HIP(team_circ_occupancy(kWideBase + kd - 1, lds[kd], &per_cu));
     else GMPS_HIP(team_occupancy(b->mixed, b->precontract, b->pipeline, kWideBase + kd - 1, lds[kd], &per_cu));
     if (b->waves_per_cu > 0) per_cu = std::min(per_cu, b->waves_per_cu);
     per_cu = std::max(per_cu, 1);
@@ -595,6 +697,8 @@ int iterate_impl(gmps_batch* b, const int64_t* k, int32_t k_len, const SampleReq
   }
   // sampling appended to the launch: its total and seed are kernel arguments of the graph
   if (smp) key.insert(key.end(), {-1, smp->total, (int64_t)smp->seed});
+  // the gate-level circuit kernels read the gate streams
+  if (circuit) key.insert(key.end(), {-2, (int64_t)reinterpret_cast<uintptr_t>(b->circuit)});
   Bundle* dev_bundles = reinterpret_cast<Bundle*>(b->ws + b->lay.bundles);
   QueueState* dev_queue = reinterpret_cast<QueueState*>(b->ws + b->lay.queue);
   // the kernels of different classes run side by side: the first on st, the others on side
@@ -630,6 +734,7 @@ int iterate_impl(gmps_batch* b, const int64_t* k, int32_t k_len, const SampleReq
       IterParams P = b->params;
       P.bundles = dev_bundles + first[kd];
       P.queue = dev_queue + kd;
+      P.circuit = circuit ? b->circuit : nullptr;
       // The team kernels compute in FP64 and compensate their complex64 stores: they round to
       // nearest unless stochastic rounding is asked for, and their Jacobi rotates every column
       // above the FP64 floor. The lane-group kernel computes in the storage type on the mixed
@@ -638,8 +743,9 @@ int iterate_impl(gmps_batch* b, const int64_t* k, int32_t k_len, const SampleReq
       const bool comp = kd > 0;
       P.stoch_round = (b->mixed && !b->fp32 && (comp ? b->round_mode == 1 : b->round_mode != -1)) ? 1 : 0;
       if (comp) P.skip_tol = std::min(b->trunc_tol, 1e-15);
-      e = kd == 0 ? launch_group(group_mode(b), P, grid[kd], lds[kd], ks)
-                  : launch_team(b->mixed, b->precontract, b->pipeline, kWideBase + kd - 1, P, grid[kd], lds[kd], ks);
+      e = kd == 0   ? launch_group(group_mode(b), P, grid[kd], lds[kd], ks)
+          : circuit ? launch_team_circ(kWideBase + kd - 1, P, grid[kd], lds[kd], ks)
+                    : launch_team(b->mixed, b->precontract, b->pipeline, kWideBase + kd - 1, P, grid[kd], lds[kd], ks);
       if (e == hipSuccess && !on_main) {
         e = hipEventRecord(b->join_ev[kd], ks);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join_ev[kd], 0);

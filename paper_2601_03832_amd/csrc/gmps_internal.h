@@ -19,7 +19,14 @@ struct InstDev {
   int64_t edge_off;        // complex-FP64 offset of this instance's first edge slot
   int32_t ew;              // edge width: sites i < ew and i >= n - ew are edge sites
   int32_t pad_;
+  int64_t circ_off;        // gate-level circuit: first gate of this instance's stream
+  int64_t circ_len;        // gate-level circuit: gates in the stream
 };
+
+// Gate-level circuits (the Common method): one 32-bit word per gate, the gate type in bits
+// 8..15 and the qubit (site) in bits 0..7; the n-controlled Z acts on every qubit.
+enum : uint32_t { kGateH = 0u, kGateX = 1u, kGateMCZ = 2u };
+__host__ __device__ constexpr uint32_t gate_word(uint32_t type, uint32_t q) { return (type << 8) | (q & 0xFFu); }
 
 // Edge sites. A stored isometry changes the state by its rounding error d times the rest of
 // the chain; the kernels fold the part of d inside the span of the stored vectors into the FP64
@@ -120,6 +127,7 @@ struct IterParams {
   int32_t stoch_round;  // stochastic (1) or nearest (0) rounding of FP64 results stored as complex64
   void* warm;           // warm-start records (null: every Jacobi starts from the identity)
   void* edge;           // edge slots (complex FP64)
+  const uint32_t* circuit;  // gate streams of the gate-level circuits (null: reflections)
 };
 
 }  // namespace gmps

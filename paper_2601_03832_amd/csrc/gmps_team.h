@@ -230,6 +230,32 @@ struct TeamAPre {
       }
     }
   }
+  // stage64 for a gate-level circuit: the pending single-qubit product u (real 2x2, row-major)
+  // acts on the physical index first, then the projector |xb><xb| of the n-controlled Z
+  __device__ __forceinline__ void stage64u(cd (*W)[CM][2][CM], const cd* es, int tl, const double* u, int xb,
+                                           double c0, double c1) const {
+    constexpr int D = 2 * CM;
+    const double u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tl + t * TW;
+      if (e < CM * CM) {
+        const int a = e / CM, b = e % CM;
+        const bool ok = a < chl_ && b < chr_;
+        cd a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+        if (ok) {
+          a0 = es ? es[a * 2 * D + b] : up(v0[t]);
+          a1 = es ? es[a * 2 * D + D + b] : up(v1[t]);
+        }
+        const cd b0 = {u00 * a0.re + u01 * a1.re, u00 * a0.im + u01 * a1.im};
+        const cd b1 = {u10 * a0.re + u11 * a1.re, u10 * a0.im + u11 * a1.im};
+        W[0][a][0][b] = c0 * b0;
+        W[0][a][1][b] = c0 * b1;
+        W[1][a][0][b] = c1 * proj_apply<double>(b0, b1, 0, false, xb);
+        W[1][a][1][b] = c1 * proj_apply<double>(b0, b1, 1, false, xb);
+      }
+    }
+  }
   __device__ __forceinline__ void stage_a64(cd (*W)[CM][2][CM], const cd* es, int tl, double c0) const {
     constexpr int D = 2 * CM;
 #pragma unroll
@@ -848,6 +874,13 @@ __device__ __forceinline__ void comp_store_rows(const cd (&wv)[RJ], const cx<S> 
 }
 
 // ------------------------------------------------------------------------------- one team
+// Gate-level circuits (the Common method): per team, the product of the single-qubit gates each
+// qubit has received since its site was last staged. H and X are real, so the products are real
+// 2x2 matrices (row-major). The block sits after the workgroup's TeamLds blocks.
+struct CircLds {
+  double U[kBondStride][4];
+};
+
 template <class S, int CM, int TW>
 __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base) {
   using T = TeamShape<CM, TW>;
@@ -1335,6 +1368,537 @@ __device__ void run_team(const IterParams& P, const Bundle* bdp, char* lds_base)
   team_sync_global();
 }
 
+// run_team for a gate-level circuit (the Common method; a separate function, so that the
+// reflection kernels keep their own code): the reflections come from the instance's gate stream
+// (P.circuit) instead of its marked set. Every n-controlled Z is a reflection about |1..1>
+// (c0 = 1, c1 = -2, renormalised), the single-qubit gates before it are fused per qubit and
+// applied as its sites are staged, and the gates after the last one are applied to the sites in
+// place at the end. The stream holds k (M+1) n-controlled Z gates, as k layers of Fig. 1(A) do.
+template <class S, int CM, int TW>
+__device__ void run_team_circ(const IterParams& P, const Bundle* bdp, char* lds_base) {
+  using T = TeamShape<CM, TW>;
+  constexpr int D = T::D, KQ = T::KQ, KJ = T::KJ;
+  constexpr int PQ = T::PQ, RQ = T::RQ, PJ = T::PJ, RJ = T::RJ, RU = T::RU;
+  constexpr int SLOT = slot_elems(CM);
+  constexpr bool kMixed = sizeof(S) == sizeof(float);
+  constexpr int64_t WREC = wide_warm_doubles(CM);
+  const int tid = threadIdx.x;
+  const int team = tid / TW;
+  const int tl = tid % TW;
+  const int qc = tl / PQ, qh = tl % PQ;  // QR layout
+  const int jc = tl / PJ, jh = tl % PJ;  // Jacobi layout
+  const int base = tid - tl;             // first thread of the team (a lane, for TW <= 64)
+  const bool real = team < bdp->count;
+  // inst[] is indexed per lane: read it from memory, not from a register copy
+  const int me = bdp->inst[real ? team : 0];
+  TeamLds<S, CM, TW>& L = reinterpret_cast<TeamLds<S, CM, TW>*>(lds_base)[team];
+  InstDev* I = P.inst + me;
+  const int n = I->n;
+  const int M = I->M;
+  const int cap = I->cap < CM ? I->cap : CM;
+  const int64_t k = bdp->k;
+  cx<S>* arena = reinterpret_cast<cx<S>*>(P.arena) + I->site_off;
+  cd* edges = reinterpret_cast<cd*>(P.edge) + I->edge_off;
+  const int ew = I->ew;
+  // the complex-FP64 slot of an edge site, or null for a bulk site
+  auto eslot = [&](int i) -> cd* {
+    const int ei = edge_index(i, n, ew);
+    return ei >= 0 ? edges + (int64_t)ei * SLOT : nullptr;
+  };
+  const double tol2 = P.trunc_tol * P.trunc_tol;
+  const double rank2 = P.rank_tol * P.rank_tol;
+  const double skip2 = P.skip_tol * P.skip_tol;
+  const bool sr = P.stoch_round != 0;
+  double* warm = P.warm ? reinterpret_cast<double*>(reinterpret_cast<char*>(P.warm) + I->warm_off) : nullptr;
+  // without warm starts the record loads read this instance's own records area: the site
+  // slots, which hold at least one record's worth of elements (never used)
+  const double* wdummy = reinterpret_cast<const double*>(reinterpret_cast<cx<S>*>(P.arena) + I->site_off);
+  // read once: a global load inside the sweeps would be waited for at its use
+  const uint64_t k_done0 = (uint64_t)I->k_done;
+  uint64_t rs_state = mix64(((uint64_t)me << 32) ^ (k_done0 * 0x9E3779B97F4A7C15ull) ^ (uint64_t)tl);
+
+  for (int l = tl; l < kBondStride; l += TW) L.bond[l] = P.bonds[(int64_t)me * kBondStride + l];
+  lds_sync();
+
+  double f64 = 0.0, f32 = 0.0, drift = 0.0, truncw = 0.0;
+  int status = 0;
+
+  if (n < 2) {
+    // gmps_circuit_build refuses chains of one site
+    status |= GMPS_ST_NAN;
+  } else {
+    // gate-level circuit: lane 0 of the team walks the stream; the walk takes no workgroup
+    // barrier (the teams of a workgroup walk streams of different lengths), and every team
+    // reaches the barrier after it once per n-controlled Z
+    CircLds& C = reinterpret_cast<CircLds*>(lds_base + TeamShape<CM, TW>::TEAMS * sizeof(TeamLds<S, CM, TW>))[team];
+    const uint32_t* gates = P.circuit + I->circ_off;
+    const int64_t ngates = I->circ_len;
+    int64_t gpos = 0;
+    auto walk = [&]() {
+      if (tl == 0) {
+        for (int q = 0; q < n; ++q) {
+          C.U[q][0] = 1.0;
+          C.U[q][1] = 0.0;
+          C.U[q][2] = 0.0;
+          C.U[q][3] = 1.0;
+        }
+        while (gpos < ngates) {
+          const uint32_t g = gates[gpos++];
+          const uint32_t ty = g >> 8, q = g & 0xFFu;
+          if (ty == kGateMCZ) break;
+          double* u = C.U[q < (uint32_t)n ? q : 0];
+          const double a = u[0], b = u[1], c = u[2], d = u[3];
+          if (ty == kGateH) {
+            u[0] = kInvSqrt2 * (a + c);
+            u[1] = kInvSqrt2 * (b + d);
+            u[2] = kInvSqrt2 * (a - c);
+            u[3] = kInvSqrt2 * (b - d);
+          } else {  // X
+            u[0] = c;
+            u[1] = d;
+            u[2] = a;
+            u[3] = b;
+          }
+        }
+      }
+      lds_sync();
+    };
+    for (int64_t it = 0; it < k; ++it) {
+      for (int j = 0; j <= M; ++j) {
+        // the next n-controlled Z, I - 2|1..1><1..1|, after the single-qubit gates before it
+        walk();
+        const bool diff = false;
+        const uint64_t xw = ~0ull;
+        const double c0 = 1.0, c1 = -2.0;
+        const bool renorm = true;  // after every n-controlled Z
+
+        // ---------------------------------------------- QR sweep with the MPO fused
+        int r = 1;
+        if (tl == 0) {
+          L.rdim[0] = 1;
+          // the first site's tile is [A | P A] itself: R = [1 1] over the two MPO blocks
+          L.u.q.R[0][0] = {1.0, 0.0};
+          L.u.q.R[0][1] = {1.0, 0.0};
+        }
+        TeamAPre<S, CM, TW> apre;
+        apre.load(arena, tl, L.bond[0], L.bond[1]);
+        lds_sync();
+        for (int i = 0; i < n; ++i) {
+          const int chl = L.bond[i], chr = L.bond[i + 1];
+          const bool first = (i == 0), last = (i == n - 1);
+          const int xb = diff ? 0 : (int)((xw >> (n - 1 - i)) & 1ull);
+          const int Dl = first ? 1 : 2 * chl;
+          const int Dr = last ? 1 : 2 * chr;
+          cx<S>* slot = arena + (int64_t)i * SLOT;
+          cd* es = eslot(i);
+          apre.stage64u(L.u.q.W, es, tl, C.U[i], xb, last ? c0 : 1.0, last ? c1 : 1.0);
+          if (i + 1 < n) apre.load(arena + (int64_t)(i + 1) * SLOT, tl, L.bond[i + 1], L.bond[i + 2]);
+          lds_sync();
+          // X = R_{i-1} * MPO(A_i): this slot's column, rows (a, s) = part + PQ*e
+          cd x[RQ];
+          {
+            const int beta = (!last && qc >= chr) ? 1 : 0;
+            const int bcol = qc - beta * chr;
+#pragma unroll
+            for (int e = 0; e < RQ; ++e) {
+              const int row = qh + PQ * e;
+              const int a = row >> 1, s = row & 1;
+              cd acc = {0.0, 0.0};
+              if (row < 2 * r && qc < Dr) {
+                // the last site sums both MPO blocks into its one column
+#pragma unroll
+                for (int bl = 0; bl < 2; ++bl) {
+                  if (last || bl == beta) {
+#pragma unroll
+                    for (int ap = 0; ap < CM; ++ap)
+                      if (ap < chl) acc = cfma(acc, L.u.q.R[a][bl * chl + ap], L.u.q.W[bl][ap][s][bcol]);
+                  }
+                }
+              }
+              x[e] = acc;
+            }
+          }
+          f64 += 8.0 * (double)r * Dl * 2.0 * Dr;
+          if (last) {
+            // the last site holds the norm: to its edge slot in FP64, to its site slot as stored
+            if (real && qc == 0) {
+#pragma unroll
+              for (int e = 0; e < RQ; ++e) {
+                const int row = qh + PQ * e;
+                if (row < 2 * r) {
+                  slot[(row >> 1) * 2 * D + (row & 1) * D] = store_cast<S>(x[e], rs_state, sr);
+                  es[(row >> 1) * 2 * D + (row & 1) * D] = x[e];
+                }
+              }
+            }
+            if (tl == 0) {
+              L.rdim[n - 1] = r;
+              L.rdim[n] = 1;
+            }
+            break;
+          }
+          const int m = 2 * r;
+          cd q[RQ];
+          double qdrop = 0.0;
+          int kr;
+          if constexpr (TW <= 64)
+            kr = team_qr_wave<TW, PQ, RQ, KQ>(x, q, base, qc, qh, m, Dr, chr, rank2, &qdrop, L.u.q.V, L.u.q.tau);
+          else
+            kr = team_qr_lds<PQ, RQ, KQ>(x, q, qc, qh, m, Dr, chr, rank2, &qdrop, L.u.q.V, L.u.q.tau, L.colv);
+          truncw = fmax(truncw, qdrop);
+          {
+            const double mm = m, cc = Dr, kk = kr;
+            f64 += 8.0 * (2.0 * mm * cc * kk - (mm + cc) * kk * kk + 2.0 * kk * kk * kk / 3.0) +
+                   8.0 * (2.0 * mm * kk * kk - 2.0 * kk * kk * kk / 3.0);
+          }
+          cx<S> qs[RQ];  // Q as stored
+#pragma unroll
+          for (int e = 0; e < RQ; ++e) qs[e] = store_cast<S>(q[e], rs_state, sr);
+          if (real && qc < kr) {
+#pragma unroll
+            for (int e = 0; e < RQ; ++e) {
+              const int row = qh + PQ * e;
+              if (row < m) {
+                slot[(row >> 1) * 2 * D + (row & 1) * D + qc] = qs[e];
+                if (es) es[(row >> 1) * 2 * D + (row & 1) * D + qc] = q[e];
+              }
+            }
+          }
+          if (qc < Dr) {
+#pragma unroll
+            for (int e = 0; e < RQ; ++e) {
+              const int row = qh + PQ * e;
+              if (row < kr) L.u.q.R[row][qc] = x[e];
+            }
+          }
+          if (kMixed && !es) {
+            comp_store_cols<PQ, RQ, KQ, D>(q, qs, qc, qh, kr, Dr, L.u.q.V, L.zbuf(), L.u.q.R);
+            f64 += 8.0 * ((double)kr * kr * m + (double)kr * kr * Dr);
+          }
+          if (tl == 0) L.rdim[i + 1] = kr;
+          r = kr;
+          lds_sync();
+        }
+        // the QR sweep's site tensors are read by every wave of the team from here on
+        team_sync_global();
+
+        // ---------------------------------------------- truncated-SVD sweep
+        // At site i the tile is M = Q_i (U Sigma)_{i+1} reshaped (r_i, 2 chi'); Jacobi runs on
+        // the r_i columns of M^H: M^H J = V Sigma with J = U, so V^H = Sigma^{-1} (M^H J)^H
+        // stays in site i and U Sigma = J Sigma moves left.
+        if (tl == 0) L.u.s.Y[0][0] = {1.0, 0.0};
+        TeamQPre<S, KQ, CM, TW> qpre;
+        TeamWPre<KJ, TW> wpre;
+        qpre.load(arena + (int64_t)(n - 1) * SLOT, tl, L.rdim[n - 1], L.rdim[n]);
+        wpre.load(warm ? warm + ((int64_t)j * n + (n - 1)) * WREC : wdummy, warm != nullptr, tl, (L.rdim[n - 1] + 1) & ~1);
+        for (int i = n - 1; i >= 1; --i) {
+          const int ri = L.rdim[i], rn = L.rdim[i + 1];
+          const int chn = L.bond[i + 1];
+          const int c = 2 * chn;
+          const int ncj = (ri + 1) & ~1;
+          cx<S>* slot = arena + (int64_t)i * SLOT;
+          cd* es = eslot(i);
+          double* wrec = warm ? warm + ((int64_t)j * n + i) * WREC : nullptr;
+          const bool use_warm = wrec && wpre.r() == ncj;
+          // the stored unitary is a product of exact rotations, so its unitarity drifts by
+          // ~1e-16 per use; one Newton-Schulz step every 64 iterations keeps it below ~1e-13
+          const bool renorm_warm = use_warm && ((k_done0 + (uint64_t)it) & 63ull) == 0ull;
+          if (es) {
+            // an edge site (the first one holds the norm): from its complex-FP64 edge slot
+            for (int e = tl; e < KQ * 2 * KQ; e += TW) {
+              const int a = e / (2 * KQ), s = (e / KQ) & 1, b = e % KQ;
+              (&L.u.s.Q[0][0][0])[e] = (a < ri && b < rn) ? es[a * 2 * D + s * D + b] : cd{0.0, 0.0};
+            }
+          } else {
+            qpre.stage(&L.u.s.Q[0][0][0], tl);
+          }
+          if (use_warm) wpre.stage(&L.u.s.W[0][0], tl);
+          if (i - 1 >= 1) {
+            qpre.load(arena + (int64_t)(i - 1) * SLOT, tl, L.rdim[i - 1], L.rdim[i]);
+            wpre.load(warm ? warm + ((int64_t)j * n + (i - 1)) * WREC : wdummy, warm != nullptr, tl,
+                      (L.rdim[i - 1] + 1) & ~1);
+          }
+          lds_sync();
+          // column jc of M^H: M^H[(s, jj)][a] = conj(sum_b Q[a][s][b] Y[b][jj])
+          cd a[RJ];
+#pragma unroll
+          for (int e = 0; e < RJ; ++e) {
+            const int row = jh + PJ * e;
+            const int s = row >= chn ? 1 : 0;
+            const int jj = row - s * chn;
+            cd acc = {0.0, 0.0};
+            if (jc < ri && row < c) {
+#pragma unroll
+              for (int b = 0; b < KQ; ++b)
+                if (b < rn) acc = cfma(acc, L.u.s.Q[jc][s][b], L.u.s.Y[b][jj]);
+            }
+            a[e] = conj(acc);
+          }
+          f64 += 8.0 * (double)ri * 2.0 * rn * chn;
+          if (renorm_warm) {
+            // one Newton-Schulz polar step W <- W (3I - W^H W) / 2 (error e -> O(e^2))
+            cd* WG = &L.u.s.XU[0][0][0];  // KJ x KJ, row-major
+            for (int e = tl; e < KJ * KJ; e += TW) {
+              const int ra = e / KJ, ca = e % KJ;
+              cd g = {0.0, 0.0};
+              for (int b = 0; b < ncj; ++b) g = g + cmulc(L.u.s.W[b][ra], L.u.s.W[b][ca]);
+              WG[e] = g;
+            }
+            lds_sync();
+            constexpr int NW = (KJ * KJ + TW - 1) / TW;
+            cd wn[NW];
+#pragma unroll
+            for (int t = 0; t < NW; ++t) {
+              const int e = tl + t * TW;
+              const int ra = e / KJ, ca = e % KJ;
+              cd acc = {0.0, 0.0};
+              if (e < KJ * KJ)
+                for (int b = 0; b < ncj; ++b) acc = cfma(acc, L.u.s.W[ra][b], WG[b * KJ + ca]);
+              wn[t] = (e < KJ * KJ) ? 1.5 * L.u.s.W[ra][ca] - 0.5 * acc : cd{0.0, 0.0};
+            }
+            lds_sync();
+#pragma unroll
+            for (int t = 0; t < NW; ++t) {
+              const int e = tl + t * TW;
+              if (e < KJ * KJ) L.u.s.W[e / KJ][e % KJ] = wn[t];
+            }
+            lds_sync();
+          }
+          cd uu[RU];
+          if (use_warm) {
+            // start from the previous iteration's unitary: M^H <- M^H W
+            if (jc < KJ) {
+#pragma unroll
+              for (int e = 0; e < RJ; ++e) L.u.s.XA[0][jc][jh + PJ * e] = a[e];
+            }
+            lds_sync();
+#pragma unroll
+            for (int e = 0; e < RJ; ++e) {
+              const int row = jh + PJ * e;
+              cd acc = {0.0, 0.0};
+              if (jc < ncj)
+                for (int b = 0; b < ncj; ++b) acc = cfma(acc, L.u.s.XA[0][b][row], L.u.s.W[b][jc]);
+              a[e] = acc;
+            }
+#pragma unroll
+            for (int e = 0; e < RU; ++e) {
+              const int row = jh + PJ * e;
+              uu[e] = (jc < ncj && row < ncj) ? L.u.s.W[row][jc] : cd{0.0, 0.0};
+            }
+            lds_sync();
+          } else {
+#pragma unroll
+            for (int e = 0; e < RU; ++e) uu[e] = {(jh + PJ * e == jc && jc < ncj) ? 1.0 : 0.0, 0.0};
+          }
+          int sweeps;
+          if constexpr (TW <= 64)
+            sweeps = team_jacobi_wave<TW, PJ, RJ, RU>(a, uu, base, jc, jh, ncj, kJacobiTol2, skip2, P.max_sweeps);
+          else
+            sweeps = team_jacobi_lds<PJ, RJ, RU, KJ, T::NBUF>(a, uu, jc, jh, ncj, kJacobiTol2, skip2, P.max_sweeps,
+                                                              L.u.s.XA, L.u.s.XU, L.u.s.XN, L.colv, L.colf);
+          f64 += (double)sweeps * ri * (ri - 1) / 2.0 * 56.0 * c;
+          // singular values, truncation and the kept order
+          const bool colok = jc < ncj;
+          double sg = 0.0;
+#pragma unroll
+          for (int e = 0; e < RJ; ++e) sg += norm2(a[e]);
+          sg = gsum<PJ>(sg);
+          // kept columns stay in their index order (so the bond basis, and the next warm
+          // start, does not jump when Schmidt values are degenerate); dropped ones follow
+          double stot, dropped;
+          int chi_new, pos;
+          bool keep;
+          if constexpr (TW <= 64) {
+            const double mine = colok ? sg : 0.0;
+            const double smax = tmax<TW>(mine);
+            stot = tsum<TW>(jh == 0 ? mine : 0.0);
+            const int above = (int)tsum<TW>((jh == 0 && mine > 0.0 && mine >= tol2 * smax) ? 1.0 : 0.0);
+            int rk = 0;
+            for (int o = 0; o < ncj; ++o) {
+              const double v = shfl_f64(mine, base + o * PJ);
+              rk += (v > sg || (v == sg && o < jc)) ? 1 : 0;
+            }
+            chi_new = above < cap ? above : cap;
+            if (chi_new < 1) chi_new = 1;
+            keep = colok && rk < chi_new;
+            const uint64_t kept = tballot<TW>(jh == 0 && keep, base);
+            const int nk = __popcll(kept & ((1ull << (base + jc * PJ)) - 1ull));
+            pos = keep ? nk : chi_new + (jc - nk);
+            dropped = tsum<TW>((jh == 0 && colok && !keep) ? sg : 0.0);
+          } else {
+            if (jh == 0) L.colv[jc] = colok ? sg : 0.0;
+            lds_sync();
+            double smax = 0.0;
+            stot = 0.0;
+            for (int o = 0; o < ncj; ++o) {
+              const double v = L.colv[o];
+              smax = fmax(smax, v);
+              stot += v;
+            }
+            int above = 0, rk = 0;
+            for (int o = 0; o < ncj; ++o) {
+              const double v = L.colv[o];
+              above += (v > 0.0 && v >= tol2 * smax) ? 1 : 0;
+              rk += (v > sg || (v == sg && o < jc)) ? 1 : 0;
+            }
+            chi_new = above < cap ? above : cap;
+            if (chi_new < 1) chi_new = 1;
+            if (jh == 0) L.colr[jc] = colok ? rk : KJ + jc;
+            lds_sync();
+            dropped = 0.0;
+            int nk = 0, nd = 0;
+            for (int o = 0; o < ncj; ++o) {
+              const bool ko = L.colr[o] < chi_new;
+              if (!ko) dropped += L.colv[o];
+              if (o < jc) {
+                nk += ko ? 1 : 0;
+                nd += ko ? 0 : 1;
+              }
+            }
+            keep = colok && rk < chi_new;
+            pos = keep ? nk : chi_new + nd;
+          }
+          if (stot > 0.0) truncw = fmax(truncw, dropped / stot);
+          if (!isfinite(stot)) status |= GMPS_ST_NAN;
+          if (wrec && real) {
+            // keep J with its columns in the kept order for the next iteration
+            if (colok) {
+#pragma unroll
+              for (int e = 0; e < RU; ++e) {
+                const int row = jh + PJ * e;
+                if (row < ncj) {
+                  wrec[2 + 2 * (row * KJ + pos)] = uu[e].re;
+                  wrec[3 + 2 * (row * KJ + pos)] = uu[e].im;
+                }
+              }
+            }
+            if (tl == 0) wrec[0] = (double)ncj;
+          }
+          const double rs = keep ? rsqrt_acc(sg) : 0.0;  // 1/sigma
+          cd wv[RJ];     // this slot's row of V^H
+          cx<S> vs[RJ];  // ... as stored
+#pragma unroll
+          for (int e = 0; e < RJ; ++e) {
+            wv[e] = rs * conj(a[e]);
+            vs[e] = store_cast<S>(wv[e], rs_state, sr);
+          }
+          if (keep && real) {
+#pragma unroll
+            for (int e = 0; e < RJ; ++e) {
+              const int row = jh + PJ * e;
+              if (row < c) {
+                const int s = row >= chn ? 1 : 0;
+                const int jp = row - s * chn;
+                slot[pos * 2 * D + s * D + jp] = vs[e];
+                if (es) es[pos * 2 * D + s * D + jp] = wv[e];
+              }
+            }
+          }
+          cd yv[RU];  // this slot's column of the carry J Sigma
+#pragma unroll
+          for (int e = 0; e < RU; ++e) yv[e] = (sg * rs) * uu[e];
+          if (kMixed && !es) {
+            // the Jacobi exchange buffers are free: the kept rows and Z go there
+            comp_store_rows<PJ, RJ, RU, CM>(wv, vs, yv, keep, pos, jh, c, ri, chi_new,
+                                            reinterpret_cast<cd*>(&L.u.s.XA[0][0][0]),
+                                            reinterpret_cast<cd*>(&L.u.s.XU[0][0][0]), L.u.s.Y);
+            f64 += 8.0 * ((double)chi_new * chi_new * c + (double)chi_new * chi_new * ri);
+          }
+          if (keep) {
+#pragma unroll
+            for (int e = 0; e < RU; ++e) {
+              const int row = jh + PJ * e;
+              if (row < ri) L.u.s.Y[row][pos] = yv[e];
+            }
+          }
+          if (tl == 0) L.bond[i] = chi_new;
+          lds_sync();
+        }
+        // ---------------------------------------------- site 0 (holds the norm)
+        team_sync_global();
+        {
+          const int rn = L.rdim[1], chn = L.bond[1];
+          cx<S>* slot = arena;
+          cd acc = {0.0, 0.0};
+          const bool act = tl < 2 * chn;
+          const int s = tl >= chn ? 1 : 0;
+          const int jj = tl - s * chn;
+          if (act) {
+#pragma unroll
+            for (int b = 0; b < KQ; ++b)
+              if (b < rn) acc = cfma(acc, edges[s * D + b], L.u.s.Y[b][jj]);
+          }
+          f64 += 8.0 * 2.0 * rn * chn;
+          double nn = 0.0;
+          if constexpr (TW <= 64) {
+            nn = tsum<TW>(act ? norm2(acc) : 0.0);
+          } else {
+            L.colv[tl] = act ? norm2(acc) : 0.0;
+            lds_sync();
+            for (int o = 0; o < 2 * chn; ++o) nn += L.colv[o];
+          }
+          if (!isfinite(nn) || !(nn > 0.0)) status |= GMPS_ST_NAN;
+          const double nr = sqrt(nn);
+          if (renorm) drift = fmax(drift, fabs(nr - 1.0));
+          // site 0 now holds the norm: to its edge slot in FP64, to its site slot as stored
+          const cd outd = (renorm ? 1.0 / nr : 1.0) * acc;
+          const cx<S> out = store_cast<S>(outd, rs_state, sr);
+          lds_sync();
+          if (real && act) {
+            slot[s * D + jj] = out;
+            edges[s * D + jj] = outd;
+          }
+          if (tl == 0) L.bond[0] = 1;
+          team_sync_global();
+        }
+      }
+    }
+    {
+      // the gates after the last n-controlled Z act on the stored sites in place (a unitary on
+      // the physical index keeps the chain right-canonical and its norm)
+      walk();
+      for (int i = 0; i < n; ++i) {
+        const int chl = L.bond[i], chr = L.bond[i + 1];
+        cx<S>* slot = arena + (int64_t)i * SLOT;
+        cd* es = eslot(i);
+        const double u00 = C.U[i][0], u01 = C.U[i][1], u10 = C.U[i][2], u11 = C.U[i][3];
+        for (int e = tl; e < CM * CM; e += TW) {
+          const int a = e / CM, b = e % CM;
+          if (real && a < chl && b < chr) {
+            const cd a0 = es ? es[a * 2 * D + b] : up(slot[a * 2 * D + b]);
+            const cd a1 = es ? es[a * 2 * D + D + b] : up(slot[a * 2 * D + D + b]);
+            const cd b0 = {u00 * a0.re + u01 * a1.re, u00 * a0.im + u01 * a1.im};
+            const cd b1 = {u10 * a0.re + u11 * a1.re, u10 * a0.im + u11 * a1.im};
+            slot[a * 2 * D + b] = store_cast<S>(b0, rs_state, sr);
+            slot[a * 2 * D + D + b] = store_cast<S>(b1, rs_state, sr);
+            if (es) {
+              es[a * 2 * D + b] = b0;
+              es[a * 2 * D + D + b] = b1;
+            }
+          }
+        }
+      }
+      team_sync_global();
+    }
+  }
+
+  // ------------------------------------------------------------------ write back
+  if (real) {
+    for (int l = tl; l < kBondStride; l += TW) P.bonds[(int64_t)me * kBondStride + l] = L.bond[l];
+    if (tl == 0) {
+      I->k_done += k;
+      I->flops64 += f64;
+      I->flops32 += f32;
+      I->drift = fmax(I->drift, drift);
+      I->trunc_w = fmax(I->trunc_w, truncw);
+      if (drift > 1e-3) status |= GMPS_ST_DRIFT;
+      if (truncw > 1e-8) status |= GMPS_ST_TRUNC;
+      I->status |= status;
+    }
+  }
+  team_sync_global();
+}
+
 // Persistent kernel of one team class W: a workgroup takes bundles from the class's queue
 // until it is empty.
 template <class S, int W>
@@ -1348,6 +1912,21 @@ __global__ __launch_bounds__(kWide[W].TW < 64 ? 64 : kWide[W].TW) void grover_te
     lds_sync();
     if ((int)bi >= P.queue->nbundles) break;
     run_team<S, kWide[W].CM, kWide[W].TW>(P, P.bundles + bi, lds);
+  }
+}
+
+// Persistent kernel of the gate-level circuits (the Common method) for team class W.
+template <class S, int W>
+__global__ __launch_bounds__(kWide[W].TW < 64 ? 64 : kWide[W].TW) void grover_team_circ_kernel(IterParams P) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ unsigned int next_bundle;
+  for (;;) {
+    if (threadIdx.x == 0) next_bundle = atomicAdd(&P.queue->next, 1u);
+    lds_sync();
+    const unsigned int bi = next_bundle;
+    lds_sync();
+    if ((int)bi >= P.queue->nbundles) break;
+    run_team_circ<S, kWide[W].CM, kWide[W].TW>(P, P.bundles + bi, lds);
   }
 }
 
@@ -2013,6 +2592,25 @@ hipError_t occupancy_team_pc_w(bool mixed, size_t lds, int* blocks_per_cu);
     constexpr int nt = kWide[W].TW < 64 ? 64 : kWide[W].TW;                                           \
     if (mixed) return hipErrorInvalidValue;                                                          \
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_team_pc_kernel<double, W>, nt, lds); \
+  }
+
+// The gate-level circuit kernels of a class (FP64 storage, classes with bond caps up to 17).
+template <int W>
+hipError_t launch_team_circ_w(const IterParams& P, int grid, size_t lds, hipStream_t st);
+template <int W>
+hipError_t occupancy_team_circ_w(size_t lds, int* blocks_per_cu);
+
+#define GMPS_TEAM_CIRC_CLASS(W)                                                                      \
+  template <>                                                                                        \
+  hipError_t launch_team_circ_w<W>(const IterParams& P, int grid, size_t lds, hipStream_t st) {      \
+    constexpr int nt = kWide[W].TW < 64 ? 64 : kWide[W].TW;                                           \
+    grover_team_circ_kernel<double, W><<<grid, nt, lds, st>>>(P);                                     \
+    return hipGetLastError();                                                                        \
+  }                                                                                                  \
+  template <>                                                                                        \
+  hipError_t occupancy_team_circ_w<W>(size_t lds, int* blocks_per_cu) {                             \
+    constexpr int nt = kWide[W].TW < 64 ? 64 : kWide[W].TW;                                           \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, grover_team_circ_kernel<double, W>, nt, lds); \
   }
 
 }  // namespace gmps

@@ -18,6 +18,10 @@ static_assert(sizeof(TeamLds<double, 5, 64>) + sizeof(PcLds<5>) <= 160 * 1024 - 
 static_assert(sizeof(TeamLds<double, 8, 64>) + sizeof(PcLds<8>) <= 160 * 1024 - 64, "LDS");
 static_assert(sizeof(TeamLds<double, 17, 192>) + sizeof(PcLds<17>) <= 160 * 1024 - 64, "LDS");
 static_assert(sizeof(TeamLds<double, 32, 256>) <= 160 * 1024 - 64, "LDS");
+// with the gate-level circuit block (classes up to bond 17)
+static_assert((sizeof(TeamLds<double, 2, 16>) + sizeof(CircLds)) * 4 <= 160 * 1024 - 64, "LDS");
+static_assert((sizeof(TeamLds<double, 3, 32>) + sizeof(CircLds)) * 2 <= 160 * 1024 - 64, "LDS");
+static_assert(sizeof(TeamLds<double, 17, 192>) + sizeof(CircLds) <= 160 * 1024 - 64, "LDS");
 
 // the pipelined kernel, with the pre-contracted reflections' overlap block
 static_assert((sizeof(PipeLds<double, 2>) + sizeof(PipeOv<2>)) * 4 <= 160 * 1024 - 256, "LDS");
@@ -62,6 +66,44 @@ size_t team_lds_bytes(bool mixed, bool pc, bool pipe, int cls) {
     case 5: return class_lds<5>(mixed, pc);
   }
   return 0;
+}
+
+// Gate-level circuits: the sequential team kernel with the circuit block after the team blocks
+// (FP64, classes with bond caps up to 17).
+size_t team_circ_lds_bytes(int cls) {
+  const int w = cls - kWideBase;
+  size_t teams = 0, base = 0;
+  switch (w) {
+    case 0: base = class_lds<0>(false, false); teams = TeamShape<kWide[0].CM, kWide[0].TW>::TEAMS; break;
+    case 1: base = class_lds<1>(false, false); teams = TeamShape<kWide[1].CM, kWide[1].TW>::TEAMS; break;
+    case 2: base = class_lds<2>(false, false); teams = TeamShape<kWide[2].CM, kWide[2].TW>::TEAMS; break;
+    case 3: base = class_lds<3>(false, false); teams = TeamShape<kWide[3].CM, kWide[3].TW>::TEAMS; break;
+    case 4: base = class_lds<4>(false, false); teams = TeamShape<kWide[4].CM, kWide[4].TW>::TEAMS; break;
+    default: return 0;
+  }
+  return base + teams * sizeof(CircLds);
+}
+
+hipError_t launch_team_circ(int cls, const IterParams& P, int grid, size_t lds, hipStream_t st) {
+  switch (cls - kWideBase) {
+    case 0: return launch_team_circ_w<0>(P, grid, lds, st);
+    case 1: return launch_team_circ_w<1>(P, grid, lds, st);
+    case 2: return launch_team_circ_w<2>(P, grid, lds, st);
+    case 3: return launch_team_circ_w<3>(P, grid, lds, st);
+    case 4: return launch_team_circ_w<4>(P, grid, lds, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t team_circ_occupancy(int cls, size_t lds, int* blocks_per_cu) {
+  switch (cls - kWideBase) {
+    case 0: return occupancy_team_circ_w<0>(lds, blocks_per_cu);
+    case 1: return occupancy_team_circ_w<1>(lds, blocks_per_cu);
+    case 2: return occupancy_team_circ_w<2>(lds, blocks_per_cu);
+    case 3: return occupancy_team_circ_w<3>(lds, blocks_per_cu);
+    case 4: return occupancy_team_circ_w<4>(lds, blocks_per_cu);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_team(bool mixed, bool pc, bool pipe, int cls, const IterParams& P, int grid, size_t lds,

@@ -4,4 +4,5 @@
 namespace gmps {
 GMPS_TEAM_CLASS(4)
 GMPS_TEAM_PC_CLASS(4)
+GMPS_TEAM_CIRC_CLASS(4)
 }  // namespace gmps

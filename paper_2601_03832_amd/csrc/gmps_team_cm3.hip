@@ -4,4 +4,5 @@
 namespace gmps {
 GMPS_TEAM_CLASS(1)
 GMPS_TEAM_PC_CLASS(1)
+GMPS_TEAM_CIRC_CLASS(1)
 }  // namespace gmps

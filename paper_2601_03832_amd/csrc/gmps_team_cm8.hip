@@ -4,4 +4,5 @@
 namespace gmps {
 GMPS_TEAM_CLASS(3)
 GMPS_TEAM_PC_CLASS(3)
+GMPS_TEAM_CIRC_CLASS(3)
 }  // namespace gmps

@@ -30,6 +30,7 @@ KERNELS = {"auto": 0, "group": 1, "team": 2}
 
 EXPORTED = ("gmps_workspace_bytes", "gmps_create", "mps_init_uniform", "grover_iterate", "grover_iterate_sample", "marked_prob",
             "sample_shots", "sample_shots_noalloc", "gmps_amplitudes", "gmps_overlap_uniform", "gmps_autotune", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
+            "gmps_circuit_bytes", "gmps_circuit_build", "grover_circuit_run",
             "gmps_strerror", "gsv_workspace_bytes", "gsv_create", "gsv_init_uniform", "gsv_iterate",
             "gsv_marked_prob", "gsv_amplitudes", "gsv_last_iterate_ms", "gsv_destroy")
 
@@ -97,6 +98,12 @@ def load(path: Optional[str] = None):
     lib.gmps_overlap_uniform.argtypes = [P, i32, ctypes.POINTER(dbl)]
     lib.gmps_autotune.restype = ctypes.c_int
     lib.gmps_autotune.argtypes = [P, ctypes.POINTER(i64), i32, i32, ctypes.c_char_p, ctypes.POINTER(GmpsPlan)]
+    lib.gmps_circuit_bytes.restype = ctypes.c_size_t
+    lib.gmps_circuit_bytes.argtypes = [ctypes.POINTER(GmpsInstance), i32, ctypes.POINTER(u64), ctypes.POINTER(i64), i32]
+    lib.gmps_circuit_build.restype = ctypes.c_int
+    lib.gmps_circuit_build.argtypes = [P, ctypes.POINTER(i64), i32, P, ctypes.c_size_t]
+    lib.grover_circuit_run.restype = ctypes.c_int
+    lib.grover_circuit_run.argtypes = [P]
     lib.gmps_diagnostics.restype = ctypes.c_int
     lib.gmps_diagnostics.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(i32),
                                      ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl)]
@@ -256,6 +263,24 @@ class Batch:
                                                    _ptr(sh, ctypes.c_int64), len(sh), ctypes.c_uint64(seed),
                                                    _ptr(hits, ctypes.c_int64)), "grover_iterate_sample")
         return hits
+
+    # -- the Common method: the k-layer gate-level circuit --------------------------------
+    def build_circuit(self, k) -> int:
+        """gmps_circuit_build: every instance's k-layer gate list (Fig. 1(A) gates), in a device
+        buffer owned by this object; returns its size in bytes."""
+        import torch
+        ks = np.ascontiguousarray(np.atleast_1d(np.asarray(k, dtype=np.int64)))
+        nbytes = int(self.lib.gmps_circuit_bytes(self._arr, self.B, _ptr(self._marked, ctypes.c_uint64),
+                                                 _ptr(ks, ctypes.c_int64), len(ks)))
+        self.circuit_buffer = torch.empty(max(nbytes, 4), dtype=torch.uint8, device=self.workspace.device)
+        self._check(self.lib.gmps_circuit_build(self.handle, _ptr(ks, ctypes.c_int64), len(ks),
+                                                ctypes.c_void_p(self.circuit_buffer.data_ptr()), nbytes),
+                    "gmps_circuit_build")
+        return nbytes
+
+    def run_circuit(self):
+        """grover_circuit_run: simulate the built circuits gate by gate."""
+        self._check(self.lib.grover_circuit_run(self.handle), "grover_circuit_run")
 
     def marked_prob(self, allow_numeric: bool = False) -> np.ndarray:
         out = np.zeros(self.B, dtype=np.float64)

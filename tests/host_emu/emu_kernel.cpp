@@ -4,8 +4,9 @@
 // gives it, and the result goes to stdout for comparison with the oracle. Built with
 // sanitizers by tests/test_host_emulation.py:
 //   EMU_KIND 0: run_team (bond-2 MPO reflections), 1: run_team_pc (pre-contracted),
-//            2: run_pipe (pipelined sweeps), 3: run_pipe pre-contracted; EMU_W: team class;
-//            EMU_S: double or float.
+//            2: run_pipe (pipelined sweeps), 3: run_pipe pre-contracted, 4: run_team_circ (the
+//            k-layer gate-level circuit of Fig. 1(A), built here as gmps_circuit_build does);
+//            EMU_W: team class; EMU_S: double or float.
 // stdin: n M cap k, then the M marked indices. stdout: status drift trunc_w, the bonds, then
 // the 2^n amplitudes (re im per line).
 #include "hip/hip_runtime.h"
@@ -65,7 +66,7 @@ constexpr int W = EMU_W;
 constexpr int KIND = EMU_KIND;
 constexpr int CM = kWide[W].CM, TW = kWide[W].TW;
 constexpr bool kMixed = sizeof(S) == sizeof(float);
-constexpr int NT = KIND >= 2 ? 128 : (TW < 64 ? 64 : TW);
+constexpr int NT = (KIND == 2 || KIND == 3) ? 128 : (TW < 64 ? 64 : TW);
 
 // templates on every parameter, so that the branches for the other kernels are not instantiated
 template <int K, class SS, int C, int T>
@@ -74,6 +75,8 @@ size_t lds_size() {
     return sizeof(PipeLds<SS, C>) * (64 / T);
   else if constexpr (K == 3)
     return (sizeof(PipeLds<SS, C>) + sizeof(PipeOv<C>)) * (64 / T);
+  else if constexpr (K == 4)
+    return (sizeof(TeamLds<SS, C, T>) + sizeof(CircLds)) * TeamShape<C, T>::TEAMS;
   else
     return (sizeof(TeamLds<SS, C, T>) + (K == 1 ? sizeof(PcLds<C>) : 0)) * TeamShape<C, T>::TEAMS;
 }
@@ -85,8 +88,10 @@ void body(const IterParams& P, const Bundle* bundle, char* lds) {
     run_team_pc<SS, C, T>(P, bundle, lds);
   else if constexpr (K == 2)
     run_pipe<SS, C, T>(P, bundle, lds);
-  else
+  else if constexpr (K == 3)
     run_pipe<SS, C, T, true>(P, bundle, lds);
+  else
+    run_team_circ<SS, C, T>(P, bundle, lds);
 }
 
 int main() {
@@ -152,6 +157,29 @@ int main() {
   P.stoch_round = 0;
   P.warm = nullptr;
   P.edge = edge;
+  // the gate-level circuit: k layers of Fig. 1(A), in its own heap block
+  std::vector<uint32_t> gl;
+  if (KIND == 4) {
+    for (long long l = 0; l < k; ++l) {
+      for (int t = 0; t < M; ++t) {
+        for (int q = 0; q < n; ++q)
+          if (!((marked_h[t] >> (n - 1 - q)) & 1ull)) gl.push_back(gate_word(kGateX, q));
+        gl.push_back(gate_word(kGateMCZ, 0));
+        for (int q = 0; q < n; ++q)
+          if (!((marked_h[t] >> (n - 1 - q)) & 1ull)) gl.push_back(gate_word(kGateX, q));
+      }
+      for (int q = 0; q < n; ++q) gl.push_back(gate_word(kGateH, q));
+      for (int q = 0; q < n; ++q) gl.push_back(gate_word(kGateX, q));
+      gl.push_back(gate_word(kGateMCZ, 0));
+      for (int q = 0; q < n; ++q) gl.push_back(gate_word(kGateX, q));
+      for (int q = 0; q < n; ++q) gl.push_back(gate_word(kGateH, q));
+    }
+  }
+  uint32_t* circ = static_cast<uint32_t*>(std::malloc(sizeof(uint32_t) * (gl.size() + 1)));
+  if (!gl.empty()) std::memcpy(circ, gl.data(), sizeof(uint32_t) * gl.size());
+  P.circuit = KIND == 4 ? circ : nullptr;
+  inst->circ_off = 0;
+  inst->circ_len = (int64_t)gl.size();
 
   const size_t lds_bytes = lds_size<KIND, S, CM, TW>();
   const size_t alloc = (lds_bytes + 15) / 16 * 16;
@@ -201,5 +229,6 @@ int main() {
   std::free(bundle);
   std::free(queue);
   std::free(lds);
+  std::free(circ);
   return 0;
 }

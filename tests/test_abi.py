@@ -200,3 +200,25 @@ def test_fp32_workspace_and_rejections_before_touching_a_device(lib):
     rc = lib.gmps_create(ctypes.byref(h), narrow, 1, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                          gmps.GMPS_FP32, ctypes.byref(opt), ctypes.c_void_p(256), 1 << 30, None)
     assert rc == gmps.GMPS_E_UNSUPPORTED
+
+
+def test_circuit_bytes_counts_the_gates_of_fig1a(lib):
+    """gmps_circuit_bytes: one 32-bit word per gate of k layers of Fig. 1(A). Per marked x: an X
+    on each qubit where x has a 0, before and after the n-controlled Z; then the diffusion as
+    H and X on every qubit, the n-controlled Z, X and H on every qubit."""
+    insts = [inputs.Instance(6, [0b101101, 0], 3, 4), inputs.Instance(9, [511], 2, 2), inputs.Instance(4, [5], 0, 2)]
+    arr, marked = gmps.pack_instances(insts)
+    ks = np.array([i.k for i in insts], dtype=np.int64)
+    got = lib.gmps_circuit_bytes(arr, len(insts), marked.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                 ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(ks))
+    # (6, {101101, 000000}): zeros 2 and 6 -> (2*2+1) + (2*6+1) + (4*6+1) = 43 gates per layer
+    # (9, {111111111}): 1 + 37 = 38; (4, {0101}): 5 + 17 = 22, but k = 0 -> no gates
+    assert got == 4 * (3 * 43 + 2 * 38 + 0)
+    one = np.array([1], dtype=np.int64)
+    assert lib.gmps_circuit_bytes(arr, len(insts), marked.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                  one.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1) == 4 * (43 + 38 + 22)
+    bad = np.array([-1], dtype=np.int64)
+    assert lib.gmps_circuit_bytes(arr, len(insts), marked.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                  bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1) == 0
+    assert lib.grover_circuit_run(None) == gmps.GMPS_E_ARG
+    assert lib.gmps_circuit_build(None, one.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1, None, 0) == gmps.GMPS_E_ARG

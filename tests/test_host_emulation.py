@@ -1,6 +1,6 @@
 """The iterate kernel bodies run on the CPU under sanitizers, lanes emulated as threads.
 
-tests/host_emu/emu_kernel.cpp calls run_team, run_team_pc or run_pipe (the device code of
+tests/host_emu/emu_kernel.cpp calls run_team, run_team_pc, run_team_circ or run_pipe (the device code of
 csrc/, unchanged except that `extern __shared__` reads `extern` in the copies compiled here)
 with every lane of the workgroup an OS thread. Cross-lane operations (DPP, swizzle,
 bpermute, ballot) and barriers synchronise exactly the lanes they involve, and a lane group
@@ -10,7 +10,7 @@ the LDS block or a global buffer, and ThreadSanitizer sees any LDS or global acc
 lanes that no barrier or wave fence orders. Each run is then compared with the statevector
 oracle.
 
-Cases: the pipelined pre-contracted reflections (one reflection for the whole oracle, and one
+Cases: the gate-level circuit kernel of the Common method; the pipelined pre-contracted reflections (one reflection for the whole oracle, and one
 per marked index where M exceeds the class bond); the bond-32 class (CM = 32, 256-thread teams, four waves) with bond-2 MPO and with
 pre-contracted reflections at n = 12, M = 24 and 31 (the cases whose GPU build of the
 pre-contracted variant failed; the variant stays off on the GPU); the pipelined two-wave
@@ -123,3 +123,16 @@ def test_pipelined_precontracted(tree, w, n, M, k, sanitize):
     assert st == 0 and kd == k
     assert max(bonds) > 1
     assert np.max(np.abs(amps - sv.grover_sv(n, W, k))) < 1e-12
+
+
+@pytest.mark.parametrize("w,n,M,k,sanitize", [(0, 9, 1, 3, "thread"), (2, 10, 4, 2, "address,undefined")],
+                         ids=["bond2-tsan", "bond5-asan"])
+def test_gate_level_circuit(tree, w, n, M, k, sanitize):
+    """run_team_circ (the Common method) on the k-layer gate list of Fig. 1(A), against the
+    gate-level statevector oracle."""
+    W = inputs.draw_marked(n, M, inputs.SplitMix64(60 + n))
+    exe = build(tree, 4, w, "double", sanitize)
+    st, drift, kd, bonds, amps = run(exe, n, M, M + 1, k, W)
+    assert st == 0 and kd == k
+    assert max(bonds) > 1
+    assert np.max(np.abs(amps - sv.grover_gates(n, W, k))) < 1e-12
