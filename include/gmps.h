@@ -293,6 +293,19 @@ typedef struct {
 int gmps_autotune(gmps_batch* b, const int64_t* k, int32_t k_len, int32_t probe_iters, const char* cache_path,
                   gmps_plan* out);
 
+/* Checkpoint and resume: the whole state of a batch (every chain as stored, its bonds, edge
+ * slots and warm-start records, and each instance's iteration count and diagnostics) copied to
+ * or from host memory the caller owns, so that a long run can stop and continue in another
+ * process (the warm-start records are held only when the batch's kernels read them).
+ * gmps_state_bytes: the size of a checkpoint of this batch (0 for NULL). export: host
+ * buffer of at least that many bytes; synchronises. import: a checkpoint exported from a batch
+ * created with the same instances, precision and kernel (anything else is refused with
+ * GMPS_E_ARG before any device memory is written); synchronises. Errors: GMPS_E_ARG,
+ * GMPS_E_HIP. */
+size_t gmps_state_bytes(const gmps_batch* b);
+int gmps_state_export(gmps_batch* b, void* host, size_t bytes);
+int gmps_state_import(gmps_batch* b, const void* host, size_t bytes);
+
 /* Per-instance diagnostics; any pointer may be NULL. Synchronises.
  *  norm_drift:   host [B], largest |norm - 1| seen before a renormalisation
  *  trunc_weight: host [B], largest fraction of weight dropped by one truncation

@@ -1111,6 +1111,100 @@ int gmps_overlap_uniform(gmps_batch* b, int32_t inst, double* out_reim) {
   return GMPS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Checkpoint format: a header, one record per instance (its shape, to check the handle that
+// imports it, and its counters), the bond table, then the device regions that hold the chains
+// as they are: warm-start records and edge slots, and the site arena.
+constexpr uint64_t kStateMagic = 0x31657461745347ull;  // a fixed tag
+struct StateHeader {
+  uint64_t magic;
+  int32_t B, mixed, fp32, path;
+  uint64_t regions_bytes, arena_bytes;
+};
+struct StateInst {
+  int32_t n, M, cap, cls;
+  int64_t k_done;
+  int32_t status, pad;
+  double drift, trunc_w, flops64, flops32;
+};
+
+// the device regions beyond the arena that a checkpoint holds: the edge slots, and the
+// warm-start records in front of them when the batch's kernels read them
+size_t region_start(const gmps_batch* b) { return b->params.warm ? b->lay.warm : b->lay.edge; }
+
+size_t state_bytes(const gmps_batch* b) {
+  return sizeof(StateHeader) + sizeof(StateInst) * (size_t)b->B + sizeof(int32_t) * kBondStride * (size_t)b->B +
+         (b->lay.stage - region_start(b)) + (b->lay.total - b->lay.arena);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gmps_state_bytes(const gmps_batch* b) { return b ? state_bytes(b) : 0; }
+
+int gmps_state_export(gmps_batch* b, void* host, size_t bytes) {
+  if (!b || !host || bytes < state_bytes(b)) return GMPS_E_ARG;
+  char* p = static_cast<char*>(host);
+  StateHeader h{kStateMagic, b->B, b->mixed ? 1 : 0, b->fp32 ? 1 : 0, b->path, b->lay.stage - region_start(b),
+                b->lay.total - b->lay.arena};
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  std::vector<InstDev> d(b->B);
+  GMPS_HIP(hipMemcpyAsync(d.data(), b->params.inst, sizeof(InstDev) * b->B, hipMemcpyDeviceToHost, b->stream));
+  GMPS_HIP(hipStreamSynchronize(b->stream));
+  for (int i = 0; i < b->B; ++i) {
+    StateInst r{d[i].n, d[i].M, d[i].cap, d[i].cls, d[i].k_done, d[i].status, 0, d[i].drift, d[i].trunc_w,
+                d[i].flops64, d[i].flops32};
+    std::memcpy(p, &r, sizeof(r));
+    p += sizeof(r);
+  }
+  GMPS_HIP(hipMemcpy(p, b->params.bonds, sizeof(int32_t) * kBondStride * b->B, hipMemcpyDeviceToHost));
+  p += sizeof(int32_t) * kBondStride * b->B;
+  GMPS_HIP(hipMemcpy(p, b->ws + region_start(b), h.regions_bytes, hipMemcpyDeviceToHost));
+  p += h.regions_bytes;
+  GMPS_HIP(hipMemcpy(p, b->ws + b->lay.arena, h.arena_bytes, hipMemcpyDeviceToHost));
+  return GMPS_OK;
+}
+
+int gmps_state_import(gmps_batch* b, const void* host, size_t bytes) {
+  if (!b || !host || bytes < sizeof(StateHeader)) return GMPS_E_ARG;
+  const char* p = static_cast<const char*>(host);
+  StateHeader h;
+  std::memcpy(&h, p, sizeof(h));
+  p += sizeof(h);
+  // a checkpoint of this batch only: same instances, precision, kernel and layout
+  if (h.magic != kStateMagic || h.B != b->B || h.mixed != (b->mixed ? 1 : 0) || h.fp32 != (b->fp32 ? 1 : 0) ||
+      h.path != b->path || h.regions_bytes != b->lay.stage - region_start(b) || h.arena_bytes != b->lay.total - b->lay.arena ||
+      bytes < state_bytes(b))
+    return GMPS_E_ARG;
+  std::vector<InstDev> d = b->inst_h;
+  for (int i = 0; i < b->B; ++i) {
+    StateInst r;
+    std::memcpy(&r, p, sizeof(r));
+    p += sizeof(r);
+    if (r.n != d[i].n || r.M != d[i].M || r.cap != d[i].cap || r.cls != d[i].cls) return GMPS_E_ARG;
+    d[i].k_done = r.k_done;
+    d[i].status = r.status;
+    d[i].drift = r.drift;
+    d[i].trunc_w = r.trunc_w;
+    d[i].flops64 = r.flops64;
+    d[i].flops32 = r.flops32;
+  }
+  GMPS_HIP(hipStreamSynchronize(b->stream));
+  GMPS_HIP(hipMemcpy(b->params.inst, d.data(), sizeof(InstDev) * b->B, hipMemcpyHostToDevice));
+  GMPS_HIP(hipMemcpy(b->params.bonds, p, sizeof(int32_t) * kBondStride * b->B, hipMemcpyHostToDevice));
+  p += sizeof(int32_t) * kBondStride * b->B;
+  GMPS_HIP(hipMemcpy(b->ws + region_start(b), p, h.regions_bytes, hipMemcpyHostToDevice));
+  p += h.regions_bytes;
+  GMPS_HIP(hipMemcpy(b->ws + b->lay.arena, p, h.arena_bytes, hipMemcpyHostToDevice));
+  for (int i = 0; i < b->B; ++i) b->k_done_h[i] = d[i].k_done;
+  return GMPS_OK;
+}
+
 int gmps_diagnostics(gmps_batch* b, double* norm_drift, double* trunc_weight, int32_t* bond_dims, int32_t* status,
                      int64_t* k_done, double* flops) {
   if (!b) return GMPS_E_ARG;

@@ -31,6 +31,7 @@ KERNELS = {"auto": 0, "group": 1, "team": 2}
 EXPORTED = ("gmps_workspace_bytes", "gmps_create", "mps_init_uniform", "grover_iterate", "grover_iterate_sample", "marked_prob",
             "sample_shots", "sample_shots_noalloc", "gmps_amplitudes", "gmps_overlap_uniform", "gmps_autotune", "gmps_diagnostics", "gmps_last_iterate_ms", "gmps_destroy",
             "gmps_circuit_bytes", "gmps_circuit_build", "grover_circuit_run",
+            "gmps_state_bytes", "gmps_state_export", "gmps_state_import",
             "gmps_strerror", "gsv_workspace_bytes", "gsv_create", "gsv_init_uniform", "gsv_iterate",
             "gsv_marked_prob", "gsv_amplitudes", "gsv_last_iterate_ms", "gsv_destroy")
 
@@ -104,6 +105,12 @@ def load(path: Optional[str] = None):
     lib.gmps_circuit_build.argtypes = [P, ctypes.POINTER(i64), i32, P, ctypes.c_size_t]
     lib.grover_circuit_run.restype = ctypes.c_int
     lib.grover_circuit_run.argtypes = [P]
+    lib.gmps_state_bytes.restype = ctypes.c_size_t
+    lib.gmps_state_bytes.argtypes = [P]
+    lib.gmps_state_export.restype = ctypes.c_int
+    lib.gmps_state_export.argtypes = [P, P, ctypes.c_size_t]
+    lib.gmps_state_import.restype = ctypes.c_int
+    lib.gmps_state_import.argtypes = [P, P, ctypes.c_size_t]
     lib.gmps_diagnostics.restype = ctypes.c_int
     lib.gmps_diagnostics.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(i32),
                                      ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl)]
@@ -281,6 +288,20 @@ class Batch:
     def run_circuit(self):
         """grover_circuit_run: simulate the built circuits gate by gate."""
         self._check(self.lib.grover_circuit_run(self.handle), "grover_circuit_run")
+
+    # -- checkpoint and resume ---------------------------------------------------------------
+    def export_state(self) -> np.ndarray:
+        """gmps_state_export: the batch's whole state as a host byte array."""
+        buf = np.zeros(int(self.lib.gmps_state_bytes(self.handle)), dtype=np.uint8)
+        self._check(self.lib.gmps_state_export(self.handle, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes),
+                    "gmps_state_export")
+        return buf
+
+    def import_state(self, buf: np.ndarray):
+        """gmps_state_import: continue from a checkpoint of a batch over the same instances."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self.lib.gmps_state_import(self.handle, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes),
+                    "gmps_state_import")
 
     def marked_prob(self, allow_numeric: bool = False) -> np.ndarray:
         out = np.zeros(self.B, dtype=np.float64)
