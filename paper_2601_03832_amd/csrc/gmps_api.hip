@@ -542,13 +542,15 @@ int gmps_circuit_build(gmps_batch* b, const int64_t* k, int32_t k_len, void* dev
   }
   if (need > 0 && (!dev_gates || bytes < need || (reinterpret_cast<uintptr_t>(dev_gates) % 4) != 0))
     return GMPS_E_WORKSPACE;
-  // each instance's k layers, built on the host and copied in turn
+  // each instance's k layers, built on the host and copied in turn; the handle takes the new
+  // offsets only once every copy has succeeded
   uint32_t* dst = static_cast<uint32_t*>(dev_gates);
   int64_t off = 0;
   std::vector<uint32_t> g;
-  b->circ_k.assign(b->B, 0);
+  std::vector<InstDev> inst = b->inst_h;
+  std::vector<int64_t> ks(b->B, 0);
   for (int i = 0; i < b->B; ++i) {
-    InstDev& d = b->inst_h[i];
+    InstDev& d = inst[i];
     const int64_t ki = k[k_len == 1 ? 0 : i];
     const uint64_t* x = mk.data() + d.marked_off;
     g.clear();
@@ -558,10 +560,12 @@ int gmps_circuit_build(gmps_batch* b, const int64_t* k, int32_t k_len, void* dev
     d.circ_off = off;
     d.circ_len = (int64_t)g.size();
     off += (int64_t)g.size();
-    b->circ_k[i] = ki;
+    ks[i] = ki;
   }
-  GMPS_HIP(hipMemcpyAsync(b->params.inst, b->inst_h.data(), sizeof(InstDev) * b->B, hipMemcpyHostToDevice, b->stream));
+  GMPS_HIP(hipMemcpyAsync(b->params.inst, inst.data(), sizeof(InstDev) * b->B, hipMemcpyHostToDevice, b->stream));
   GMPS_HIP(hipStreamSynchronize(b->stream));
+  b->inst_h = inst;
+  b->circ_k = ks;
   b->circuit = static_cast<const uint32_t*>(dev_gates);
   return GMPS_OK;
 }
