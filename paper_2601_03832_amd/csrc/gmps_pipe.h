@@ -1,5 +1,5 @@
 // Pipelined reflections for the team classes whose teams fit one wave (bond caps 2, 3, 5
-// and 8), per-projector MPO form (Section III-B).
+// and 8), in the per-projector MPO form (Section III-B) and in the pre-contracted form.
 //
 // Each reflection is a canonicalisation sweep (MPO applied, rank-stopped QR) followed by a
 // truncation sweep (one-sided Jacobi SVD) in the opposite direction. Reflections alternate
@@ -207,8 +207,9 @@ __device__ void run_pipe(const IterParams& P, const Bundle* bdp, char* lds_base)
   };
 
   // ---------------------------------------------------------------- canonicalisation step
-  // Reflection jr (0..M, M = diffusion) at site i, direction lr; the site tensor comes from
-  // the handover buffer h (null: from its arena slot). rdo: the ranks it produces.
+  // Reflection jr (0..nrefl-1, the last one the diffusion) at site i, direction lr; the site
+  // tensor comes from the handover buffer h (null: from its arena slot). rdo: the ranks it
+  // produces.
   auto canon_step = [&](int jr, bool ident, bool lr, int i, const cd (*h)[2][CM], int32_t* rdo) {
     const bool diff = (jr == nrefl - 1);
     const int xb = (diff || ident) ? 0 : (int)((Wm[jr] >> (n - 1 - i)) & 1ull);
