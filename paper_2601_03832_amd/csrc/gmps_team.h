@@ -168,6 +168,23 @@ __device__ __forceinline__ void jacobi_rotation(cd g, double g2, double ni, doub
   *tg = g2 * rr;
 }
 
+// One term of the Gram element of a Jacobi pair, accumulated as conj(own) other. Both slots of
+// the pair must arrive at the same gamma = conj(x) y (x the lower column) to the bit: the pair's
+// 2x2 is unitary only if its two halves come from one rotation, and for near-equal norms and
+// small |gamma| a rounding difference between the halves turns the phase by eps |x||y| / |gamma|.
+// The real part is symmetric in the operands even when contracted to FMAs; the imaginary part
+// is formed from two rounded products, so that swapping the operands negates it exactly. The
+// upper slot's sum is then exactly conj(gamma), and it flips the sign of the imaginary part.
+__device__ __forceinline__ void gram_acc(cd& g, cd own, cd oth) {
+  g.re = fma(own.re, oth.re, fma(own.im, oth.im, g.re));
+  double t;
+  {
+#pragma clang fp contract(off)
+    t = own.re * oth.im - own.im * oth.re;
+  }
+  g.im = g.im + t;
+}
+
 // ----------------------------------------------------------------------- prefetched loads
 // The site tensor A_i of the QR sweep, loaded one site ahead as (a, b) pairs with both
 // physical values, so that staging can write both blocks of the bond-2 MPO applied to it:
@@ -491,8 +508,8 @@ __device__ __forceinline__ int team_qr_lds(cd (&x)[RQ], cd (&q)[RQ], int qc, int
 // (a[e] = row part + PJ*e of this slot's column), accumulating the unitary (u[e], same
 // layout). Same rotation, skip and stopping rules as the lane-group kernel's jacobi_fixed;
 // in round r of the round-robin schedule every slot meets its partner: the pair exchanges
-// columns through LDS, both members form the same inner product with the same operand
-// order, and each applies its half of the rotation to its own column. Returns the sweeps.
+// columns through LDS, both members form the same inner product to the bit (gram_acc), and
+// each applies its half of the rotation to its own column. Returns the sweeps.
 template <int PJ, int RJ, int RU, int KJ, int NBUF>
 __device__ __forceinline__ int team_jacobi_lds(cd (&a)[RJ], cd (&u)[RU], int jc, int jh, int ncj, double tol2,
                                            double skip2, int max_sweeps, cd (*XA)[KJ][PJ * RJ],
@@ -539,8 +556,9 @@ __device__ __forceinline__ int team_jacobi_lds(cd (&a)[RJ], cd (&u)[RU], int jc,
         const bool lo = jc < pt;
         cd g = {0.0, 0.0};
 #pragma unroll
-        for (int e = 0; e < RJ; ++e) g = g + (lo ? cmulc(a[e], b[e]) : cmulc(b[e], a[e]));
+        for (int e = 0; e < RJ; ++e) gram_acc(g, a[e], b[e]);
         g = gsum<PJ>(g);
+        if (!lo) g.im = -g.im;
         const double ni = lo ? nrm : nb, nj = lo ? nb : nrm;
         const double g2 = norm2(g);
         const double ab = ni * nj;
@@ -755,8 +773,9 @@ __device__ __forceinline__ int team_jacobi_wave(cd (&a)[RJ], cd (&u)[RU], int ba
         const bool lo = jc < pt;
         cd g = {0.0, 0.0};
 #pragma unroll
-        for (int e = 0; e < RJ; ++e) g = g + (lo ? cmulc(a[e], b[e]) : cmulc(b[e], a[e]));
+        for (int e = 0; e < RJ; ++e) gram_acc(g, a[e], b[e]);
         g = gsum<PJ>(g);
+        if (!lo) g.im = -g.im;
         const double ni = lo ? nrm : nb, nj = lo ? nb : nrm;
         const double g2 = norm2(g);
         const double ab = ni * nj;
