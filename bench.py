@@ -143,6 +143,8 @@ def plan_name(kernel: str, plan) -> str:
     """The launch plan in words: the kernel choice and, when autotuned, the plan it picked."""
     if not plan:
         return kernel + " (library default plan)"
+    if plan.get("chosen") == "library default plan":
+        return kernel + " (library default plan: faster than the autotuner's pick in a full-size step)"
     return "%s: %s sweeps, %s reflections, %s workgroups per CU (autotuned)" % (
         "team" if kernel == "auto" else kernel, "pipelined" if plan["pipeline"] else "sequential",
         "pre-contracted" if plan["precontract"] else "bond-2 MPO",
@@ -600,6 +602,8 @@ def main():
                     help="also time the whole workload on the lane-group kernel in FP32, mixed and FP64")
     ap.add_argument("--no-tune", action="store_true", help="run the library's default launch plan")
     ap.add_argument("--tune-probe", type=int, default=64, help="iterations of the longest chain per autotuner probe")
+    ap.add_argument("--no-tune-check", dest="tune_check", action="store_false",
+                    help="keep the autotuner's pick without a full-size step against the library default plan")
     ap.add_argument("--tune-cache", default=None, help="plan cache file of the autotuner (default: none)")
     ap.add_argument("--kernel", default="auto", choices=sorted(["auto", "group", "team"]),
                     help="iterate kernel: lane-group, team, or the library's choice")
@@ -639,12 +643,34 @@ def main():
         log("calibration copy of %d bytes done" % args.copy_bytes)
     batch = gmps.Batch(w.instances, w.precision, kernel=args.kernel)
     plan = None
+    untimed = 0
     if not args.no_tune:
         # the launch plan: timed probes of every plan that keeps the batch's parity (untimed here)
         plan = batch.autotune(ks, probe_iters=args.tune_probe, cache_path=args.tune_cache)
         log("autotuned plan: %s" % plan)
+        default = {"pipeline": True, "precontract": False, "waves_per_cu": 0}
+        if args.tune_check and any(plan[key] != v for key, v in default.items()):
+            # The probes scale every chain down by k_max / probe_iters, and there plans within a
+            # few percent of each other rank by noise. One full-size step under the probes' pick
+            # and one under the library's default plan (a second batch) decide between the two;
+            # the step taken on the batch that is kept counts as one of its warm-up steps.
+            alt = gmps.Batch(w.instances, w.precision, kernel=args.kernel)
+            run_step(batch, ks, shots, w.shot_seed)
+            t_pick = batch.last_iterate_ms()
+            run_step(alt, ks, shots, w.shot_seed)
+            t_def = alt.last_iterate_ms()
+            check = {"probe_pick_ms": t_pick, "library_default_ms": t_def}
+            if t_def < t_pick:
+                batch.close()
+                batch = alt
+                plan = dict(plan, full_size_check=check, chosen="library default plan")
+            else:
+                alt.close()
+                plan = dict(plan, full_size_check=check, chosen="probe pick")
+            untimed = 1
+            log("full-size check: %s" % plan)
 
-    for s in range(args.warmup):
+    for s in range(max(0, args.warmup - untimed)):
         run_step(batch, ks, shots, w.shot_seed)
         log("warmup step %d done" % s)
     torch.cuda.synchronize()

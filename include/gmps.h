@@ -283,8 +283,8 @@ typedef struct {
  * caps up to 17 only; on GMPS_MIXED their rotation angle drifts), and 0, 1 or 2 workgroups per CU and class
  * kernel -- and switches the batch to the fastest. k: host, k_len == 1 or B, the iteration
  * counts of the run to be tuned for; each probe scales them so that the longest chain runs
- * probe_iters (>= 1) iterations, and is timed by HIP events after an untimed run that captures
- * its graph. cache_path (may be NULL): a text file of "key pipeline precontract waves_per_cu ms"
+ * probe_iters (>= 1) iterations; a plan's time is the minimum of three runs timed by HIP
+ * events, after an untimed run that captures its graph. cache_path (may be NULL): a text file of "key pipeline precontract waves_per_cu ms"
  * lines; the key hashes the device, the library's device sources, the precision, the kernel
  * and the batch's (class, n, M, probe k) multiset. A cached plan is applied without timing; a
  * timed one is appended (file errors are ignored). Leaves every instance at |s>, as
