@@ -651,15 +651,19 @@ def main():
         default = {"pipeline": True, "precontract": False, "waves_per_cu": 0}
         if args.tune_check and any(plan[key] != v for key, v in default.items()):
             # The probes scale every chain down by k_max / probe_iters, and there plans within a
-            # few percent of each other rank by noise. One full-size step under the probes' pick
-            # and one under the library's default plan (a second batch) decide between the two;
-            # the step taken on the batch that is kept counts as one of its warm-up steps.
+            # few percent of each other rank by noise. Full-size steps under the probes' pick and
+            # under the library's default plan (a second batch) decide between the two: the
+            # second step of each, since a first step also captures the graph and starts cold.
+            # The steps taken on the batch that is kept count as its warm-up steps.
             alt = gmps.Batch(w.instances, w.precision, kernel=args.kernel)
-            run_step(batch, ks, shots, w.shot_seed)
-            t_pick = batch.last_iterate_ms()
-            run_step(alt, ks, shots, w.shot_seed)
-            t_def = alt.last_iterate_ms()
+            t_pick, t_def = [], []
+            for _ in range(2):
+                run_step(batch, ks, shots, w.shot_seed)
+                t_pick.append(batch.last_iterate_ms())
+                run_step(alt, ks, shots, w.shot_seed)
+                t_def.append(alt.last_iterate_ms())
             check = {"probe_pick_ms": t_pick, "library_default_ms": t_def}
+            t_pick, t_def = t_pick[-1], t_def[-1]
             if t_def < t_pick:
                 batch.close()
                 batch = alt
@@ -667,7 +671,7 @@ def main():
             else:
                 alt.close()
                 plan = dict(plan, full_size_check=check, chosen="probe pick")
-            untimed = 1
+            untimed = 2
             log("full-size check: %s" % plan)
 
     for s in range(max(0, args.warmup - untimed)):
