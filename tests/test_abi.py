@@ -222,3 +222,25 @@ def test_circuit_bytes_counts_the_gates_of_fig1a(lib):
                                   bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1) == 0
     assert lib.grover_circuit_run(None) == gmps.GMPS_E_ARG
     assert lib.gmps_circuit_build(None, one.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1, None, 0) == gmps.GMPS_E_ARG
+
+
+def test_jacobi_probe_library_shapes():
+    """The Jacobi test probe (tests/gpu_probes) loads without a GPU and reports each team class's
+    Jacobi shape as the team layout defines it: KJ = chi_max + 1 rounded up to even columns, and
+    2 chi_max rows (the bond-2 MPO's largest bond) held as PJ lanes per column times RJ rows per
+    lane, PJ the largest of 16, 8, 4, 2 with KJ * PJ <= the team width."""
+    path = os.path.join(ROOT, "tests", "gpu_probes", "libjacobi_probe.so")
+    if not os.path.exists(path):
+        pytest.fail("the Jacobi probe is not built; run __graft_entry__.build()")
+    probe = ctypes.CDLL(path)
+    probe.gmps_probe_jacobi_shape.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    assert hasattr(probe, "gmps_probe_team_jacobi")
+    for w, (cap, tw) in enumerate([(2, 16), (3, 32), (5, 64), (8, 64), (17, 192), (32, 256)]):
+        kj, rows = ctypes.c_int(), ctypes.c_int()
+        assert probe.gmps_probe_jacobi_shape(w, ctypes.byref(kj), ctypes.byref(rows)) == 0
+        want_kj = (cap + 2) // 2 * 2
+        pj = next(p for p in (16, 8, 4, 2) if want_kj * p <= tw)
+        rj = -(-2 * cap // pj)
+        assert (kj.value, rows.value) == (want_kj, min(2 * cap, pj * rj)), (w, kj.value, rows.value)
+    kj, rows = ctypes.c_int(), ctypes.c_int()
+    assert probe.gmps_probe_jacobi_shape(6, ctypes.byref(kj), ctypes.byref(rows)) == -1
